@@ -1,0 +1,153 @@
+"""Pins of the oracle's CGP time step (Sect. 2.2, Eqs. 21-26; Sect. 3.1)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.cgp import OracleCGP, build
+from workloads import get_workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _run(w, steps, chi=None):
+    w = w if chi is None else w.with_(chi=chi)
+    ora = build(w)
+    st = ora.initial_state(*w.initial_fields(ora.fine_xy))
+    xyd = ora.fine_xy[ora.dir]
+    for s in range(steps):
+        st = ora.step(st, w.dirichlet_values(xyd, (s + 1) * w.dt)).state
+    return ora, st
+
+
+def _tg(n, k, dt, nu, **kw):
+    return get_workload("tg33_k1").with_(coarse_n=n, levels=k, dt=dt, nu=nu, **kw)
+
+
+@pytest.mark.parametrize("mode", ["galerkin", "inject"])
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_linear_divergence_free_velocity_passes_through(mode, k):
+    """A linear divergence-free U~ has zero discrete divergence under both
+    restriction readings, so Phi = 0 and U^{n+1} = U~ (up to rounding)."""
+    w = _tg(5, k, 1e-3, 0.01, restrict=mode)
+    ora = build(w)
+    x, y = ora.fine_xy[:, 0], ora.fine_xy[:, 1]
+    Ut = np.stack([0.3 + 0.8 * x - 1.1 * y, -0.2 + 0.6 * x - 0.8 * y])
+    b = ora.restrict_rhs(Ut)
+    assert np.abs(b).max() < 1e-11
+    phi_c, info = ora.poisson(b, np.zeros(ora.nc))
+    assert np.abs(phi_c).max() < 1e-10
+    U, _ = ora.velocity_correction(Ut, ora.hier.prolong(phi_c))
+    np.testing.assert_allclose(U, Ut, rtol=0, atol=1e-12)
+
+
+def test_restriction_readings_coincide_without_coarsening():
+    w = _tg(9, 0, 1e-3, 0.01)
+    a = build(w)
+    b = build(w.with_(restrict="inject"))
+    rng = np.random.default_rng(0)
+    Ut = rng.normal(size=(2, a.nf))
+    np.testing.assert_allclose(a.restrict_rhs(Ut), b.restrict_rhs(Ut), rtol=0, atol=1e-12)
+
+
+def test_galerkin_restriction_is_coarse_test_functions():
+    """(Dbar U)_I = int psi_I^c div u_f: for U the prolongation of a coarse
+    field the Galerkin and the injection readings agree (P^T D_f P = D_c)."""
+    w = _tg(5, 2, 1e-3, 0.01)
+    a = build(w)
+    b = build(w.with_(restrict="inject"))
+    rng = np.random.default_rng(1)
+    Uc = rng.normal(size=(2, a.nc))
+    Uf = np.stack([a.hier.prolong(Uc[0]), a.hier.prolong(Uc[1])])
+    np.testing.assert_allclose(a.restrict_rhs(Uf), b.restrict_rhs(Uf), atol=1e-9)
+
+
+def test_schemes_differ_only_by_rotational_correction():
+    w = _tg(9, 1, 1e-3, 0.05)
+    o0, o1 = build(w.with_(chi=0)), build(w.with_(chi=1))
+    st = o0.initial_state(*w.initial_fields(o0.fine_xy))
+    uD = w.dirichlet_values(o0.fine_xy[o0.dir], w.dt)
+    r0, r1 = o0.step(st, uD), o1.step(st, uD)
+    np.testing.assert_array_equal(r0.state.U, r1.state.U)
+    dp = r1.state.P - r0.state.P
+    # dp solves M dp = -nu D U~
+    res = o1.F.M @ dp + o1.nu * o1.F.div(r1.U_tilde)
+    assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(o1.nu * o1.F.div(r1.U_tilde))
+
+
+def test_pure_neumann_normalisation():
+    w = _tg(9, 1, 1e-3, 0.01)
+    ora = build(w)
+    st = ora.initial_state(*w.initial_fields(ora.fine_xy))
+    r = ora.step(st, w.dirichlet_values(ora.fine_xy[ora.dir], w.dt))
+    assert abs(r.b_c.sum()) < 1e-10 * np.abs(r.b_c).sum()
+    assert abs(ora.C.lumped @ r.phi_c) < 1e-14 * np.abs(r.phi_c).max()
+    # the true FP64 residual of the coarse solve respects the tolerance
+    res = ora.Kc_ff @ r.phi_c[ora.phi_free] - r.b_c[ora.phi_free]
+    assert np.linalg.norm(res) <= 2 * w.pcg_tol * np.linalg.norm(r.b_c)
+
+
+def test_taylor_green_33_k1_accuracy():
+    """The 33x33 / 17x17 Taylor-Green workload (nu=0.01, dt=1e-3, 100 steps,
+    standard form) stays within 0.5 % relative L2 of the exact velocity."""
+    w = get_workload("tg33_k1")
+    ora, st = _run(w, w.steps)
+    ex = w.exact(ora.fine_xy, w.steps * w.dt)
+    rel_u = ora.l2(st.U - ex[0]) / ora.l2(ex[0])
+    rel_p = ora.l2(ora.mean_free(st.P) - ora.mean_free(ex[1])) / ora.l2(ex[1])
+    assert rel_u < 5e-3
+    assert rel_p < 3e-2
+
+
+def test_spatial_convergence_rate():
+    """Velocity error at fixed time, dt small: second order in h."""
+    errs = []
+    for n in (5, 9, 17):
+        w = _tg(n, 1, 2.5e-4, 0.1, pcg_tol=1e-12)
+        ora, st = _run(w, 40)
+        errs.append(ora.l2(st.U - w.exact(ora.fine_xy, 40 * w.dt)[0]))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), rates
+
+
+def test_temporal_convergence_rate_standard_form():
+    """Velocity difference to a dt/32 run on the same mesh: BDF2 second order
+    (standard form; average rate over two halvings)."""
+    T = 0.2
+    w = _tg(9, 1, T / 256, 0.1, pcg_tol=1e-12, chi=0)
+    ora, ref = _run(w, 256)
+    errs = []
+    for m in (8, 16, 32):
+        _, st = _run(w.with_(dt=T / m), m)
+        errs.append(ora.l2(st.U - ref.U))
+    rate = np.log2(errs[0] / errs[2]) / 2
+    assert rate > 1.7, errs
+
+
+def test_table1_velocity_error_independent_of_coarsening():
+    """Sect. 3.1, Table 1 (qualitative): in the rotational form the velocity
+    error at t does not depend on the coarsening level."""
+    g = json.load(open(os.path.join(GOLDEN, "table1_k_invariance.json")))
+    printed = g["printed_rotational_L2"]
+    spread = (max(printed.values()) - min(printed.values())) / min(printed.values())
+    assert spread < 2e-5
+    errs = []
+    for k, n in ((0, 33), (1, 17), (2, 9)):
+        w = _tg(n, k, 0.00125, 0.1, chi=1)
+        ora, st = _run(w, 80)
+        ex = w.exact(ora.fine_xy, 80 * w.dt)
+        errs.append(ora.l2(st.U - ex[0]) / ora.l2(ex[0]))
+    assert max(errs) / min(errs) < 1.05, errs
+
+
+def test_injection_reading_loses_k_invariance():
+    """The literal injection reading of Eq. 22 does not reproduce Table 1: its
+    velocity error at k=1 is many times the k=0 error."""
+    e = []
+    for k, n, mode in ((0, 33, "galerkin"), (1, 17, "inject")):
+        w = _tg(n, k, 0.00125, 0.1, chi=0, restrict=mode)
+        ora, st = _run(w, 20)
+        ex = w.exact(ora.fine_xy, 20 * w.dt)
+        e.append(ora.l2(st.U - ex[0]) / ora.l2(ex[0]))
+    assert e[1] > 5 * e[0], e

@@ -1,0 +1,131 @@
+"""The synthetic workloads: coarse mesh, coarsening level, time step, viscosity,
+scheme and solver settings, initial fields and boundary data.
+
+Each entry describes a problem only; how it is discretised and solved is up to
+the caller (the HIP library or the CPU oracle).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+from functools import lru_cache
+
+import numpy as np
+
+from . import flows
+from .meshes import unit_square, channel_cylinder
+
+FP64 = 0
+MIXED = 1
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    mesh: str                  # 'square' | 'channel'
+    coarse_n: int              # nodes per side of the coarse square mesh (square only)
+    levels: int                # coarsening level k: fine = k uniform 4:1 refinements
+    dt: float
+    nu: float
+    steps: int
+    chi: int                   # 0 standard, 1 rotational
+    flow: str                  # 'taylor_green' | 'cavity' | 'channel'
+    precision: int = FP64
+    pcg_tol: float = 1e-8
+    inner_tol: float = 1e-5
+    mom_tol: float = 1e-12
+    mass_tol: float = 1e-12
+    max_iter: int = 20000
+    restrict: str = "galerkin"     # 'galerkin' | 'inject'
+    lid_speed: float = 1.0
+    channel_h: float = 0.0082
+    seed: int = 0
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    # ---- input data -----------------------------------------------------
+    def coarse_mesh(self) -> dict:
+        if self.mesh == "square":
+            return _square(self.coarse_n)
+        if self.mesh == "channel":
+            return _channel(self.channel_h, self.seed)
+        raise ValueError(self.mesh)
+
+    def initial_fields(self, xy: np.ndarray):
+        """(U^{-1}, U^0, P^0): Taylor-Green takes the exact fields at t=-dt and
+        t=0; the impulsively started flows start from rest."""
+        n = xy.shape[0]
+        if self.flow == "taylor_green":
+            um, vm, _ = flows.taylor_green(xy[:, 0], xy[:, 1], -self.dt, self.nu)
+            u0, v0, p0 = flows.taylor_green(xy[:, 0], xy[:, 1], 0.0, self.nu)
+            return np.stack([um, vm]), np.stack([u0, v0]), p0
+        z = np.zeros(n)
+        return np.stack([z, z]), np.stack([z, z]), z.copy()
+
+    def dirichlet_values(self, xy_dir: np.ndarray, t: float) -> np.ndarray:
+        """[2, n_dir] velocity at the Dirichlet nodes at time t."""
+        x, y = xy_dir[:, 0], xy_dir[:, 1]
+        if self.flow == "taylor_green":
+            u, v, _ = flows.taylor_green(x, y, t, self.nu)
+        elif self.flow == "cavity":
+            u, v = flows.cavity_lid(x, y, self.lid_speed)
+        elif self.flow == "channel":
+            u, v = flows.channel_inflow(x, y)
+        else:
+            raise ValueError(self.flow)
+        return np.stack([u, v])
+
+    def exact(self, xy: np.ndarray, t: float):
+        if self.flow != "taylor_green":
+            return None
+        u, v, p = flows.taylor_green(xy[:, 0], xy[:, 1], t, self.nu)
+        return np.stack([u, v]), p
+
+
+@lru_cache(maxsize=8)
+def _square_cached(n):
+    return unit_square(n)
+
+
+def _square(n):
+    m = _square_cached(n)
+    return {k: v.copy() for k, v in m.items()}
+
+
+@lru_cache(maxsize=2)
+def _channel_cached(h, seed):
+    return channel_cylinder(h, seed)
+
+
+def _channel(h, seed):
+    m = _channel_cached(h, seed)
+    return {k: v.copy() for k, v in m.items()}
+
+
+# The five workloads.  Sizes follow the problem statement: unit-square meshes
+# with n x n nodes, a channel with a cylinder, levels of 4:1 coarsening.
+WORKLOADS = {
+    # 33x33 fine / 17x17 pressure mesh, Taylor-Green, standard scheme, FP64 PCG 1e-10
+    "tg33_k1": Workload("tg33_k1", "square", 17, 1, 1e-3, 0.01, 100, 0, "taylor_green",
+                        FP64, pcg_tol=1e-10),
+    # 257x257 fine lid-driven cavity Re=100, coarsening 0..3, both schemes
+    **{f"cavity257_k{k}_chi{c}_{p}": Workload(
+        f"cavity257_k{k}_chi{c}_{p}", "square", (256 >> k) + 1, k, 5e-3, 0.01, 500, c,
+        "cavity", FP64 if p == "fp64" else MIXED, pcg_tol=1e-8)
+       for k in range(4) for c in (0, 1) for p in ("fp64", "mixed")},
+    # channel minus cylinder, 2 levels, Re=20, rotational, mixed
+    "channel_k2": Workload("channel_k2", "channel", 0, 2, 1e-3, 1e-3, 1000, 1, "channel",
+                           MIXED, pcg_tol=1e-8),
+    # learned-guess cavity (config-2 mesh, k=1 pressure mesh 129x129)
+    "cavity257_k1_learned": Workload("cavity257_k1_learned", "square", 129, 1, 5e-3, 0.01,
+                                     1000, 0, "cavity", MIXED, pcg_tol=1e-8),
+    # 2049x2049 Taylor-Green, 3 levels (257x257 pressure mesh), rotational
+    "tg2049_k3_fp64": Workload("tg2049_k3_fp64", "square", 257, 3, 2e-4, 0.005, 200, 1,
+                               "taylor_green", FP64, pcg_tol=1e-8),
+    "tg2049_k3_mixed": Workload("tg2049_k3_mixed", "square", 257, 3, 2e-4, 0.005, 200, 1,
+                                "taylor_green", MIXED, pcg_tol=1e-8),
+}
+
+
+def get_workload(name: str) -> Workload:
+    return WORKLOADS[name]

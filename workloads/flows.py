@@ -1,0 +1,48 @@
+"""Closed-form flow data for the synthetic workloads (input data only).
+
+Initial fields and Dirichlet boundary values, evaluated at whatever node
+coordinates the caller supplies.  Nothing here discretises or solves anything.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .meshes import CHANNEL_H
+
+
+def taylor_green(x, y, t, nu):
+    """Taylor-Green vortex (Sect. 3.1, Eqs. 28-30) with 1/Re replaced by nu.
+
+    An exact Navier-Stokes solution with zero forcing on [0,1]^2:
+      u = -cos(2 pi x) sin(2 pi y) exp(-8 pi^2 nu t)
+      v =  sin(2 pi x) cos(2 pi y) exp(-8 pi^2 nu t)
+      p = -(cos(4 pi x) + cos(4 pi y)) / 4 * exp(-16 pi^2 nu t)
+    """
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    e = np.exp(-8.0 * np.pi ** 2 * nu * t)
+    u = -np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y) * e
+    v = np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) * e
+    p = -0.25 * (np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) * e * e
+    return u, v, p
+
+
+def cavity_lid(x, y, speed=1.0):
+    """Lid-driven cavity wall velocity: (speed, 0) on the lid y = 1 strictly
+    between the two top corners, zero on every other wall node (the corners
+    belong to the side walls)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    lid = (y == 1.0) & (x > 0.0) & (x < 1.0)
+    return np.where(lid, speed, 0.0), np.zeros_like(x)
+
+
+def channel_inflow(x, y, u_max=0.3):
+    """Parabolic inflow 4 U_m y (H - y) / H^2 at x = 0; zero on walls and the
+    cylinder (every other Dirichlet node)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    H = CHANNEL_H
+    inflow = x == 0.0
+    u = np.where(inflow, 4.0 * u_max * y * (H - y) / (H * H), 0.0)
+    return u, np.zeros_like(x)
