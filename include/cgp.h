@@ -1,0 +1,252 @@
+/*
+ * cgp.h -- C ABI of the MI355X (gfx950) coarse-grid incremental
+ * pressure-projection (CGP) library.
+ *
+ * The method (Kashefi, "A coarse-grid incremental pressure-projection method
+ * for accelerating low Reynolds number incompressible flow simulations"):
+ * each time step solves a fine-mesh momentum problem for the intermediate
+ * velocity (Eq. 21), restricts it to a mesh coarsened by k levels of uniform
+ * 4:1 refinement (Eq. 22), solves the pressure-increment Poisson problem there
+ * (Eq. 23), prolongs the increment back (Eq. 24) and corrects velocity and
+ * pressure on the fine mesh (Eqs. 25-26, Sect. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: CGP_OK (0), CGP_NOT_CONVERGED (1, outputs written and stats
+ *    valid) or a negative error code.  cgp_last_error() returns a
+ *    thread-local message describing the last failure.  Nothing throws across
+ *    the ABI and nothing calls exit().
+ *  - Host pointers are read during the call only.  Device pointers are owned
+ *    by the caller and must stay valid until the work queued on `stream` has
+ *    finished.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Device work is queued on `stream`; a call returns before it
+ *    finishes unless stated otherwise.
+ *  - The library allocates no device memory.  cgp_query() reports the size of
+ *    the device workspace the caller provides to cgp_assemble(); it also
+ *    allocates one small pinned host buffer (hipHostMalloc) per context for
+ *    convergence flags.
+ *  - Node numbering of the fine mesh (the only numbering seen at the ABI):
+ *    the coarse nodes keep their numbers 0..N_c-1; each refinement appends the
+ *    midpoint of every edge in first-encounter order over (triangle, local
+ *    edge (0,1), (1,2), (2,0)); triangle (a,b,c) with midpoints m_ab, m_bc,
+ *    m_ca has children (a,m_ab,m_ca), (m_ab,b,m_bc), (m_ca,m_bc,c),
+ *    (m_ab,m_bc,m_ca) in that order.  A boundary edge (p,q) splits into
+ *    (p,m), (m,q) with the parent's tag.
+ *  - Field layout: velocities are structure-of-arrays float64 [2][N_f]
+ *    (u then v); scalars float64 [N]; all arrays dense and contiguous.
+ */
+#ifndef CGP_H
+#define CGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CGP_OK 0
+#define CGP_NOT_CONVERGED 1
+#define CGP_ERR_INVALID (-1)   /* bad argument, size or pointer            */
+#define CGP_ERR_MESH (-2)      /* clockwise/degenerate/non-conforming mesh */
+#define CGP_ERR_HIP (-3)       /* a HIP runtime call failed                */
+#define CGP_ERR_NAN (-4)       /* a solver produced NaN/Inf                */
+#define CGP_ERR_WORKSPACE (-5) /* workspace missing, too small, misaligned */
+
+/* boundary-edge tags (problem statement, Sect. 2.1, Eqs. 3-4) */
+#define CGP_DIRICHLET 1 /* velocity prescribed (Eq. 10); grad(phi).n = 0 (Eq. 13) */
+#define CGP_NATURAL 2   /* traction-free outflow (Eq. 11 with t = 0); phi = 0 (Eq. 14) */
+
+/* coarse-solve precision */
+#define CGP_FP64 0  /* Jacobi-PCG in FP64 throughout */
+#define CGP_MIXED 1 /* FP64 iterative refinement around FP32-inner Jacobi-PCG */
+
+/* reading of the coarse divergence in Eq. 23 (Sect. 2.2) */
+#define CGP_RESTRICT_GALERKIN 0 /* coarse shape functions against the fine velocity */
+#define CGP_RESTRICT_INJECT 1   /* inject U~ at the coarse nodes (Eq. 22), then D_c */
+
+/* Coarse (Poisson) mesh; the fine mesh is `levels` uniform refinements of it.
+ * Host arrays.  Triangles counter-clockwise with positive area; every
+ * boundary edge must be an edge of exactly one triangle. */
+typedef struct cgp_mesh {
+  int32_t n_nodes;
+  int32_t n_tris;
+  int32_t n_bedges;
+  const double* xy;     /* [2*n_nodes] interleaved (x, y)        */
+  const int32_t* tri;   /* [3*n_tris]                            */
+  const int32_t* bedge; /* [2*n_bedges] node pairs               */
+  const int32_t* btag;  /* [n_bedges] CGP_DIRICHLET / CGP_NATURAL */
+} cgp_mesh;
+
+/* The problem statement of Sect. 2.1 (dimensionless; nu = 1/Re) plus the
+ * coarsening level k of Sect. 2.2 and the solver settings. */
+typedef struct cgp_problem {
+  cgp_mesh coarse;
+  int32_t levels;        /* k in 0..3                                        */
+  int32_t chi;           /* 0 standard, 1 rotational form (Eq. 16)           */
+  int32_t precision;     /* CGP_FP64 or CGP_MIXED                            */
+  int32_t restrict_mode; /* CGP_RESTRICT_GALERKIN or CGP_RESTRICT_INJECT     */
+  double dt;             /* time step                                        */
+  double nu;             /* kinematic viscosity 1/Re                         */
+  double pcg_tol;        /* coarse solve: ||b - K phi||_2 <= pcg_tol ||b||_2  */
+  double inner_tol;      /* mixed: FP32 inner solve relative tolerance       */
+  double mom_tol;        /* momentum BiCGSTAB relative tolerance             */
+  double mass_tol;       /* mass-matrix PCG relative tolerance               */
+  int32_t max_iter;      /* coarse PCG iteration cap (all inner iterations)  */
+  int32_t mom_max_iter;  /* momentum iteration cap                           */
+  int32_t mass_max_iter; /* mass-solve iteration cap                         */
+  int32_t max_outer;     /* mixed: refinement-step cap                       */
+} cgp_problem;
+
+typedef struct cgp_sizes {
+  int64_t n_fine, n_coarse;          /* nodes                                 */
+  int64_t n_fine_tris, n_coarse_tris;
+  int64_t nnz_fine, nnz_coarse;      /* CSR nonzeros of the P1 node graphs    */
+  int64_t n_dirichlet;               /* fine velocity-Dirichlet nodes         */
+  int64_t n_natural_coarse;          /* coarse phi = 0 nodes                  */
+  size_t workspace_bytes;            /* device workspace for cgp_assemble     */
+} cgp_sizes;
+
+/* One linear solve.  iters counts Krylov iterations (inner iterations summed
+ * on the mixed path); rel_res is the FP64 relative residual the stopping test
+ * last saw (recursive for plain PCG/BiCGSTAB, true for mixed refinement). */
+typedef struct cgp_solve_stats {
+  int32_t iters;
+  int32_t outer_iters;
+  int32_t converged;
+  int32_t pad_;
+  double rel_res;
+} cgp_solve_stats;
+
+typedef struct cgp_step_stats {
+  cgp_solve_stats momentum[2]; /* u, v                          */
+  cgp_solve_stats poisson;     /* coarse pressure increment     */
+  cgp_solve_stats mass[2];     /* velocity correction u, v      */
+  cgp_solve_stats prot;        /* rotational pressure mass solve */
+} cgp_step_stats;
+
+/* Time-stepping state, device pointers owned by the caller.  The step writes
+ * U^{n+1} into the buffer that held U^{n-1} and swaps the two pointers, so on
+ * return u_prev = U^n and u = U^{n+1}; p is updated in place; phi_hist[0..3]
+ * are rotated so that phi_hist[0] holds the new coarse increment. */
+typedef struct cgp_state {
+  double* u_prev;      /* [2][N_f] U^{n-1}                          */
+  double* u;           /* [2][N_f] U^n                              */
+  double* p;           /* [N_f]    P^n                              */
+  double* phi_hist[4]; /* [N_c] each: coarse increments, newest first */
+  int64_t step;
+} cgp_state;
+
+typedef struct cgp_ctx cgp_ctx;
+
+/* Host-only set-up: validates the coarse mesh (index range, positive area,
+ * conformity, boundary edges), refines it `levels` times and builds every
+ * index structure (CSR graphs, edge-side lists, prolongation codes).  No
+ * device memory is touched.  *out receives a context to be released with
+ * cgp_destroy().  Errors: CGP_ERR_INVALID, CGP_ERR_MESH. */
+int cgp_create(const cgp_problem* problem, cgp_ctx** out);
+
+/* Sizes of the refined problem and of the device workspace. */
+int cgp_query(const cgp_ctx* ctx, cgp_sizes* out);
+
+/* Fine-mesh node coordinates, host [2*N_f] interleaved (x, y). */
+int cgp_fine_nodes(const cgp_ctx* ctx, double* xy_host);
+
+/* Sorted fine velocity-Dirichlet nodes, host [n_dirichlet].  Every node on a
+ * CGP_DIRICHLET edge is one (walls win at junctions with the outflow).  The
+ * u_dir arrays passed below follow this order. */
+int cgp_dirichlet_nodes(const cgp_ctx* ctx, int32_t* nodes_host);
+
+/* Device set-up: carves `workspace` (device, >= workspace_bytes, 256-byte
+ * aligned, caller-owned for the life of the context), uploads the index
+ * structures and assembles the constant operators (fine mass matrix; coarse
+ * stiffness, divergence, lumped masses; Jacobi diagonals).  Synchronises
+ * `stream` before returning.  Errors: CGP_ERR_WORKSPACE, CGP_ERR_HIP. */
+int cgp_assemble(cgp_ctx* ctx, void* workspace, size_t bytes, void* stream);
+
+/* Step 1 (Eq. 21): solves
+ *   (3/2 M + dt N(w) + dt nu K) U~ = -dt G P + dt M F + 2 M U - 1/2 M U_prev,
+ *   w = 2 U - U_prev, with U~ = u_dir at the Dirichlet nodes (Eq. 10),
+ * by right-Jacobi-preconditioned BiCGSTAB from U~ = w, stopping when
+ * ||r|| <= mom_tol ||rhs||.  u_prev, u, u_tilde: device [2][N_f]; p device
+ * [N_f]; u_dir device [2][n_dirichlet]; f device [2][N_f] or NULL (no
+ * forcing).  u_tilde must not alias the inputs.  stats may be NULL; when
+ * given, the call synchronises `stream` to fill it. */
+int cgp_momentum(cgp_ctx* ctx, const double* u_prev, const double* u, const double* p,
+                 const double* u_dir, const double* f, double* u_tilde,
+                 cgp_solve_stats stats[2], void* stream);
+
+/* Steps 2-3, right-hand side (Eqs. 22-23): b_c = -(3/(2 dt)) Dbar U~ with
+ * Dbar the coarse divergence selected by restrict_mode; zero at the coarse
+ * phi = 0 nodes (Eq. 14); projected onto zero mean when no boundary is
+ * natural.  u_tilde device [2][N_f], b_c device [N_c]. */
+int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream);
+
+/* Step 3 (Eq. 23): solves K_c phi_c = b_c (K_c the coarse stiffness matrix,
+ * phi = 0 rows/columns removed) from the guess held in phi_c, stopping when
+ * ||b - K phi|| <= pcg_tol ||b||; CGP_FP64 runs Jacobi-PCG in FP64,
+ * CGP_MIXED runs FP64 refinement steps around FP32 Jacobi-PCG (FP64 dot
+ * products and norms).  For the pure Neumann problem the lumped-mass mean of
+ * the result is removed.  b_c, phi_c device [N_c].  stats may be NULL (then
+ * no synchronisation beyond the convergence polling). */
+int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stats* stats,
+                  void* stream);
+
+/* Step 4 (Eq. 24): phi_f = P phi_c, linear interpolation applied k times
+ * (each fine node is the coarse P1 function evaluated there).  phi_c device
+ * [N_c], phi_f device [N_f]. */
+int cgp_prolong(cgp_ctx* ctx, const double* phi_c, double* phi_f, void* stream);
+
+/* Steps 5-6 (Eqs. 25-26, Sect. 2.3): M dU = -(2/3) dt G phi_f on the
+ * non-Dirichlet nodes (consistent mass, Jacobi-PCG to mass_tol), u_out =
+ * u_tilde + dU; p_out = p_in + phi_f for chi = 0; for chi = 1 additionally
+ * M dp = -nu D u_tilde and p_out = p_in + phi_f + dp.  p_out may alias p_in.
+ * u_tilde, u_out device [2][N_f]; phi_f, p_in, p_out device [N_f].  stats:
+ * [3] (u, v, rotational) or NULL. */
+int cgp_correct(cgp_ctx* ctx, const double* u_tilde, const double* phi_f, const double* p_in,
+                double* u_out, double* p_out, cgp_solve_stats stats[3], void* stream);
+
+/* One whole CGP step (Eqs. 21-26): momentum, restriction, coarse solve from
+ * the guess phi_hist[0] (or `guess` when not NULL), prolongation,
+ * correction; then rotates the state as described at cgp_state.  u_dir
+ * device [2][n_dirichlet] at t^{n+1}; f device [2][N_f] or NULL; guess
+ * device [N_c] or NULL.  stats may be NULL; when given the call
+ * synchronises `stream` to fill it. */
+int cgp_project_step(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const double* f,
+                     const double* guess, cgp_step_stats* stats, void* stream);
+
+/* Device buffers of the last step's intermediates (read-only views into the
+ * workspace, valid until the next call on ctx): U~ [2][N_f], b_c [N_c],
+ * phi_f [N_f].  Any argument may be NULL. */
+int cgp_intermediates(cgp_ctx* ctx, const double** u_tilde, const double** b_c,
+                      const double** phi_f);
+
+/* Measurement hook.  While enabled, every launch of the selected kernel on
+ * this context is bracketed by a pair of HIP events recorded on the stream
+ * the kernel runs on.  kernel_id: 0 off, CGP_K_MASS_SPMV (velocity-correction
+ * mass-matrix product, 2 right-hand sides), CGP_K_MOM_SPMV (momentum BiCGSTAB
+ * product v = A p^, 2 right-hand sides), CGP_K_COARSE_SPMV (coarse PCG
+ * product), CGP_K_MOM_ASSEMBLE (momentum matrix and right-hand side),
+ * CGP_K_ROT_SPMV (rotational pressure mass-matrix product).  Enabling resets
+ * the accumulated time.  cgp_timing_read synchronises the recorded events and
+ * returns the summed kernel time (ms) and the number of launches. */
+#define CGP_K_MASS_SPMV 1
+#define CGP_K_MOM_SPMV 2
+#define CGP_K_COARSE_SPMV 3
+#define CGP_K_MOM_ASSEMBLE 4
+#define CGP_K_ROT_SPMV 5
+int cgp_timing_enable(cgp_ctx* ctx, int kernel_id);
+int cgp_timing_read(cgp_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Releases host memory and the pinned buffer; the workspace stays the
+ * caller's.  Safe on NULL. */
+void cgp_destroy(cgp_ctx* ctx);
+
+/* Thread-local description of the last error (never NULL). */
+const char* cgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGP_H */

@@ -1,0 +1,133 @@
+"""ctypes declarations mirroring include/cgp.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgp.so")
+
+CGP_OK = 0
+CGP_NOT_CONVERGED = 1
+CGP_ERR_INVALID = -1
+CGP_ERR_MESH = -2
+CGP_ERR_HIP = -3
+CGP_ERR_NAN = -4
+CGP_ERR_WORKSPACE = -5
+
+CGP_DIRICHLET = 1
+CGP_NATURAL = 2
+CGP_FP64 = 0
+CGP_MIXED = 1
+CGP_K_MASS_SPMV = 1
+CGP_K_MOM_SPMV = 2
+CGP_K_COARSE_SPMV = 3
+CGP_K_MOM_ASSEMBLE = 4
+CGP_K_ROT_SPMV = 5
+CGP_RESTRICT_GALERKIN = 0
+CGP_RESTRICT_INJECT = 1
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tris", C.c_int32), ("n_bedges", C.c_int32),
+                ("xy", _dp), ("tri", _ip), ("bedge", _ip), ("btag", _ip)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("coarse", Mesh), ("levels", C.c_int32), ("chi", C.c_int32),
+                ("precision", C.c_int32), ("restrict_mode", C.c_int32),
+                ("dt", C.c_double), ("nu", C.c_double), ("pcg_tol", C.c_double),
+                ("inner_tol", C.c_double), ("mom_tol", C.c_double), ("mass_tol", C.c_double),
+                ("max_iter", C.c_int32), ("mom_max_iter", C.c_int32),
+                ("mass_max_iter", C.c_int32), ("max_outer", C.c_int32)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_fine", C.c_int64), ("n_coarse", C.c_int64), ("n_fine_tris", C.c_int64),
+                ("n_coarse_tris", C.c_int64), ("nnz_fine", C.c_int64), ("nnz_coarse", C.c_int64),
+                ("n_dirichlet", C.c_int64), ("n_natural_coarse", C.c_int64),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("converged", C.c_int32),
+                ("pad_", C.c_int32), ("rel_res", C.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, outer_iters=self.outer_iters,
+                    converged=bool(self.converged), rel_res=self.rel_res)
+
+
+class StepStats(C.Structure):
+    _fields_ = [("momentum", SolveStats * 2), ("poisson", SolveStats), ("mass", SolveStats * 2),
+                ("prot", SolveStats)]
+
+    def as_dict(self):
+        return dict(momentum=[s.as_dict() for s in self.momentum], poisson=self.poisson.as_dict(),
+                    mass=[s.as_dict() for s in self.mass], prot=self.prot.as_dict())
+
+
+class State(C.Structure):
+    _fields_ = [("u_prev", C.c_void_p), ("u", C.c_void_p), ("p", C.c_void_p),
+                ("phi_hist", C.c_void_p * 4), ("step", C.c_int64)]
+
+
+# (name, restype, argtypes) of every entry point declared in include/cgp.h
+SIGNATURES = [
+    ("cgp_create", C.c_int, [C.POINTER(Problem), C.POINTER(C.c_void_p)]),
+    ("cgp_query", C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
+    ("cgp_fine_nodes", C.c_int, [C.c_void_p, _dp]),
+    ("cgp_dirichlet_nodes", C.c_int, [C.c_void_p, _ip]),
+    ("cgp_assemble", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cgp_momentum", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
+    ("cgp_restrict", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cgp_pcg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats),
+                                C.c_void_p]),
+    ("cgp_prolong", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cgp_correct", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
+    ("cgp_project_step", C.c_int, [C.c_void_p, C.POINTER(State), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
+    ("cgp_intermediates", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p)]),
+    ("cgp_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
+    ("cgp_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("cgp_destroy", None, [C.c_void_p]),
+    ("cgp_last_error", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libcgp.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} not found: the CGP HIP library is not built "
+            "(run `python -m paper_1812_00185_amd.build` or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class CGPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"CGP error {code}: {msg}")
+        self.code = code
+
+
+def check(code: int, allow_not_converged: bool = True) -> int:
+    if code == CGP_OK or (code == CGP_NOT_CONVERGED and allow_not_converged):
+        return code
+    raise CGPError(code, load().cgp_last_error().decode())

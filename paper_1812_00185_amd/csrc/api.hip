@@ -1,0 +1,627 @@
+// C-ABI entry points of the CGP library (declared in include/cgp.h).
+//
+// Orchestration only: argument checks, workspace carving, uploads, and the
+// host loops that queue solver iterations.  Krylov loops queue iterations in
+// chunks and poll the device-side stopping flags one chunk behind (a copy of
+// the solver scalars into pinned memory plus an event), so the GPU never
+// idles waiting for the host while a solve is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cgp.h"
+#include "device.hpp"
+#include "mesh.hpp"
+
+using cgp::DLevel;
+using cgp::Scal;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(CGP_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).  With
+// base == nullptr it only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct cgp_ctx {
+  cgp_problem prob;
+  cgp::Hierarchy h;
+  size_t ws_bytes = 0;
+  bool assembled = false;
+  int32_t nf = 0, nc = 0, tf = 0, tc = 0, ndir = 0;
+  int nb_f = 1, nb_c = 1;
+
+  DLevel F{}, C{};
+  int32_t *tri_f = nullptr, *tri_c = nullptr, *pcode = nullptr, *cn_ptr = nullptr,
+          *cn_tri = nullptr, *dir_index = nullptr;
+  uint8_t* nat_c = nullptr;
+  double *Mval = nullptr, *Aval = nullptr, *invdA = nullptr, *invdM = nullptr,
+         *invdM_int = nullptr;
+  double *Kc = nullptr, *Dxc = nullptr, *Dyc = nullptr, *invdKc = nullptr, *lumped_c = nullptr;
+  float *Kc32 = nullptr, *invdKc32 = nullptr;
+  double *ut = nullptr, *rhs = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr,
+         *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
+  double *phi_f = nullptr, *rot_rhs = nullptr, *dp = nullptr;
+  double *bc = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
+  float *cb32 = nullptr, *cx32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
+        *cq32 = nullptr;
+  double* tripart = nullptr;
+  double* part = nullptr;
+  Scal* scal = nullptr;
+
+  Scal* pinned = nullptr;  // [2][8] host-pinned copies of the solver scalars
+  hipEvent_t ev[2] = {nullptr, nullptr};
+
+  // measurement hook (cgp_timing_enable)
+  int timed_id = 0;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
+};
+
+namespace {
+
+// Lays out the workspace; with base == nullptr it measures.
+size_t carve(cgp_ctx* c, void* base) {
+  Carver w(base);
+  const size_t nf = c->nf, nc = c->nc;
+  const size_t nnzf = c->h.gf.nnz(), nnzc = c->h.gc.nnz();
+  int32_t* rp_f = w.take<int32_t>(nf + 1);
+  int32_t* col_f = w.take<int32_t>(nnzf);
+  int32_t* side_f = w.take<int32_t>(2 * nnzf);
+  double2* xy_f = w.take<double2>(nf);
+  c->tri_f = w.take<int32_t>(3 * (size_t)c->tf);
+  c->pcode = w.take<int32_t>(2 * nf);
+  c->dir_index = w.take<int32_t>(nf);
+  c->Mval = w.take<double>(nnzf);
+  c->Aval = w.take<double>(nnzf);
+  c->invdA = w.take<double>(nf);
+  c->invdM = w.take<double>(nf);
+  c->invdM_int = w.take<double>(nf);
+  double** vec2[] = {&c->ut, &c->rhs, &c->r, &c->rhat, &c->p, &c->v, &c->phat, &c->shat, &c->t};
+  for (double** q : vec2) *q = w.take<double>(2 * nf);
+  c->phi_f = w.take<double>(nf);
+  c->rot_rhs = w.take<double>(nf);
+  c->dp = w.take<double>(nf);
+
+  int32_t* rp_c = w.take<int32_t>(nc + 1);
+  int32_t* col_c = w.take<int32_t>(nnzc);
+  int32_t* side_c = w.take<int32_t>(2 * nnzc);
+  double2* xy_c = w.take<double2>(nc);
+  c->tri_c = w.take<int32_t>(3 * (size_t)c->tc);
+  c->cn_ptr = w.take<int32_t>(nc + 1);
+  c->cn_tri = w.take<int32_t>(3 * (size_t)c->tc);
+  c->nat_c = w.take<uint8_t>(nc);
+  c->Kc = w.take<double>(nnzc);
+  c->Kc32 = w.take<float>(nnzc);
+  c->Dxc = w.take<double>(nnzc);
+  c->Dyc = w.take<double>(nnzc);
+  c->invdKc = w.take<double>(nc);
+  c->invdKc32 = w.take<float>(nc);
+  c->lumped_c = w.take<double>(nc);
+  double** cvec[] = {&c->bc, &c->cr, &c->cz, &c->cp, &c->cq};
+  for (double** q : cvec) *q = w.take<double>(nc);
+  float** cvec32[] = {&c->cb32, &c->cx32, &c->cr32, &c->cz32, &c->cp32, &c->cq32};
+  for (float** q : cvec32) *q = w.take<float>(nc);
+  c->tripart = w.take<double>(3 * (size_t)c->tc);
+  c->part = w.take<double>((size_t)cgp::kSlots * 2 * cgp::kNbMax);
+  c->scal = w.take<Scal>(8);
+
+  c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f};
+  c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c};
+  return w.off + 256;
+}
+
+int check_ready(cgp_ctx* c) {
+  if (!c) return fail(CGP_ERR_INVALID, "null context");
+  if (!c->assembled) return fail(CGP_ERR_INVALID, "cgp_assemble has not been called");
+  return CGP_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Event pair for one launch of kernel `id` when it is the timed kernel.
+hipEvent_t* timer(cgp_ctx* c, int id) {
+  if (c->timed_id != id) return nullptr;
+  while (c->tev.size() < c->tev_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->tev.push_back(e);
+  }
+  hipEvent_t* p = c->tev.data() + c->tev_used;
+  c->tev_used += 2;
+  return p;
+}
+
+// Queues iterations 1..last of a Krylov solve through `launch(it, check_only)`
+// in chunks, polling the stopping flags of the first `nrhs` scalars one chunk
+// behind.  `last` = max_iter for PCG, max_iter + 1 for BiCGSTAB (whose final
+// test runs at the start of the next iteration).  Copies the final scalars to
+// `out`.
+template <class Launch>
+int drive(cgp_ctx* c, Scal* sc, int nrhs, int last, int chunk, bool trailing_check,
+          Launch launch, hipStream_t s, Scal* out) {
+  int it = 1, k = 0;
+  bool have_prev = false;
+  while (true) {
+    const int hi = std::min(it + chunk - 1, last);
+    for (; it <= hi; ++it) launch(it, trailing_check && it == last);
+    HIPCHK(hipMemcpyAsync(c->pinned + 8 * k, sc, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(c->ev[k], s));
+    auto all_done = [&](int slot) {
+      for (int d = 0; d < nrhs; ++d)
+        if (c->pinned[8 * slot + d].done_stamp == 0) return false;
+      return true;
+    };
+    if (have_prev) {
+      HIPCHK(hipEventSynchronize(c->ev[k ^ 1]));
+      if (all_done(k ^ 1)) {
+        std::memcpy(out, c->pinned + 8 * (k ^ 1), sizeof(Scal) * nrhs);
+        return CGP_OK;
+      }
+    }
+    if (it > last) {
+      HIPCHK(hipEventSynchronize(c->ev[k]));
+      std::memcpy(out, c->pinned + 8 * k, sizeof(Scal) * nrhs);
+      return CGP_OK;
+    }
+    have_prev = true;
+    k ^= 1;
+  }
+}
+
+int stats_status(const Scal* s, int nrhs, int max_iter, cgp_solve_stats* st) {
+  int code = CGP_OK;
+  for (int d = 0; d < nrhs; ++d) {
+    const bool done = s[d].done_stamp != 0;
+    if (s[d].status == 2) code = CGP_ERR_NAN;
+    else if (!done && code == CGP_OK) code = CGP_NOT_CONVERGED;
+    if (st) {
+      st[d].iters = done ? s[d].iters : max_iter;
+      st[d].outer_iters = 0;
+      st[d].converged = done && s[d].status == 0;
+      st[d].rel_res = s[d].rel;
+    }
+  }
+  if (code == CGP_ERR_NAN) g_err = "solver produced NaN/Inf";
+  if (code == CGP_NOT_CONVERGED) g_err = "iteration limit reached";
+  return code;
+}
+
+int worst(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  return std::max(a, b);
+}
+
+int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double* p,
+                 const double* u_dir, const double* f, double* ut, cgp_solve_stats* st,
+                 hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  cgp::launch_momentum_assemble(c->F, c->dir_index, P.dt, P.nu, u_prev, u, p, u_dir, c->ndir,
+                                f, c->Aval, c->invdA, c->rhs, ut, s, timer(c, CGP_K_MOM_ASSEMBLE));
+  cgp::BicgVecs V{ut, c->r, c->rhat, c->p, c->v, c->phat, c->shat, c->t, c->rhs, c->invdA};
+  cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
+  Scal out[2];
+  const int last = P.mom_max_iter + 1;
+  int rc = drive(c, c->scal, 2, last, 4, true,
+                 [&](int it, bool chk) {
+                   cgp::launch_bicg_iter(c->F, c->Aval, V, c->scal, c->part, c->nb_f, it,
+                                         P.mom_tol, chk, s, chk ? nullptr : timer(c, CGP_K_MOM_SPMV));
+                 },
+                 s, out);
+  if (rc) return rc;
+  return stats_status(out, 2, P.mom_max_iter, st);
+}
+
+int run_restrict(cgp_ctx* c, const double* ut, double* b, hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  const bool fp32 = P.precision == CGP_MIXED;
+  const double scale = -1.5 / P.dt;
+  if (P.restrict_mode == CGP_RESTRICT_GALERKIN) {
+    cgp::launch_restrict_galerkin(c->tri_f, c->tf, c->F.xy, P.levels, ut, c->nf, c->tripart,
+                                  fp32, s);
+    cgp::launch_restrict_nodes(c->nc, c->cn_ptr, c->cn_tri, c->tripart, c->nat_c, scale, b,
+                               c->part, c->nb_c, s);
+  } else {
+    cgp::launch_restrict_inject(c->C, c->nat_c, ut, c->nf, scale, b, c->part, c->nb_c, fp32, s);
+  }
+  if (c->h.n_nat_c == 0) cgp::launch_remove_mean(c->nc, b, c->part, c->nb_c, nullptr, s);
+  return CGP_OK;
+}
+
+int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  int rc = CGP_OK;
+  if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
+  if (P.precision == CGP_FP64) {
+    cgp::PcgVecs<double> V{x, c->cr, c->cz, c->cp, c->cq, b, c->invdKc, c->Kc};
+    cgp::launch_pcg_init<double, 1>(c->C, V, nullptr, false, c->scal, c->part, c->nb_c, s);
+    Scal out[1];
+    rc = drive(c, c->scal, 1, P.max_iter, 32, false,
+               [&](int it, bool) {
+                 cgp::launch_pcg_iter<double, 1>(c->C, V, nullptr, c->scal, c->part, c->nb_c,
+                                                 it, P.pcg_tol, false, s,
+                                                 timer(c, CGP_K_COARSE_SPMV));
+               },
+               s, out);
+    if (rc) return rc;
+    rc = stats_status(out, 1, P.max_iter, st);
+  } else {
+    // FP64 iterative refinement around FP32-inner Jacobi-PCG
+    int inner_total = 0, outer = 0;
+    Scal chk{};
+    bool converged = false;
+    for (;;) {
+      cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
+      cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, outer, s);
+      HIPCHK(hipMemcpyAsync(c->pinned, c->scal + 4, sizeof(Scal), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      chk = c->pinned[0];
+      if (chk.status == 2) {
+        rc = fail(CGP_ERR_NAN, "mixed-precision refinement produced NaN/Inf");
+        break;
+      }
+      if (chk.done_stamp) {
+        converged = true;
+        break;
+      }
+      if (outer >= P.max_outer || inner_total >= P.max_iter) break;
+      cgp::PcgVecs<float> V{c->cx32, c->cr32, c->cz32, c->cp32, c->cq32, c->cb32, c->invdKc32,
+                            c->Kc32};
+      cgp::launch_pcg_init<float, 1>(c->C, V, nullptr, true, c->scal, c->part, c->nb_c, s);
+      Scal out[1];
+      const int budget = std::max(1, P.max_iter - inner_total);
+      int r2 = drive(c, c->scal, 1, budget, 32, false,
+                     [&](int it, bool) {
+                       cgp::launch_pcg_iter<float, 1>(c->C, V, nullptr, c->scal, c->part,
+                                                      c->nb_c, it, P.inner_tol, false, s);
+                     },
+                     s, out);
+      if (r2) return r2;
+      if (out[0].status == 2) {
+        rc = fail(CGP_ERR_NAN, "inner FP32 solve produced NaN/Inf");
+        break;
+      }
+      inner_total += out[0].done_stamp ? out[0].iters : budget;
+      cgp::launch_axpy_f32(c->cx32, x, c->nc, s);
+      ++outer;
+    }
+    if (st) {
+      st->iters = inner_total;
+      st->outer_iters = outer;
+      st->converged = converged;
+      st->rel_res = chk.rel;
+    }
+    if (rc == CGP_OK && !converged) rc = fail(CGP_NOT_CONVERGED, "refinement limit reached");
+  }
+  if (c->h.n_nat_c == 0) {
+    cgp::launch_weighted_sums(c->nc, x, c->lumped_c, c->part, c->nb_c, s);
+    cgp::launch_remove_mean(c->nc, x, c->part, c->nb_c, c->lumped_c, s);
+  }
+  return rc;
+}
+
+int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
+                double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  const int chi = P.chi;
+  cgp::launch_correct_rhs(c->F, c->dir_index, P.dt, P.nu, chi, phi_f, ut, c->rhs, c->rot_rhs, s);
+  // velocity: M dU = rhs on the non-Dirichlet nodes (Dirichlet rows masked)
+  double* du = c->phat;
+  cgp::PcgVecs<double> V{du, c->r, c->rhat, c->p, c->v, c->rhs, c->invdM_int, c->Mval};
+  cgp::launch_pcg_init<double, 2>(c->F, V, c->dir_index, true, c->scal, c->part, c->nb_f, s);
+  Scal out[2];
+  int rc = drive(c, c->scal, 2, P.mass_max_iter, 8, false,
+                 [&](int it, bool) {
+                   cgp::launch_pcg_iter<double, 2>(c->F, V, c->dir_index, c->scal, c->part,
+                                                   c->nb_f, it, P.mass_tol, false, s,
+                                                   timer(c, CGP_K_MASS_SPMV));
+                 },
+                 s, out);
+  if (rc) return rc;
+  rc = stats_status(out, 2, P.mass_max_iter, st);
+  const double* dp = nullptr;
+  if (chi) {
+    cgp::PcgVecs<double> W{c->dp, c->t, c->t + c->nf, c->shat, c->shat + c->nf, c->rot_rhs,
+                           c->invdM, c->Mval};
+    cgp::launch_pcg_init<double, 1>(c->F, W, nullptr, true, c->scal + 2, c->part, c->nb_f, s);
+    Scal o1[1];
+    int r2 = drive(c, c->scal + 2, 1, P.mass_max_iter, 8, false,
+                   [&](int it, bool) {
+                     cgp::launch_pcg_iter<double, 1>(c->F, W, nullptr, c->scal + 2, c->part,
+                                                     c->nb_f, it, P.mass_tol, false, s,
+                                                     timer(c, CGP_K_ROT_SPMV));
+                   },
+                   s, o1);
+    if (r2) return r2;
+    rc = worst(rc, stats_status(o1, 1, P.mass_max_iter, st ? st + 2 : nullptr));
+    dp = c->dp;
+  } else if (st) {
+    st[2] = cgp_solve_stats{0, 0, 1, 0, 0.0};
+  }
+  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, dp, u_out, p_out, s);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cgp_last_error(void) { return g_err.c_str(); }
+
+int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
+  if (!prob || !out) return fail(CGP_ERR_INVALID, "null argument");
+  *out = nullptr;
+  const cgp_mesh& m = prob->coarse;
+  if (!m.xy || !m.tri || (m.n_bedges > 0 && (!m.bedge || !m.btag)) || m.n_nodes < 3 ||
+      m.n_tris < 1 || m.n_bedges < 0)
+    return fail(CGP_ERR_INVALID, "coarse mesh arrays missing or empty");
+  if (prob->levels < 0 || prob->levels > 3) return fail(CGP_ERR_INVALID, "levels must be 0..3");
+  if (prob->chi != 0 && prob->chi != 1) return fail(CGP_ERR_INVALID, "chi must be 0 or 1");
+  if (prob->precision != CGP_FP64 && prob->precision != CGP_MIXED)
+    return fail(CGP_ERR_INVALID, "precision must be CGP_FP64 or CGP_MIXED");
+  if (prob->restrict_mode != CGP_RESTRICT_GALERKIN && prob->restrict_mode != CGP_RESTRICT_INJECT)
+    return fail(CGP_ERR_INVALID, "unknown restrict_mode");
+  if (!(prob->dt > 0) || !(prob->nu > 0) || !(prob->pcg_tol > 0) || !(prob->mom_tol > 0) ||
+      !(prob->mass_tol > 0) || !(prob->inner_tol > 0) || prob->max_iter < 1 ||
+      prob->mom_max_iter < 1 || prob->mass_max_iter < 1 || prob->max_outer < 1)
+    return fail(CGP_ERR_INVALID, "dt, nu, tolerances and iteration caps must be positive");
+  cgp::Mesh cm;
+  cm.n_nodes = m.n_nodes;
+  cm.n_tris = m.n_tris;
+  cm.xy.assign(m.xy, m.xy + 2 * (size_t)m.n_nodes);
+  cm.tri.assign(m.tri, m.tri + 3 * (size_t)m.n_tris);
+  if (m.n_bedges) {
+    cm.bedge.assign(m.bedge, m.bedge + 2 * (size_t)m.n_bedges);
+    cm.btag.assign(m.btag, m.btag + m.n_bedges);
+  }
+  cgp_ctx* c = new (std::nothrow) cgp_ctx();
+  if (!c) return fail(CGP_ERR_INVALID, "out of host memory");
+  c->prob = *prob;
+  c->prob.coarse = cgp_mesh{};  // host pointers are not kept
+  std::string err;
+  try {
+    err = cgp::build_hierarchy(cm, prob->levels, c->h);
+  } catch (const std::exception& e) {
+    err = std::string("host set-up failed: ") + e.what();
+  }
+  if (!err.empty()) {
+    delete c;
+    return fail(CGP_ERR_MESH, err);
+  }
+  c->nf = c->h.fine.n_nodes;
+  c->nc = c->h.coarse.n_nodes;
+  c->tf = c->h.fine.n_tris;
+  c->tc = c->h.coarse.n_tris;
+  c->ndir = (int32_t)c->h.dir_nodes.size();
+  c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
+  c->nb_c = std::min(cgp::kNbMax, std::max(1, (c->nc + cgp::kBlock - 1) / cgp::kBlock));
+  c->ws_bytes = carve(c, nullptr);
+  *out = c;
+  return CGP_OK;
+}
+
+int cgp_query(const cgp_ctx* c, cgp_sizes* out) {
+  if (!c || !out) return fail(CGP_ERR_INVALID, "null argument");
+  out->n_fine = c->nf;
+  out->n_coarse = c->nc;
+  out->n_fine_tris = c->tf;
+  out->n_coarse_tris = c->tc;
+  out->nnz_fine = c->h.gf.nnz();
+  out->nnz_coarse = c->h.gc.nnz();
+  out->n_dirichlet = c->ndir;
+  out->n_natural_coarse = c->h.n_nat_c;
+  out->workspace_bytes = c->ws_bytes;
+  return CGP_OK;
+}
+
+int cgp_fine_nodes(const cgp_ctx* c, double* xy) {
+  if (!c || !xy) return fail(CGP_ERR_INVALID, "null argument");
+  std::memcpy(xy, c->h.fine.xy.data(), sizeof(double) * c->h.fine.xy.size());
+  return CGP_OK;
+}
+
+int cgp_dirichlet_nodes(const cgp_ctx* c, int32_t* nodes) {
+  if (!c || (!nodes && c->ndir)) return fail(CGP_ERR_INVALID, "null argument");
+  if (c->ndir) std::memcpy(nodes, c->h.dir_nodes.data(), sizeof(int32_t) * c->ndir);
+  return CGP_OK;
+}
+
+int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c) return fail(CGP_ERR_INVALID, "null context");
+  if (!ws || bytes < c->ws_bytes)
+    return fail(CGP_ERR_WORKSPACE, "workspace missing or smaller than cgp_query().workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(CGP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = as_stream(stream);
+  carve(c, ws);
+  auto up = [&](void* dst, const void* src, size_t n) -> hipError_t {
+    return n ? hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  const cgp::Hierarchy& h = c->h;
+  HIPCHK(up((void*)c->F.rowptr, h.gf.rowptr.data(), 4 * h.gf.rowptr.size()));
+  HIPCHK(up((void*)c->F.col, h.gf.col.data(), 4 * h.gf.col.size()));
+  HIPCHK(up((void*)c->F.side, h.gf.side.data(), 4 * h.gf.side.size()));
+  HIPCHK(up((void*)c->F.xy, h.fine.xy.data(), 8 * h.fine.xy.size()));
+  HIPCHK(up(c->tri_f, h.fine.tri.data(), 4 * h.fine.tri.size()));
+  HIPCHK(up(c->pcode, h.pcode.data(), 4 * h.pcode.size()));
+  HIPCHK(up(c->dir_index, h.dir_index.data(), 4 * h.dir_index.size()));
+  HIPCHK(up((void*)c->C.rowptr, h.gc.rowptr.data(), 4 * h.gc.rowptr.size()));
+  HIPCHK(up((void*)c->C.col, h.gc.col.data(), 4 * h.gc.col.size()));
+  HIPCHK(up((void*)c->C.side, h.gc.side.data(), 4 * h.gc.side.size()));
+  HIPCHK(up((void*)c->C.xy, h.coarse.xy.data(), 8 * h.coarse.xy.size()));
+  HIPCHK(up(c->tri_c, h.coarse.tri.data(), 4 * h.coarse.tri.size()));
+  HIPCHK(up(c->cn_ptr, h.cn_ptr.data(), 4 * h.cn_ptr.size()));
+  HIPCHK(up(c->cn_tri, h.cn_tri.data(), 4 * h.cn_tri.size()));
+  HIPCHK(up(c->nat_c, h.nat_c.data(), h.nat_c.size()));
+  if (!c->pinned) {
+    HIPCHK(hipHostMalloc((void**)&c->pinned, sizeof(Scal) * 16, hipHostMallocDefault));
+    std::memset(c->pinned, 0, sizeof(Scal) * 16);
+  }
+  for (int k = 0; k < 2; ++k)
+    if (!c->ev[k]) HIPCHK(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming));
+  HIPCHK(hipMemsetAsync(c->scal, 0, sizeof(Scal) * 8, s));
+  cgp::launch_mass_assemble(c->F, c->dir_index, c->Mval, c->invdM, c->invdM_int, s);
+  cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
+                              c->invdKc32, c->lumped_c, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  c->assembled = true;
+  return CGP_OK;
+}
+
+int cgp_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double* p,
+                 const double* u_dir, const double* f, double* u_tilde, cgp_solve_stats st[2],
+                 void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!u_prev || !u || !p || !u_tilde || (c->ndir && !u_dir))
+    return fail(CGP_ERR_INVALID, "null device pointer");
+  if (u_tilde == u || u_tilde == u_prev) return fail(CGP_ERR_INVALID, "u_tilde aliases an input");
+  hipStream_t s = as_stream(stream);
+  int rc = run_momentum(c, u_prev, u, p, u_dir, f, u_tilde, st, s);
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+
+int cgp_restrict(cgp_ctx* c, const double* ut, double* b, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!ut || !b) return fail(CGP_ERR_INVALID, "null device pointer");
+  run_restrict(c, ut, b, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
+int cgp_pcg_solve(cgp_ctx* c, const double* b, double* phi, cgp_solve_stats* st, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!b || !phi) return fail(CGP_ERR_INVALID, "null device pointer");
+  if (b == phi) return fail(CGP_ERR_INVALID, "b_c and phi_c alias");
+  int rc = run_pcg(c, b, phi, st, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+
+int cgp_prolong(cgp_ctx* c, const double* phic, double* phif, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!phic || !phif) return fail(CGP_ERR_INVALID, "null device pointer");
+  cgp::launch_prolong(c->nf, c->nc, c->pcode, c->tri_c, c->prob.levels, phic, phif,
+                      c->prob.precision == CGP_MIXED, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
+int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
+                double* u_out, double* p_out, cgp_solve_stats st[3], void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!ut || !phi_f || !p_in || !u_out || !p_out) return fail(CGP_ERR_INVALID, "null device pointer");
+  if (u_out == ut) return fail(CGP_ERR_INVALID, "u_out aliases u_tilde");
+  int rc = run_correct(c, ut, phi_f, p_in, u_out, p_out, st, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+
+int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
+                     const double* guess, cgp_step_stats* st, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!S || !S->u_prev || !S->u || !S->p || (c->ndir && !u_dir))
+    return fail(CGP_ERR_INVALID, "null state or boundary pointer");
+  for (int k = 0; k < 4; ++k)
+    if (!S->phi_hist[k]) return fail(CGP_ERR_INVALID, "null phi_hist pointer");
+  hipStream_t s = as_stream(stream);
+  cgp_step_stats local{};
+  cgp_step_stats* T = st ? st : &local;
+  int rc = run_momentum(c, S->u_prev, S->u, S->p, u_dir, f, c->ut, T->momentum, s);
+  if (rc < 0) return rc;
+  run_restrict(c, c->ut, c->bc, s);
+  double* phi_new = S->phi_hist[3];
+  cgp::launch_copy(guess ? guess : S->phi_hist[0], phi_new, c->nc, s);
+  rc = worst(rc, run_pcg(c, c->bc, phi_new, &T->poisson, s));
+  if (rc < 0) return rc;
+  cgp::launch_prolong(c->nf, c->nc, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f,
+                      c->prob.precision == CGP_MIXED, s);
+  cgp_solve_stats cs[3];
+  rc = worst(rc, run_correct(c, c->ut, c->phi_f, S->p, S->u_prev, S->p, cs, s));
+  if (rc < 0) return rc;
+  T->mass[0] = cs[0];
+  T->mass[1] = cs[1];
+  T->prot = cs[2];
+  double* np1 = S->u_prev;
+  S->u_prev = S->u;
+  S->u = np1;
+  double* h3 = S->phi_hist[3];
+  S->phi_hist[3] = S->phi_hist[2];
+  S->phi_hist[2] = S->phi_hist[1];
+  S->phi_hist[1] = S->phi_hist[0];
+  S->phi_hist[0] = h3;
+  S->step += 1;
+  HIPCHK(hipGetLastError());
+  if (st) HIPCHK(hipStreamSynchronize(s));
+  return rc;
+}
+
+int cgp_intermediates(cgp_ctx* c, const double** ut, const double** bc, const double** phif) {
+  if (int rc = check_ready(c)) return rc;
+  if (ut) *ut = c->ut;
+  if (bc) *bc = c->bc;
+  if (phif) *phif = c->phi_f;
+  return CGP_OK;
+}
+
+int cgp_timing_enable(cgp_ctx* c, int kernel_id) {
+  if (!c) return fail(CGP_ERR_INVALID, "null context");
+  if (kernel_id < 0 || kernel_id > CGP_K_ROT_SPMV) return fail(CGP_ERR_INVALID, "unknown kernel id");
+  c->timed_id = kernel_id;
+  c->tev_used = 0;
+  return CGP_OK;
+}
+
+int cgp_timing_read(cgp_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return fail(CGP_ERR_INVALID, "null argument");
+  double sum = 0.0;
+  for (size_t k = 0; k + 1 < c->tev_used; k += 2) {
+    HIPCHK(hipEventSynchronize(c->tev[k + 1]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->tev[k], c->tev[k + 1]));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)(c->tev_used / 2);
+  return CGP_OK;
+}
+
+void cgp_destroy(cgp_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal declarations shared by the kernels (kernels.hip) and the C-ABI
+// orchestration (api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cgp {
+
+constexpr int kBlock = 256;    // threads per block (4 wave64)
+constexpr int kNbMax = 1024;   // blocks per solver launch (partial-sum slots)
+constexpr int kSlots = 8;      // reduction slots per right-hand side
+
+// CSR node graph with edge sides (see mesh.hpp), on the device.
+struct DLevel {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const int32_t* side;
+  const double2* xy;
+};
+
+// Per right-hand-side solver scalars.  done_stamp is the (iteration, phase)
+// stamp of the kernel that finished the solve, 0 while running; a kernel
+// skips a right-hand side whose stamp is smaller than its own, so the kernel
+// that takes the decision (every block of it computes the same value) never
+// races with its own write.
+struct Scal {
+  double rho[2];    // PCG: rho of even / odd iterations; BiCGSTAB: rho[0] current
+  double rho_old;
+  double alpha;
+  double omega;
+  double bb;        // ||b||^2
+  double rel;       // last relative residual seen by the stopping test
+  int32_t done_stamp;
+  int32_t iters;
+  int32_t status;   // 0 converged, 2 NaN
+  int32_t pad_;
+};
+
+inline int stamp(int it, int phase) { return it * 8 + phase; }
+
+// ---------------------------------------------------------------- assembly
+void launch_mass_assemble(const DLevel& L, const int32_t* dir_index, double* Mval,
+                          double* invd_full, double* invd_int, hipStream_t s);
+void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
+                            double* Dxval, double* Dyval, double* invd, float* invd32,
+                            double* lumped, hipStream_t s);
+void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double dt, double nu,
+                              const double* u_prev, const double* u, const double* p,
+                              const double* u_dir, int32_t n_dir, const double* f,
+                              double* Aval, double* invdA, double* rhs, double* x0,
+                              hipStream_t s, hipEvent_t* ev = nullptr);
+
+// ---------------------------------------------------------------- BiCGSTAB (2 rhs)
+struct BicgVecs {
+  double *x, *r, *rhat, *p, *v, *phat, *shat, *t;
+  const double* b;
+  const double* invd;
+};
+void launch_bicg_init(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
+                      double* part, int nb, hipStream_t s);
+// `ev`, when not null, is a pair of events recorded around the SpMV kernel
+// v = A p^ (measurement hook).
+void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
+                      double* part, int nb, int it, double tol, bool check_only,
+                      hipStream_t s, hipEvent_t* ev = nullptr);
+
+// ---------------------------------------------------------------- PCG
+template <typename T>
+struct PcgVecs {
+  T *x, *r, *z, *p, *q;
+  const T* b;
+  const T* invd;
+  const T* val;
+};
+template <typename T, int NR>
+void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, bool zero_x0,
+                     Scal* sc, double* part, int nb, hipStream_t s);
+// `ev`, when not null, is a pair of events recorded around the SpMV kernel.
+template <typename T, int NR>
+void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, Scal* sc,
+                     double* part, int nb, int it, double tol, bool check_only, hipStream_t s,
+                     hipEvent_t* ev = nullptr);
+
+// ---------------------------------------------------------------- restriction / prolongation
+void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
+                              int levels, const double* ut, int64_t stride, double* tripart,
+                              bool fp32, hipStream_t s);
+void launch_restrict_nodes(int32_t n_c, const int32_t* cn_ptr, const int32_t* cn_tri,
+                           const double* tripart, const uint8_t* nat, double scale, double* b,
+                           double* part, int nb, hipStream_t s);
+void launch_restrict_inject(const DLevel& C, const uint8_t* nat, const double* ut,
+                            int64_t stride, double scale, double* b, double* part, int nb,
+                            bool fp32, hipStream_t s);
+void launch_remove_mean(int32_t n, double* v, const double* part, int nb, const double* weights,
+                        hipStream_t s);
+void launch_weighted_sums(int32_t n, const double* v, const double* w, double* part, int nb,
+                          hipStream_t s);
+void launch_prolong(int32_t n_f, int32_t n_c, const int32_t* pcode, const int32_t* tri_c,
+                    int levels, const double* phic, double* phif, bool fp32, hipStream_t s);
+
+// ---------------------------------------------------------------- correction
+void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
+                        int chi, const double* phi_f, const double* ut, double* rhs_vel,
+                        double* rhs_rot, hipStream_t s);
+void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
+                         const double* phi_f, const double* dp, double* u_out, double* p_out,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------- small vector ops
+void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s);
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s);
+void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,
+                       double* r, float* r32, double* part, int nb, hipStream_t s);
+void launch_reduce_check(const double* part, int nb, double tol, Scal* sc, int outer,
+                         hipStream_t s);
+
+}  // namespace cgp

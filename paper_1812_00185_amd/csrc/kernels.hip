@@ -1,0 +1,1219 @@
+// HIP kernels of the CGP step for gfx950 (wave64).
+//
+// Operators are assembled from the CSR node graph with "edge sides" (for an
+// off-diagonal slot (i, j): the third vertex of each triangle sharing edge
+// ij, with its orientation).  For P1 triangles every per-row quantity follows
+// from the sides of the row:
+//   with (i, j, k) taken counter-clockwise (sign s = +1 for the ccw side,
+//   -1 for the cw side), |e| = s det(x_j - x_i, x_k - x_i) / 2 and
+//   b_i = s (y_j - y_k), c_i = s (x_k - x_j), b_j = s (y_k - y_i), c_j = s (x_i - x_k):
+//     mass        M_ij  = sum |e| / 12,          M_ii = sum_j M_ij
+//     stiffness   K_ij  = sum (b_i b_j + c_i c_j) / (4|e|),  K_ii = -sum_j K_ij
+//     convection  N_ij  = sum ((2 w_i + w_j + w_k) . (b_j, c_j)) / 24,  N_ii = -sum_j N_ij
+//     divergence  (D u)_i = sum_sides (b_j u_j + c_j v_j) / 6 + (b_i u_i + c_i v_i) / 12
+//     gradient    (G p)_i = -sum_sides (b_i, c_i) (p_j + p_i / 2) / 6      (G = -D^T)
+// (each triangle at i appears as two sides of row i).  No element matrices are
+// stored and no atomics are used: every output row is owned by one thread or
+// one lane group, and every reduction is a fixed-order two-pass block sum, so
+// results are bitwise reproducible run to run.
+#include "device.hpp"
+
+namespace cgp {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+// reduction slot kinds (x2 right-hand sides)
+enum { SL_RR = 0, SL_RZ = 1, SL_BB = 2, SL_PQ = 3, SL_RHR = 4, SL_RHV = 5, SL_SS = 6, SL_TS = 7 };
+// BiCGSTAB's (t, t) reuses the PQ slot
+#define SL_TT SL_PQ
+
+__device__ __forceinline__ int slot(int kind, int d) { return (kind * 2 + d) * kNbMax; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum NS per-thread values over the block; thread 0 stores them at
+// part[idx[s] + blockIdx.x].
+template <int NS>
+__device__ void block_store(const double (&v)[NS], double* part, const int (&idx)[NS]) {
+  __shared__ double sh[NS][kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double t = wave_sum(v[s]);
+    if (lane == 0) sh[s][wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double t = 0.0;
+      for (int w = 0; w < kWaves; ++w) t += sh[s][w];
+      part[idx[s] + blockIdx.x] = t;
+    }
+  }
+}
+
+// Every thread of the block receives sum_{b < nb} part[idx[s] + b], summed in
+// the same order by every block.
+template <int NS>
+__device__ void block_sums(const double* part, int nb, const int (&idx)[NS], double (&out)[NS]) {
+  __shared__ double sh[NS][kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) t += part[idx[s] + b];
+    t = wave_sum(t);
+    if (lane == 0) sh[s][wv] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += sh[s][w];
+    out[s] = t;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool active(const Scal* sc, int d, int my_stamp) {
+  const int st = sc[d].done_stamp;
+  return st == 0 || st >= my_stamp;
+}
+
+// y(row) = sum_s val[s] x[col[s]] for NR right-hand sides (stride n) with
+// LW lanes per row; every lane of the group ends with the full sums.
+template <typename T, int NR, int LW>
+__device__ __forceinline__ void spmv_row(const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ col,
+                                         const T* __restrict__ val, const T* __restrict__ x,
+                                         int64_t n, int row, int lane, T (&acc)[NR]) {
+#pragma unroll
+  for (int d = 0; d < NR; ++d) acc[d] = T(0);
+  const int beg = rowptr[row], end = rowptr[row + 1];
+  for (int s = beg + lane; s < end; s += LW) {
+    const T a = val[s];
+    const int c = col[s];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) acc[d] += a * x[d * n + c];
+  }
+#pragma unroll
+  for (int o = LW / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int d = 0; d < NR; ++d) acc[d] += __shfl_xor(acc[d], o, LW);
+}
+
+constexpr int kLanes = 8;   // lanes per CSR row in the SpMV kernels (~7 nonzeros per row)
+
+// ------------------------------------------------------------------ assembly
+
+struct SideGeo {
+  double area, bi, ci, bj, cj;
+};
+
+__device__ __forceinline__ SideGeo side_geo(double2 pi, double2 pj, double2 pk, double sg) {
+  SideGeo g;
+  const double a2 = (pj.x - pi.x) * (pk.y - pi.y) - (pk.x - pi.x) * (pj.y - pi.y);
+  g.area = 0.5 * sg * a2;
+  g.bi = sg * (pj.y - pk.y);
+  g.ci = sg * (pk.x - pj.x);
+  g.bj = sg * (pk.y - pi.y);
+  g.cj = sg * (pi.x - pk.x);
+  return g;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_mass_assemble(DLevel L, const int32_t* __restrict__ dir_index, double* __restrict__ Mval,
+                double* __restrict__ invd_full, double* __restrict__ invd_int) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L.n; i += gridDim.x * blockDim.x) {
+    const int beg = L.rowptr[i], end = L.rowptr[i + 1];
+    const double2 pi = L.xy[i];
+    double dm = 0.0;
+    for (int s = beg + 1; s < end; ++s) {
+      const double2 pj = L.xy[L.col[s]];
+      double m = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = L.side[2 * s + q];
+        if (k < 0) continue;
+        m += side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0).area * (1.0 / 12.0);
+      }
+      Mval[s] = m;
+      dm += m;
+    }
+    Mval[beg] = dm;
+    invd_full[i] = 1.0 / dm;
+    invd_int[i] = (dir_index && dir_index[i] >= 0) ? 0.0 : 1.0 / dm;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_coarse_assemble(DLevel L, const uint8_t* __restrict__ nat, double* __restrict__ Kval,
+                  float* __restrict__ Kval32, double* __restrict__ Dx, double* __restrict__ Dy,
+                  double* __restrict__ invd, float* __restrict__ invd32,
+                  double* __restrict__ lumped) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L.n; i += gridDim.x * blockDim.x) {
+    const int beg = L.rowptr[i], end = L.rowptr[i + 1];
+    const double2 pi = L.xy[i];
+    const bool nat_i = nat[i] != 0;
+    double dk = 0.0, dxi = 0.0, dyi = 0.0, lump = 0.0;
+    for (int s = beg + 1; s < end; ++s) {
+      const int j = L.col[s];
+      const double2 pj = L.xy[j];
+      double kk = 0.0, dx = 0.0, dy = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = L.side[2 * s + q];
+        if (k < 0) continue;
+        const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
+        kk += (g.bi * g.bj + g.ci * g.cj) / (4.0 * g.area);
+        dx += g.bj * (1.0 / 6.0);
+        dy += g.cj * (1.0 / 6.0);
+        dxi += g.bi * (1.0 / 12.0);
+        dyi += g.ci * (1.0 / 12.0);
+        lump += g.area * (1.0 / 6.0);
+      }
+      dk += kk;
+      // phi = 0 rows and columns removed: identity rows, zero coupling
+      const double kv = (nat_i || nat[j]) ? 0.0 : kk;
+      Kval[s] = kv;
+      Kval32[s] = (float)kv;
+      Dx[s] = dx;
+      Dy[s] = dy;
+    }
+    const double kii = nat_i ? 1.0 : -dk;
+    Kval[beg] = kii;
+    Kval32[beg] = (float)kii;
+    invd[i] = 1.0 / kii;
+    invd32[i] = (float)(1.0 / kii);
+    Dx[beg] = dxi;
+    Dy[beg] = dyi;
+    lumped[i] = lump;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
+                    const double* __restrict__ up, const double* __restrict__ u,
+                    const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
+                    const double* __restrict__ f, double* __restrict__ A,
+                    double* __restrict__ invdA, double* __restrict__ rhs,
+                    double* __restrict__ x0) {
+  const int64_t n = L.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int beg = L.rowptr[i], end = L.rowptr[i + 1];
+    const double wix = 2.0 * u[i] - up[i], wiy = 2.0 * u[n + i] - up[n + i];
+    x0[i] = wix;
+    x0[n + i] = wiy;
+    const int di = dir_index[i];
+    if (di >= 0) {  // Dirichlet row: identity, right-hand side = boundary value
+      A[beg] = 1.0;
+      for (int s = beg + 1; s < end; ++s) A[s] = 0.0;
+      invdA[i] = 1.0;
+      rhs[i] = udir[di];
+      rhs[n + i] = udir[ndir + di];
+      continue;
+    }
+    const double2 pi = L.xy[i];
+    const double Pi = p[i];
+    double bxi = 2.0 * u[i] - 0.5 * up[i], byi = 2.0 * u[n + i] - 0.5 * up[n + i];
+    if (f) {
+      bxi += dt * f[i];
+      byi += dt * f[n + i];
+    }
+    double dm = 0.0, dk = 0.0, dn = 0.0, rx = 0.0, ry = 0.0, gx = 0.0, gy = 0.0;
+    for (int s = beg + 1; s < end; ++s) {
+      const int j = L.col[s];
+      const double2 pj = L.xy[j];
+      const double ujx = u[j], ujy = u[n + j], upjx = up[j], upjy = up[n + j];
+      const double wjx = 2.0 * ujx - upjx, wjy = 2.0 * ujy - upjy;
+      const double Pj = p[j];
+      double m = 0.0, kk = 0.0, nn = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = L.side[2 * s + q];
+        if (k < 0) continue;
+        const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
+        const double wkx = 2.0 * u[k] - up[k], wky = 2.0 * u[n + k] - up[n + k];
+        m += g.area * (1.0 / 12.0);
+        kk += (g.bi * g.bj + g.ci * g.cj) / (4.0 * g.area);
+        nn += ((2.0 * wix + wjx + wkx) * g.bj + (2.0 * wiy + wjy + wky) * g.cj) * (1.0 / 24.0);
+        gx += g.bi * (Pj + 0.5 * Pi);
+        gy += g.ci * (Pj + 0.5 * Pi);
+      }
+      A[s] = 1.5 * m + dtnu * kk + dt * nn;
+      dm += m;
+      dk += kk;
+      dn += nn;
+      double bx = 2.0 * ujx - 0.5 * upjx, by = 2.0 * ujy - 0.5 * upjy;
+      if (f) {
+        bx += dt * f[j];
+        by += dt * f[n + j];
+      }
+      rx += m * bx;
+      ry += m * by;
+    }
+    const double aii = 1.5 * dm - dtnu * dk - dt * dn;
+    A[beg] = aii;
+    invdA[i] = 1.0 / aii;
+    rhs[i] = rx + dm * bxi + (dt / 6.0) * gx;
+    rhs[n + i] = ry + dm * byi + (dt / 6.0) * gy;
+  }
+}
+
+// ------------------------------------------------------------------ BiCGSTAB
+// Right-Jacobi-preconditioned BiCGSTAB on two right-hand sides sharing A.
+// One iteration = five kernels:
+//   B1  stopping test on r, rho = (r^, r), p = r + beta (p - omega v), p^ = D^-1 p
+//   B2  v = A p^,                         partial (r^, v)
+//   B3  alpha, s = r - alpha v (in r),    s^ = D^-1 s, partial (s, s)
+//   B4  half-step test (x += alpha p^ and stop) or t = A s^, partials (t, s), (t, t)
+//   B5  omega, x += alpha p^ + omega s^, r = s - omega t, partials (r, r), (r^, r)
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part) {
+  const int64_t n = L.n;
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double rr[2] = {0, 0}, bb[2] = {0, 0};
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      double ax[2];
+      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.x, n, row, lane, ax);
+      if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          const double b = V.b[d * n + row];
+          const double r = b - ax[d];
+          V.r[d * n + row] = r;
+          V.rhat[d * n + row] = r;
+          V.p[d * n + row] = 0.0;
+          V.v[d * n + row] = 0.0;
+          rr[d] += r * r;
+          bb[d] += b * b;
+        }
+      }
+    }
+  }
+  const double vals[6] = {rr[0], rr[1], rr[0], rr[1], bb[0], bb[1]};
+  const int idx[6] = {slot(SL_RR, 0), slot(SL_RR, 1), slot(SL_RHR, 0), slot(SL_RHR, 1),
+                      slot(SL_BB, 0), slot(SL_BB, 1)};
+  block_store<6>(vals, part, idx);
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    Scal& s = sc[threadIdx.x];
+    s.rho[0] = s.rho[1] = 0.0;
+    s.rho_old = s.alpha = s.omega = 1.0;
+    s.bb = 0.0;
+    s.rel = 0.0;
+    s.done_stamp = 0;
+    s.iters = 0;
+    s.status = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_b1(int32_t n32, BicgVecs V, Scal* sc, const double* part, int nb, int it, double tol,
+          int my_stamp, int check_only) {
+  const int64_t n = n32;
+  bool act[2] = {active(sc, 0, my_stamp), active(sc, 1, my_stamp)};
+  if (!act[0] && !act[1]) return;
+  const int idx[6] = {slot(SL_RR, 0), slot(SL_RR, 1), slot(SL_RHR, 0), slot(SL_RHR, 1),
+                      slot(SL_BB, 0), slot(SL_BB, 1)};
+  double s6[6];
+  block_sums<6>(part, nb, idx, s6);
+  bool zero_rhs[2] = {false, false}, upd[2] = {false, false};
+  double beta[2] = {0, 0}, omega[2] = {1, 1};
+  for (int d = 0; d < 2; ++d) {
+    if (!act[d]) continue;
+    const double bb = it == 1 ? s6[4 + d] : sc[d].bb;
+    const double rel = bb > 0.0 ? sqrt(s6[d] / bb) : 0.0;
+    const bool nan = !isfinite(bb) || !isfinite(s6[d]) || !isfinite(rel);
+    bool fin = false;
+    if (bb == 0.0) {
+      zero_rhs[d] = true;
+      fin = true;
+    } else if (nan || rel <= tol || check_only) {
+      fin = nan || rel <= tol;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (it == 1) sc[d].bb = bb;
+      sc[d].rel = rel;
+      if (fin) {
+        sc[d].done_stamp = my_stamp;
+        sc[d].iters = it - 1;
+        sc[d].status = nan ? 2 : 0;
+      } else if (!check_only) {
+        sc[d].rho[0] = s6[2 + d];
+      }
+    }
+    if (!fin && !check_only) {
+      upd[d] = true;
+      beta[d] = (s6[2 + d] / sc[d].rho_old) * (sc[d].alpha / sc[d].omega);
+      omega[d] = sc[d].omega;
+    }
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double dinv = V.invd[i];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (zero_rhs[d]) V.x[d * n + i] = 0.0;
+      if (!upd[d]) continue;
+      const double pv = V.r[d * n + i] + beta[d] * (V.p[d * n + i] - omega[d] * V.v[d * n + i]);
+      V.p[d * n + i] = pv;
+      V.phat[d * n + i] = dinv * pv;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_b2(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part,
+          int my_stamp) {
+  if (!active(sc, 0, my_stamp) && !active(sc, 1, my_stamp)) return;
+  const int64_t n = L.n;
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double dot[2] = {0, 0};
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      double av[2];
+      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.phat, n, row, lane, av);
+      if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          V.v[d * n + row] = av[d];
+          dot[d] += V.rhat[d * n + row] * av[d];
+        }
+      }
+    }
+  }
+  const int idx[2] = {slot(SL_RHV, 0), slot(SL_RHV, 1)};
+  block_store<2>(dot, part, idx);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_b3(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp) {
+  const int64_t n = n32;
+  bool act[2] = {active(sc, 0, my_stamp), active(sc, 1, my_stamp)};
+  if (!act[0] && !act[1]) return;
+  const int idx[2] = {slot(SL_RHV, 0), slot(SL_RHV, 1)};
+  double rhv[2];
+  block_sums<2>(part, nb, idx, rhv);
+  double alpha[2];
+  for (int d = 0; d < 2; ++d) {
+    alpha[d] = act[d] ? sc[d].rho[0] / rhv[d] : 0.0;
+    if (act[d] && blockIdx.x == 0 && threadIdx.x == 0) sc[d].alpha = alpha[d];
+  }
+  double ss[2] = {0, 0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double dinv = V.invd[i];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (!act[d]) continue;
+      const double s = V.r[d * n + i] - alpha[d] * V.v[d * n + i];
+      V.r[d * n + i] = s;
+      V.shat[d * n + i] = dinv * s;
+      ss[d] += s * s;
+    }
+  }
+  const int o[2] = {slot(SL_SS, 0), slot(SL_SS, 1)};
+  block_store<2>(ss, part, o);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part, int nb,
+          int it, double tol, int my_stamp) {
+  const int64_t n = L.n;
+  bool act[2] = {active(sc, 0, my_stamp), active(sc, 1, my_stamp)};
+  if (!act[0] && !act[1]) return;
+  const int idx[2] = {slot(SL_SS, 0), slot(SL_SS, 1)};
+  double ss[2];
+  block_sums<2>(part, nb, idx, ss);
+  bool half[2] = {false, false}, need_t = false;
+  double alpha[2] = {0, 0};
+  for (int d = 0; d < 2; ++d) {
+    if (!act[d]) continue;
+    const double rel = sqrt(ss[d] / sc[d].bb);
+    const bool nan = !isfinite(rel);
+    if (nan || rel <= tol) {
+      half[d] = true;
+      alpha[d] = sc[d].alpha;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[d].rel = rel;
+        sc[d].done_stamp = my_stamp;
+        sc[d].iters = it;
+        sc[d].status = nan ? 2 : 0;
+      }
+    } else {
+      need_t = true;
+    }
+  }
+  if (half[0] || half[1]) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        if (half[d]) V.x[d * n + i] += alpha[d] * V.phat[d * n + i];
+    }
+  }
+  if (!need_t) return;
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double ts[2] = {0, 0}, tt[2] = {0, 0};
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      double at[2];
+      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.shat, n, row, lane, at);
+      if (lane == 0) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          V.t[d * n + row] = at[d];
+          ts[d] += at[d] * V.r[d * n + row];
+          tt[d] += at[d] * at[d];
+        }
+      }
+    }
+  }
+  const double vals[4] = {ts[0], ts[1], tt[0], tt[1]};
+  const int o[4] = {slot(SL_TS, 0), slot(SL_TS, 1), slot(SL_TT, 0), slot(SL_TT, 1)};
+  block_store<4>(vals, part, o);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bicg_b5(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp) {
+  const int64_t n = n32;
+  bool act[2] = {active(sc, 0, my_stamp), active(sc, 1, my_stamp)};
+  if (!act[0] && !act[1]) return;
+  const int idx[4] = {slot(SL_TS, 0), slot(SL_TS, 1), slot(SL_TT, 0), slot(SL_TT, 1)};
+  double s4[4];
+  block_sums<4>(part, nb, idx, s4);
+  double alpha[2] = {0, 0}, omega[2] = {0, 0};
+  for (int d = 0; d < 2; ++d) {
+    if (!act[d]) continue;
+    alpha[d] = sc[d].alpha;
+    omega[d] = s4[d] / s4[2 + d];
+  }
+  double rr[2] = {0, 0}, rhr[2] = {0, 0};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (!act[d]) continue;
+      const int64_t k = d * n + i;
+      V.x[k] += alpha[d] * V.phat[k] + omega[d] * V.shat[k];
+      const double r = V.r[k] - omega[d] * V.t[k];
+      V.r[k] = r;
+      rr[d] += r * r;
+      rhr[d] += V.rhat[k] * r;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int d = 0; d < 2; ++d)
+      if (act[d]) {
+        sc[d].omega = omega[d];
+        sc[d].rho_old = sc[d].rho[0];
+      }
+  }
+  const double vals[4] = {rr[0], rr[1], rhr[0], rhr[1]};
+  const int o[4] = {slot(SL_RR, 0), slot(SL_RR, 1), slot(SL_RHR, 0), slot(SL_RHR, 1)};
+  block_store<4>(vals, part, o);
+}
+
+// ------------------------------------------------------------------ PCG
+// Jacobi-preconditioned CG on NR right-hand sides (vectors of type T, dot
+// products in FP64).  Rows with mask[i] >= 0 are removed (their residual,
+// update and matrix-vector product are zero).  One iteration = three kernels:
+//   P1  (first iteration: stopping test on r_0)  q = A p, partial (p, q)
+//   P2  alpha = rho / (p, q), x += alpha p, r -= alpha q, z = D^-1 r, partials (r, z), (r, r)
+//   P3  stopping test on r, beta = rho' / rho, p = z + beta p
+
+template <typename T, int NR, bool MASK>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_init(DLevel L, PcgVecs<T> V, const int32_t* __restrict__ mask, int zero_x0, Scal* sc,
+           double* part) {
+  const int64_t n = L.n;
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double rz[NR], rr[NR], bb[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) rz[d] = rr[d] = bb[d] = 0.0;
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      T ax[NR];
+      if (zero_x0) {
+#pragma unroll
+        for (int d = 0; d < NR; ++d) ax[d] = T(0);
+      } else {
+        spmv_row<T, NR, kLanes>(L.rowptr, L.col, V.val, V.x, n, row, lane, ax);
+      }
+      if (lane == 0) {
+        const bool masked = MASK && mask[row] >= 0;
+        const T dinv = V.invd[row];
+#pragma unroll
+        for (int d = 0; d < NR; ++d) {
+          const int64_t k = d * n + row;
+          const T b = V.b[k];
+          if (zero_x0 || masked) V.x[k] = T(0);
+          const T r = masked ? T(0) : (zero_x0 ? b : b - ax[d]);
+          const T z = masked ? T(0) : dinv * r;
+          V.r[k] = r;
+          V.z[k] = z;
+          V.p[k] = z;
+          rz[d] += (double)r * (double)z;
+          rr[d] += (double)r * (double)r;
+          bb[d] += masked ? 0.0 : (double)b * (double)b;
+        }
+      }
+    }
+  }
+  double vals[3 * NR];
+  int idx[3 * NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    vals[d] = rz[d];
+    idx[d] = slot(SL_RZ, d);
+    vals[NR + d] = rr[d];
+    idx[NR + d] = slot(SL_RR, d);
+    vals[2 * NR + d] = bb[d];
+    idx[2 * NR + d] = slot(SL_BB, d);
+  }
+  block_store<3 * NR>(vals, part, idx);
+  if (blockIdx.x == 0 && threadIdx.x < NR) {
+    Scal& s = sc[threadIdx.x];
+    s.rho[0] = s.rho[1] = 0.0;
+    s.rho_old = s.alpha = s.omega = 1.0;
+    s.bb = 0.0;
+    s.rel = 0.0;
+    s.done_stamp = 0;
+    s.iters = 0;
+    s.status = 0;
+  }
+}
+
+template <typename T, int NR, bool MASK>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_p1(DLevel L, PcgVecs<T> V, const int32_t* __restrict__ mask, Scal* sc, double* part,
+         int nb, int it, double tol, int my_stamp) {
+  const int64_t n = L.n;
+  bool act[NR];
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
+  if (!any) return;
+  if (it == 1) {
+    double s[3 * NR];
+    int idx[3 * NR];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      idx[d] = slot(SL_RZ, d);
+      idx[NR + d] = slot(SL_RR, d);
+      idx[2 * NR + d] = slot(SL_BB, d);
+    }
+    block_sums<3 * NR>(part, nb, idx, s);
+    bool zero_rhs[NR];
+    any = false;
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      zero_rhs[d] = false;
+      if (!act[d]) continue;
+      const double bb = s[2 * NR + d];
+      const double rel = bb > 0.0 ? sqrt(s[NR + d] / bb) : 0.0;
+      const bool nan = !isfinite(bb) || !isfinite(s[NR + d]) || !isfinite(rel);
+      const bool fin = bb == 0.0 || nan || rel <= tol;
+      zero_rhs[d] = bb == 0.0;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[d].bb = bb;
+        sc[d].rel = rel;
+        sc[d].rho[0] = s[d];
+        if (fin) {
+          sc[d].done_stamp = my_stamp;
+          sc[d].iters = 0;
+          sc[d].status = nan ? 2 : 0;
+        }
+      }
+      act[d] = !fin;
+      any |= act[d];
+    }
+    bool any_zero = false;
+#pragma unroll
+    for (int d = 0; d < NR; ++d) any_zero |= zero_rhs[d];
+    if (any_zero) {
+      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < NR; ++d)
+          if (zero_rhs[d]) V.x[d * n + i] = T(0);
+      }
+    }
+    if (!any) return;
+  }
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double pq[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) pq[d] = 0.0;
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      T ap[NR];
+      spmv_row<T, NR, kLanes>(L.rowptr, L.col, V.val, V.p, n, row, lane, ap);
+      if (lane == 0) {
+        const bool masked = MASK && mask[row] >= 0;
+#pragma unroll
+        for (int d = 0; d < NR; ++d) {
+          const T q = masked ? T(0) : ap[d];
+          V.q[d * n + row] = q;
+          pq[d] += (double)V.p[d * n + row] * (double)q;
+        }
+      }
+    }
+  }
+  int idx[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) idx[d] = slot(SL_PQ, d);
+  block_store<NR>(pq, part, idx);
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_p2(int32_t n32, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my_stamp) {
+  const int64_t n = n32;
+  bool act[NR];
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
+  if (!any) return;
+  int idx[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) idx[d] = slot(SL_PQ, d);
+  double pq[NR];
+  block_sums<NR>(part, nb, idx, pq);
+  T alpha[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    const double a = act[d] ? sc[d].rho[(it - 1) & 1] / pq[d] : 0.0;
+    alpha[d] = (T)a;
+    if (act[d] && blockIdx.x == 0 && threadIdx.x == 0) sc[d].alpha = a;
+  }
+  double rz[NR], rr[NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) rz[d] = rr[d] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const T dinv = V.invd[i];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      if (!act[d]) continue;
+      const int64_t k = d * n + i;
+      V.x[k] += alpha[d] * V.p[k];
+      const T r = V.r[k] - alpha[d] * V.q[k];
+      V.r[k] = r;
+      const T z = dinv * r;
+      V.z[k] = z;
+      rz[d] += (double)r * (double)z;
+      rr[d] += (double)r * (double)r;
+    }
+  }
+  double vals[2 * NR];
+  int o[2 * NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    vals[d] = rz[d];
+    o[d] = slot(SL_RZ, d);
+    vals[NR + d] = rr[d];
+    o[NR + d] = slot(SL_RR, d);
+  }
+  block_store<2 * NR>(vals, part, o);
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_p3(int32_t n32, PcgVecs<T> V, Scal* sc, const double* part, int nb, int it, double tol,
+         int my_stamp) {
+  const int64_t n = n32;
+  bool act[NR];
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
+  if (!any) return;
+  double s[2 * NR];
+  int idx[2 * NR];
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    idx[d] = slot(SL_RZ, d);
+    idx[NR + d] = slot(SL_RR, d);
+  }
+  block_sums<2 * NR>(part, nb, idx, s);
+  T beta[NR];
+  any = false;
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    beta[d] = T(0);
+    if (!act[d]) continue;
+    const double rel = sqrt(s[NR + d] / sc[d].bb);
+    const bool nan = !isfinite(rel);
+    const bool fin = nan || rel <= tol;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[d].rel = rel;
+      if (fin) {
+        sc[d].done_stamp = my_stamp;
+        sc[d].iters = it;
+        sc[d].status = nan ? 2 : 0;
+      } else {
+        sc[d].rho[it & 1] = s[d];
+      }
+    }
+    act[d] = !fin;
+    any |= act[d];
+    if (!fin) beta[d] = (T)(s[d] / sc[d].rho[(it - 1) & 1]);
+  }
+  if (!any) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      if (!act[d]) continue;
+      const int64_t k = d * n + i;
+      V.p[k] = V.z[k] + beta[d] * V.p[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ restriction
+// Coarse divergence tested with the coarse shape functions against the fine
+// velocity: (Dbar U)_I = sum over fine triangles e of (int_e div u_h)
+// * (mean of psi_I^c over e).  psi_I^c is linear on e, so its mean is the
+// mean of its values at e's vertices, i.e. of their barycentric coordinates in
+// the coarse ancestor T = e >> 2k.  Those follow from e's index: the children
+// of triangle t are 4t..4t+3, so the base-4 digits of e below T are the child
+// choices (0: corner a, 1: corner b, 2: corner c, 3: middle).  One thread per
+// fine triangle; the 4^k triangles of T are consecutive lanes (4^k <= 64),
+// reduced with a segmented butterfly into tripart[T][3].
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_galerkin(const int32_t* __restrict__ tri, int32_t nt, const double2* __restrict__ xy,
+                    int levels, const double* __restrict__ ut, int64_t stride,
+                    double* __restrict__ tripart) {
+  const int seg = 1 << (2 * levels);
+  const R wscale = R(1.0) / R(3 << levels);
+  for (int e0 = blockIdx.x * blockDim.x; e0 < nt; e0 += gridDim.x * blockDim.x) {
+    const int e = e0 + threadIdx.x;
+    R c[3] = {R(0), R(0), R(0)};
+    if (e < nt) {
+      int B[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+      for (int l = levels - 1; l >= 0; --l) {
+        const int ch = (e >> (2 * l)) & 3;
+        int nbv[3][3];
+        for (int w = 0; w < 3; ++w) {
+          const int ab = B[0][w] + B[1][w], bc = B[1][w] + B[2][w], ca = B[2][w] + B[0][w];
+          if (ch == 0) {
+            nbv[0][w] = 2 * B[0][w]; nbv[1][w] = ab; nbv[2][w] = ca;
+          } else if (ch == 1) {
+            nbv[0][w] = ab; nbv[1][w] = 2 * B[1][w]; nbv[2][w] = bc;
+          } else if (ch == 2) {
+            nbv[0][w] = ca; nbv[1][w] = bc; nbv[2][w] = 2 * B[2][w];
+          } else {
+            nbv[0][w] = ab; nbv[1][w] = bc; nbv[2][w] = ca;
+          }
+        }
+        for (int v = 0; v < 3; ++v)
+          for (int w = 0; w < 3; ++w) B[v][w] = nbv[v][w];
+      }
+      const int v0 = tri[3 * e], v1 = tri[3 * e + 1], v2 = tri[3 * e + 2];
+      const double2 p0 = xy[v0], p1 = xy[v1], p2 = xy[v2];
+      const R b0 = R(p1.y - p2.y), c0 = R(p2.x - p1.x);
+      const R b1 = R(p2.y - p0.y), c1 = R(p0.x - p2.x);
+      const R b2 = R(p0.y - p1.y), c2 = R(p1.x - p0.x);
+      // int_e div u_h = sum_j (b_j u_j + c_j v_j) / 2
+      const R I = R(0.5) * (b0 * R(ut[v0]) + c0 * R(ut[stride + v0]) + b1 * R(ut[v1]) +
+                            c1 * R(ut[stride + v1]) + b2 * R(ut[v2]) + c2 * R(ut[stride + v2]));
+      for (int w = 0; w < 3; ++w) c[w] = I * R(B[0][w] + B[1][w] + B[2][w]) * wscale;
+    }
+    for (int o = seg >> 1; o > 0; o >>= 1)
+      for (int w = 0; w < 3; ++w) c[w] += __shfl_xor(c[w], o, 64);
+    if (e < nt && (e & (seg - 1)) == 0) {
+      const int T = e >> (2 * levels);
+      for (int w = 0; w < 3; ++w) tripart[3 * T + w] = (double)c[w];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_restrict_nodes(int32_t nc, const int32_t* __restrict__ cn_ptr, const int32_t* __restrict__ cn_tri,
+                 const double* __restrict__ tripart, const uint8_t* __restrict__ nat, double scale,
+                 double* __restrict__ b, double* part) {
+  double sum = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+    double dv = 0.0;
+    for (int q = cn_ptr[i]; q < cn_ptr[i + 1]; ++q) {
+      const int e = cn_tri[q];
+      dv += tripart[3 * (e >> 2) + (e & 3)];
+    }
+    const double v = nat[i] ? 0.0 : scale * dv;
+    b[i] = v;
+    sum += v;
+  }
+  const double vals[1] = {sum};
+  const int idx[1] = {0};
+  block_store<1>(vals, part, idx);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_inject(DLevel C, const uint8_t* __restrict__ nat, const double* __restrict__ ut,
+                  int64_t stride, double scale, double* __restrict__ b, double* part) {
+  double sum = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C.n; i += gridDim.x * blockDim.x) {
+    const int beg = C.rowptr[i], end = C.rowptr[i + 1];
+    const double2 pi = C.xy[i];
+    const R ui = R(ut[i]), vi = R(ut[stride + i]);
+    R dv = R(0);
+    for (int s = beg + 1; s < end; ++s) {
+      const int j = C.col[s];
+      const double2 pj = C.xy[j];
+      const R uj = R(ut[j]), vj = R(ut[stride + j]);
+      for (int q = 0; q < 2; ++q) {
+        const int k = C.side[2 * s + q];
+        if (k < 0) continue;
+        const SideGeo g = side_geo(pi, pj, C.xy[k], q == 0 ? 1.0 : -1.0);
+        dv += (R(g.bj) * uj + R(g.cj) * vj) * R(1.0 / 6.0) +
+              (R(g.bi) * ui + R(g.ci) * vi) * R(1.0 / 12.0);
+      }
+    }
+    const double v = nat[i] ? 0.0 : scale * (double)dv;
+    b[i] = v;
+    sum += v;
+  }
+  const double vals[1] = {sum};
+  const int idx[1] = {0};
+  block_store<1>(vals, part, idx);
+}
+
+// v -= sum(part slot 0) / n, or with weights: v -= (sum w v) / (sum w) where
+// part slot 0 holds sum w v and slot 1 sum w.
+__global__ void __launch_bounds__(kBlock)
+k_remove_mean(int32_t n, double* __restrict__ v, const double* part, int nb, int weighted) {
+  const int idx[2] = {0, kNbMax};
+  double s[2];
+  block_sums<2>(part, nb, idx, s);
+  const double mean = weighted ? s[0] / s[1] : s[0] / (double)n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    v[i] -= mean;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_weighted_sums(int32_t n, const double* __restrict__ v, const double* __restrict__ w,
+                double* part) {
+  double a = 0.0, b = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    a += w[i] * v[i];
+    b += w[i];
+  }
+  const double vals[2] = {a, b};
+  const int idx[2] = {0, kNbMax};
+  block_store<2>(vals, part, idx);
+}
+
+// ------------------------------------------------------------------ prolongation
+// Every fine node is the coarse P1 function evaluated there: with the coarse
+// triangle T holding the node and its barycentric coordinates n/2^k,
+// phi_f = (n0 phi[T0] + n1 phi[T1] + n2 phi[T2]) / 2^k (dyadic weights, exact).
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(int32_t nf, const int32_t* __restrict__ pcode, const int32_t* __restrict__ tri_c,
+          int levels, const double* __restrict__ phic, double* __restrict__ phif) {
+  const int den = 1 << levels;
+  const R inv = R(1.0) / R(den);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
+    const int2 code = reinterpret_cast<const int2*>(pcode)[i];
+    const int T = code.x;
+    const int n1 = code.y & 0xffff, n2 = code.y >> 16, n0 = den - n1 - n2;
+    const R f = R(n0) * R(phic[tri_c[3 * T]]) + R(n1) * R(phic[tri_c[3 * T + 1]]) +
+                R(n2) * R(phic[tri_c[3 * T + 2]]);
+    phif[i] = (double)(f * inv);
+  }
+}
+
+// ------------------------------------------------------------------ correction
+// rhs_vel = -(2/3) dt G phi_f on non-Dirichlet rows (0 on Dirichlet rows),
+// rhs_rot = -nu D U~ (rotational form only).
+__global__ void __launch_bounds__(kBlock)
+k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double nu, int chi,
+              const double* __restrict__ phi, const double* __restrict__ ut,
+              double* __restrict__ rhs_vel, double* __restrict__ rhs_rot) {
+  const int64_t n = L.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int beg = L.rowptr[i], end = L.rowptr[i + 1];
+    const double2 pi = L.xy[i];
+    const double phii = phi[i];
+    const double ui = ut[i], vi = ut[n + i];
+    double gx = 0.0, gy = 0.0, dv = 0.0;
+    for (int s = beg + 1; s < end; ++s) {
+      const int j = L.col[s];
+      const double2 pj = L.xy[j];
+      const double ph = phi[j] + 0.5 * phii;
+      const double uj = chi ? ut[j] : 0.0, vj = chi ? ut[n + j] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = L.side[2 * s + q];
+        if (k < 0) continue;
+        const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
+        gx += g.bi * ph;
+        gy += g.ci * ph;
+        if (chi) dv += (g.bj * uj + g.cj * vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
+      }
+    }
+    const bool dir = dir_index[i] >= 0;
+    rhs_vel[i] = dir ? 0.0 : (dt / 9.0) * gx;
+    rhs_vel[n + i] = dir ? 0.0 : (dt / 9.0) * gy;
+    if (chi) rhs_rot[i] = -nu * dv;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restrict__ du,
+               const double* p_in, const double* __restrict__ phi, const double* __restrict__ dp,
+               double* __restrict__ u_out, double* p_out) {
+  const int64_t n = n32;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    u_out[i] = ut[i] + du[i];
+    u_out[n + i] = ut[n + i] + du[n + i];
+    const double pv = p_in[i] + phi[i];
+    p_out[i] = dp ? pv + dp[i] : pv;
+  }
+}
+
+// ------------------------------------------------------------------ small ops
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+__global__ void k_zero_masked(double* __restrict__ x, const uint8_t* __restrict__ nat, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (nat[i]) x[i] = 0.0;
+}
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+__global__ void k_axpy_f32(const float* __restrict__ d, double* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += (double)d[i];
+}
+
+// r = b - K x in FP64 (and its FP32 copy), partials (r, r) and (b, b)
+__global__ void __launch_bounds__(kBlock)
+k_residual64(DLevel C, const double* __restrict__ K, const double* __restrict__ b,
+             const double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
+             double* part) {
+  const int64_t n = C.n;
+  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  double rr = 0.0, bb = 0.0;
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int row = base + threadIdx.x / kLanes;
+    if (row < n) {
+      double ax[1];
+      spmv_row<double, 1, kLanes>(C.rowptr, C.col, K, x, n, row, lane, ax);
+      if (lane == 0) {
+        const double bv = b[row];
+        const double rv = bv - ax[0];
+        r[row] = rv;
+        r32[row] = (float)rv;
+        rr += rv * rv;
+        bb += bv * bv;
+      }
+    }
+  }
+  const double vals[2] = {rr, bb};
+  const int idx[2] = {slot(SL_RR, 0), slot(SL_BB, 0)};
+  block_store<2>(vals, part, idx);
+}
+
+// one block: relative residual of the outer refinement loop into sc[0]
+__global__ void k_reduce_check(const double* part, int nb, double tol, Scal* sc, int outer) {
+  const int idx[2] = {slot(SL_RR, 0), slot(SL_BB, 0)};
+  double s[2];
+  block_sums<2>(part, nb, idx, s);
+  if (threadIdx.x == 0) {
+    const double rel = s[1] > 0.0 ? sqrt(s[0] / s[1]) : 0.0;
+    const bool nan = !isfinite(s[0]) || !isfinite(s[1]) || !isfinite(rel);
+    sc[0].bb = s[1];
+    sc[0].rel = rel;
+    sc[0].status = nan ? 2 : 0;
+    sc[0].done_stamp = (nan || rel <= tol || s[1] == 0.0) ? outer + 1 : 0;
+  }
+}
+
+inline int grid_for(int64_t units, int per_block, int cap = 4096) {
+  int64_t g = (units + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_mass_assemble(const DLevel& L, const int32_t* dir_index, double* Mval,
+                          double* invd_full, double* invd_int, hipStream_t s) {
+  k_mass_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, dir_index, Mval, invd_full, invd_int);
+}
+
+void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
+                            double* Dxval, double* Dyval, double* invd, float* invd32,
+                            double* lumped, hipStream_t s) {
+  k_coarse_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, nat, Kval, Kval32, Dxval, Dyval,
+                                                             invd, invd32, lumped);
+}
+
+void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double dt, double nu,
+                              const double* u_prev, const double* u, const double* p,
+                              const double* u_dir, int32_t n_dir, const double* f,
+                              double* Aval, double* invdA, double* rhs, double* x0,
+                              hipStream_t s, hipEvent_t* ev) {
+  if (ev) (void)hipEventRecord(ev[0], s);
+  k_momentum_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(
+      L, dir_index, dt, dt * nu, u_prev, u, p, u_dir, n_dir, f, Aval, invdA, rhs, x0);
+  if (ev) (void)hipEventRecord(ev[1], s);
+}
+
+void launch_bicg_init(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
+                      double* part, int nb, hipStream_t s) {
+  k_bicg_init<<<nb, kBlock, 0, s>>>(L, Aval, V, sc, part);
+}
+
+void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
+                      double* part, int nb, int it, double tol, bool check_only,
+                      hipStream_t s, hipEvent_t* ev) {
+  k_bicg_b1<<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, tol, stamp(it, 1), check_only ? 1 : 0);
+  if (check_only) return;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  k_bicg_b2<<<nb, kBlock, 0, s>>>(L, Aval, V, sc, part, stamp(it, 2));
+  if (ev) (void)hipEventRecord(ev[1], s);
+  k_bicg_b3<<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, stamp(it, 3));
+  k_bicg_b4<<<nb, kBlock, 0, s>>>(L, Aval, V, sc, part, nb, it, tol, stamp(it, 4));
+  k_bicg_b5<<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, stamp(it, 5));
+}
+
+template <typename T, int NR>
+void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, bool zero_x0,
+                     Scal* sc, double* part, int nb, hipStream_t s) {
+  if (mask)
+    k_pcg_init<T, NR, true><<<nb, kBlock, 0, s>>>(L, V, mask, zero_x0 ? 1 : 0, sc, part);
+  else
+    k_pcg_init<T, NR, false><<<nb, kBlock, 0, s>>>(L, V, mask, zero_x0 ? 1 : 0, sc, part);
+}
+
+template <typename T, int NR>
+void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, Scal* sc,
+                     double* part, int nb, int it, double tol, bool check_only, hipStream_t s,
+                     hipEvent_t* ev) {
+  (void)check_only;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (mask)
+    k_pcg_p1<T, NR, true><<<nb, kBlock, 0, s>>>(L, V, mask, sc, part, nb, it, tol, stamp(it, 1));
+  else
+    k_pcg_p1<T, NR, false><<<nb, kBlock, 0, s>>>(L, V, mask, sc, part, nb, it, tol, stamp(it, 1));
+  if (ev) (void)hipEventRecord(ev[1], s);
+  k_pcg_p2<T, NR><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, stamp(it, 2));
+  k_pcg_p3<T, NR><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, tol, stamp(it, 3));
+}
+
+template void launch_pcg_init<double, 1>(const DLevel&, const PcgVecs<double>&, const int32_t*,
+                                         bool, Scal*, double*, int, hipStream_t);
+template void launch_pcg_init<double, 2>(const DLevel&, const PcgVecs<double>&, const int32_t*,
+                                         bool, Scal*, double*, int, hipStream_t);
+template void launch_pcg_init<float, 1>(const DLevel&, const PcgVecs<float>&, const int32_t*,
+                                        bool, Scal*, double*, int, hipStream_t);
+template void launch_pcg_iter<double, 1>(const DLevel&, const PcgVecs<double>&, const int32_t*,
+                                         Scal*, double*, int, int, double, bool, hipStream_t,
+                                         hipEvent_t*);
+template void launch_pcg_iter<double, 2>(const DLevel&, const PcgVecs<double>&, const int32_t*,
+                                         Scal*, double*, int, int, double, bool, hipStream_t,
+                                         hipEvent_t*);
+template void launch_pcg_iter<float, 1>(const DLevel&, const PcgVecs<float>&, const int32_t*,
+                                        Scal*, double*, int, int, double, bool, hipStream_t,
+                                        hipEvent_t*);
+
+void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
+                              int levels, const double* ut, int64_t stride, double* tripart,
+                              bool fp32, hipStream_t s) {
+  const int g = grid_for(n_fine_tris, kBlock);
+  if (fp32)
+    k_restrict_galerkin<float><<<g, kBlock, 0, s>>>(tri_f, n_fine_tris, xy_f, levels, ut, stride, tripart);
+  else
+    k_restrict_galerkin<double><<<g, kBlock, 0, s>>>(tri_f, n_fine_tris, xy_f, levels, ut, stride, tripart);
+}
+
+void launch_restrict_nodes(int32_t n_c, const int32_t* cn_ptr, const int32_t* cn_tri,
+                           const double* tripart, const uint8_t* nat, double scale, double* b,
+                           double* part, int nb, hipStream_t s) {
+  k_restrict_nodes<<<nb, kBlock, 0, s>>>(n_c, cn_ptr, cn_tri, tripart, nat, scale, b, part);
+}
+
+void launch_restrict_inject(const DLevel& C, const uint8_t* nat, const double* ut,
+                            int64_t stride, double scale, double* b, double* part, int nb,
+                            bool fp32, hipStream_t s) {
+  if (fp32)
+    k_restrict_inject<float><<<nb, kBlock, 0, s>>>(C, nat, ut, stride, scale, b, part);
+  else
+    k_restrict_inject<double><<<nb, kBlock, 0, s>>>(C, nat, ut, stride, scale, b, part);
+}
+
+void launch_remove_mean(int32_t n, double* v, const double* part, int nb, const double* weights,
+                        hipStream_t s) {
+  k_remove_mean<<<nb, kBlock, 0, s>>>(n, v, part, nb, weights ? 1 : 0);
+}
+
+void launch_weighted_sums(int32_t n, const double* v, const double* w, double* part, int nb,
+                          hipStream_t s) {
+  k_weighted_sums<<<nb, kBlock, 0, s>>>(n, v, w, part);
+}
+
+void launch_prolong(int32_t n_f, int32_t n_c, const int32_t* pcode, const int32_t* tri_c,
+                    int levels, const double* phic, double* phif, bool fp32, hipStream_t s) {
+  (void)n_c;
+  const int g = grid_for(n_f, kBlock);
+  if (fp32)
+    k_prolong<float><<<g, kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
+  else
+    k_prolong<double><<<g, kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
+}
+
+void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
+                        int chi, const double* phi_f, const double* ut, double* rhs_vel,
+                        double* rhs_rot, hipStream_t s) {
+  k_correct_rhs<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, dir_index, dt, nu, chi, phi_f, ut,
+                                                         rhs_vel, rhs_rot);
+}
+
+void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
+                         const double* phi_f, const double* dp, double* u_out, double* p_out,
+                         hipStream_t s) {
+  k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, dp, u_out, p_out);
+}
+
+void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
+  k_copy<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, dst, n);
+}
+void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s) {
+  k_zero_masked<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, nat, n);
+}
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  k_to_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, dst, n);
+}
+void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s) {
+  k_axpy_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(d, x, n);
+}
+void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,
+                       double* r, float* r32, double* part, int nb, hipStream_t s) {
+  k_residual64<<<nb, kBlock, 0, s>>>(C, Kval, b, x, r, r32, part);
+}
+void launch_reduce_check(const double* part, int nb, double tol, Scal* sc, int outer,
+                         hipStream_t s) {
+  k_reduce_check<<<1, kBlock, 0, s>>>(part, nb, tol, sc, outer);
+}
+
+}  // namespace cgp

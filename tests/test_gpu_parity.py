@@ -1,0 +1,264 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+FP64 path bar: relative Euclidean difference <= 1e-10 per field (the
+published bound for this method's FP64 path); integer/index work bit-exact.
+Each case prints its name, sizes and seed before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from oracle.cgp import build as build_oracle
+from workloads import get_workload, unit_square, channel_cylinder, disc, NATURAL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1812_00185_amd import CGP  # noqa: E402
+
+TOL64 = 1e-10
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def make(w, **kw):
+    print(f"\n[case] {w.name} coarse_n={w.coarse_n} k={w.levels} chi={w.chi} "
+          f"prec={w.precision} restrict={w.restrict} {kw}", flush=True)
+    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
+            precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
+            pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol,
+            max_iter=w.max_iter, **kw)
+    o = build_oracle(w)
+    return g, o
+
+
+def tg(n, k, **kw):
+    return get_workload("tg33_k1").with_(coarse_n=n, levels=k, **kw)
+
+
+def cavity(n, k, **kw):
+    return get_workload("cavity257_k0_chi0_fp64").with_(coarse_n=n, levels=k, **kw)
+
+
+def channel(k=1, h=0.05, **kw):
+    return get_workload("channel_k2").with_(levels=k, channel_h=h, precision=0, **kw)
+
+
+def start(w, o, g, seed=None):
+    Um, U0, P0 = w.initial_fields(o.fine_xy)
+    if seed is not None:   # perturbed state so that every term of the step is exercised
+        rng = np.random.default_rng(seed)
+        U0 = U0 + 0.05 * rng.standard_normal(U0.shape)
+        Um = Um + 0.05 * rng.standard_normal(Um.shape)
+        P0 = P0 + 0.05 * rng.standard_normal(P0.shape)
+    return Um, U0, P0
+
+
+# ----------------------------------------------------------------- hierarchy (bit-exact)
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_fine_nodes_bit_exact(k):
+    w = channel(k=k, h=0.08)
+    g, o = make(w)
+    assert np.array_equal(g.fine_xy, o.fine_xy)
+    assert np.array_equal(g.dirichlet_nodes, o.dir)
+
+
+# ----------------------------------------------------------------- per-call parity
+CASES = [
+    ("tg", lambda: tg(9, 1)),
+    ("tg_k3_ragged", lambda: tg(6, 3)),
+    ("cavity_k2", lambda: cavity(17, 2, chi=1)),
+    ("channel_k1", lambda: channel(1, 0.05, chi=1)),
+    ("tg_k0", lambda: tg(9, 0)),
+]
+
+
+@pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
+def test_momentum_parity(name, wf):
+    w = wf()
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g, seed=1)
+    uD = w.dirichlet_values(o.fine_xy[o.dir], w.dt)
+    Ut_o, its_o = o.momentum(Um, U0, P0, uD)
+    Ut_g, st = g.momentum(g.to_device(Um), g.to_device(U0), g.to_device(P0), g.to_device(uD))
+    torch.cuda.synchronize()
+    assert rel(np_(Ut_g), Ut_o) <= TOL64
+    assert [s["iters"] for s in st] == its_o
+    assert all(s["converged"] for s in st)
+
+
+@pytest.mark.parametrize("mode", ["galerkin", "inject"])
+@pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
+def test_restrict_parity(name, wf, mode):
+    w = wf().with_(restrict=mode)
+    g, o = make(w)
+    rng = np.random.default_rng(2)
+    Ut = rng.standard_normal((2, o.nf))
+    b_o = o.restrict_rhs(Ut)
+    b_g = np_(g.restrict(g.to_device(Ut)))
+    assert rel(b_g, b_o) <= 1e-12
+
+
+@pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
+def test_prolong_parity(name, wf):
+    w = wf()
+    g, o = make(w)
+    rng = np.random.default_rng(3)
+    phic = rng.standard_normal(o.nc)
+    f_o = o.hier.prolong(phic)
+    f_g = np_(g.prolong(g.to_device(phic)))
+    assert rel(f_g, f_o) <= 1e-15
+    np.testing.assert_array_equal(f_g[: o.nc], phic)
+
+
+@pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
+def test_pcg_parity(name, wf):
+    w = wf().with_(pcg_tol=1e-10)
+    g, o = make(w)
+    rng = np.random.default_rng(4)
+    Ut = rng.standard_normal((2, o.nf))
+    b = o.restrict_rhs(Ut)
+    guess = rng.standard_normal(o.nc) * 0.1
+    guess[o.nat_c] = 0.0
+    phi_o, info = o.poisson(b, guess)
+    phi_g = g.to_device(guess)
+    st = g.pcg_solve(g.to_device(b), phi_g)
+    torch.cuda.synchronize()
+    assert abs(st["iters"] - info.iters) <= 1
+    assert st["converged"]
+    assert rel(np_(phi_g), phi_o) <= TOL64
+
+
+@pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
+def test_correct_parity(name, wf):
+    w = wf()
+    g, o = make(w)
+    rng = np.random.default_rng(5)
+    Ut = rng.standard_normal((2, o.nf))
+    Ut[:, o.dir] = w.dirichlet_values(o.fine_xy[o.dir], w.dt)
+    phi_f = o.hier.prolong(rng.standard_normal(o.nc))
+    P = rng.standard_normal(o.nf)
+    U_o, its = o.velocity_correction(Ut, phi_f)
+    P_o, pits = o.pressure_update(P, phi_f, Ut)
+    U_g, P_g, st = g.correct(g.to_device(Ut), g.to_device(phi_f), g.to_device(P))
+    torch.cuda.synchronize()
+    assert rel(np_(U_g), U_o) <= TOL64
+    assert rel(np_(P_g), P_o) <= TOL64
+    assert [s["iters"] for s in st[:2]] == its
+    if w.chi:
+        assert st[2]["iters"] == pits
+
+
+# ----------------------------------------------------------------- whole steps
+def run_both(w, steps, seed=None):
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g, seed)
+    so = o.initial_state(Um, U0, P0)
+    sg = g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    worst = 0.0
+    for n in range(steps):
+        uD = w.dirichlet_values(xyd, (n + 1) * w.dt)
+        r = o.step(so, uD)
+        so = r.state
+        st = g.step(sg, g.to_device(uD), stats=True)
+        assert st["poisson"]["converged"]
+        assert abs(st["poisson"]["iters"] - r.stats["pcg_iters"]) <= 1
+        du = rel(np_(sg.U), so.U)
+        dp = rel(np_(sg.P), so.P)
+        worst = max(worst, du, dp)
+    return g, o, sg, so, worst
+
+
+def test_step_tg33_k1_100_steps():
+    """The 33x33 / 17x17 Taylor-Green workload end to end (FP64, tol 1e-10)."""
+    w = get_workload("tg33_k1")
+    g, o, sg, so, worst = run_both(w, w.steps)
+    assert worst <= TOL64, worst
+    np.testing.assert_allclose(np_(sg.phi_hist[0]), so.phi_hist[0], rtol=0,
+                               atol=TOL64 * np.abs(so.phi_hist[0]).max())
+
+
+@pytest.mark.parametrize("name,wf,steps", [
+    ("cavity_k1_chi1", lambda: cavity(17, 1, chi=1), 20),
+    ("cavity_k3_chi0", lambda: cavity(9, 3, chi=0), 10),
+    ("channel_k1_chi1", lambda: channel(1, 0.05, chi=1), 10),
+    ("channel_k2_inject", lambda: channel(2, 0.08, chi=0, restrict="inject"), 5),
+    ("disc_k2", lambda: tg(5, 2, chi=1), 10),
+])
+def test_step_trajectories(name, wf, steps):
+    w = wf()
+    _, _, _, _, worst = run_both(w, steps)
+    assert worst <= TOL64, worst
+
+
+def test_step_matches_composed_calls():
+    """cgp_project_step equals momentum -> restrict -> pcg -> prolong -> correct."""
+    w = tg(9, 1, chi=1)
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g, seed=7)
+    uD = g.to_device(w.dirichlet_values(o.fine_xy[o.dir], w.dt))
+    s = g.new_state(Um, U0, P0)
+    Ut, _ = g.momentum(g.to_device(Um), g.to_device(U0), g.to_device(P0), uD)
+    b = g.restrict(Ut)
+    phi = g.zeros(g.nc)
+    g.pcg_solve(b, phi)
+    phif = g.prolong(phi)
+    U1, P1, _ = g.correct(Ut, phif, g.to_device(P0))
+    g.step(s, uD)
+    torch.cuda.synchronize()
+    assert torch.equal(s.U, U1) and torch.equal(s.P, P1)
+    assert torch.equal(s.phi_hist[0], phi)
+
+
+# ----------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("name,wf", [
+    ("tg_k2", lambda: tg(17, 2, chi=1)),
+    ("cavity_k1", lambda: cavity(33, 1, chi=0)),
+    ("channel_k1", lambda: channel(1, 0.05, chi=1)),
+])
+def test_mixed_precision_vs_fp64_oracle(name, wf):
+    """Mixed path: FP64 true residual <= tol, fields within 1e-6 of FP64."""
+    w = wf().with_(precision=1, pcg_tol=1e-8)
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g)
+    so = o.initial_state(Um, U0, P0)
+    sg = g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    for n in range(10):
+        uD = w.dirichlet_values(xyd, (n + 1) * w.dt)
+        r = o.step(so, uD)
+        so = r.state
+        st = g.step(sg, g.to_device(uD), stats=True)
+        assert st["poisson"]["converged"] and st["poisson"]["rel_res"] <= w.pcg_tol
+        assert rel(np_(sg.U), so.U) <= 1e-6
+        assert rel(np_(sg.P), so.P) <= 1e-6
+
+
+# ----------------------------------------------------------------- failure paths
+def test_not_converged_and_nan_status():
+    from paper_1812_00185_amd import _native as N
+
+    w = tg(9, 1).with_(max_iter=2)
+    g, o = make(w)
+    rng = np.random.default_rng(8)
+    b = g.to_device(o.restrict_rhs(rng.standard_normal((2, o.nf))))
+    phi = g.zeros(g.nc)
+    st = g.pcg_solve(b, phi)
+    assert not st["converged"] and st["iters"] == 2
+    bad = b.clone()
+    bad[3] = float("nan")
+    with pytest.raises(N.CGPError) as e:
+        g.pcg_solve(bad, g.zeros(g.nc))
+    assert e.value.code == N.CGP_ERR_NAN
