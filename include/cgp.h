@@ -167,7 +167,8 @@ int cgp_assemble(cgp_ctx* ctx, void* workspace, size_t bytes, void* stream);
 /* Step 1 (Eq. 21): solves
  *   (3/2 M + dt N(w) + dt nu K) U~ = -dt G P + dt M F + 2 M U - 1/2 M U_prev,
  *   w = 2 U - U_prev, with U~ = u_dir at the Dirichlet nodes (Eq. 10),
- * by right-Jacobi-preconditioned BiCGSTAB from U~ = w, stopping when
+ * by right-Jacobi-preconditioned BiCGSTAB from U~ = w (u_dir at the
+ * Dirichlet nodes), stopping when
  * ||r|| <= mom_tol ||rhs||.  u_prev, u, u_tilde: device [2][N_f]; p device
  * [N_f]; u_dir device [2][n_dirichlet]; f device [2][N_f] or NULL (no
  * forcing).  u_tilde must not alias the inputs.  stats may be NULL; when

@@ -31,8 +31,10 @@ to (U^{n+1}, P^{n+1}, Phi_c^{n+1}):
 
 Readings where the paper is silent:
   * the linear solvers are Jacobi-PCG (symmetric) and Jacobi-BiCGSTAB
-    (momentum, initial guess w) with ||r|| <= tol ||b||; the Poisson solve
-    starts from the previous step's Phi_c (zero at the first step);
+    (momentum) with ||r|| <= tol ||b||; the momentum solve starts from w with
+    the Dirichlet values of Eq. 10 imposed (so the Dirichlet rows' residual is
+    zero throughout and the shadow residual lives on the free rows), the
+    Poisson solve from the previous step's Phi_c (zero at the first step);
   * when no boundary is natural the coarse Poisson problem is pure Neumann:
     the right-hand side is projected onto mean zero (Euclidean mean) before the
     solve, and the lumped-mass-weighted mean of Phi_c is removed after it;
@@ -134,10 +136,13 @@ class OracleCGP:
 
     def momentum(self, U_prev, U, P, uD, F=None):
         A, rhs, w = self.momentum_system(U_prev, U, P, uD, F)
+        # initial guess: w, with the Dirichlet values of Eq. 10 imposed
+        x0 = w.copy()
+        x0[:, self.dir] = uD
         Ut = np.empty_like(rhs)
         its = []
         for d in range(2):
-            Ut[d], info = bicgstab_jacobi(A, rhs[d], x0=w[d], tol=self.mom_tol,
+            Ut[d], info = bicgstab_jacobi(A, rhs[d], x0=x0[d], tol=self.mom_tol,
                                           maxit=self.max_iter)
             its.append(info.iters)
         return Ut, its

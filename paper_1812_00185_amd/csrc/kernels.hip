@@ -215,8 +215,13 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       A[beg] = 1.0;
       for (int s = beg + 1; s < end; ++s) A[s] = 0.0;
       invdA[i] = 1.0;
-      rhs[i] = udir[di];
-      rhs[n + i] = udir[ndir + di];
+      const double gx = udir[di], gy = udir[ndir + di];
+      rhs[i] = gx;
+      rhs[n + i] = gy;
+      // the initial guess satisfies the Dirichlet condition exactly, so these
+      // rows keep a zero residual and BiCGSTAB works on the free rows only
+      x0[i] = gx;
+      x0[n + i] = gy;
       continue;
     }
     const double2 pi = L.xy[i];

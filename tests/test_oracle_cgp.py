@@ -151,3 +151,20 @@ def test_injection_reading_loses_k_invariance():
         ex = w.exact(ora.fine_xy, 20 * w.dt)
         e.append(ora.l2(st.U - ex[0]) / ora.l2(ex[0]))
     assert e[1] > 5 * e[0], e
+
+
+def test_impulsive_start_converges():
+    """Lid-driven cavity from rest: every solve converges (the momentum guess
+    carries the lid velocity, Eq. 10) and the lid drives the flow."""
+    w = get_workload("cavity257_k0_chi0_fp64").with_(coarse_n=9, levels=1, chi=1)
+    ora = build(w)
+    st = ora.initial_state(*w.initial_fields(ora.fine_xy))
+    for n in range(5):
+        r = ora.step(st, w.dirichlet_values(ora.fine_xy[ora.dir], (n + 1) * w.dt))
+        st = r.state
+        assert r.stats["pcg_converged"]
+        assert max(r.stats["mom_iters"]) < 100
+        assert np.all(np.isfinite(st.U)) and np.all(np.isfinite(st.P))
+    top = np.isclose(ora.fine_xy[:, 1], 1.0) & (ora.fine_xy[:, 0] > 0) & (ora.fine_xy[:, 0] < 1)
+    np.testing.assert_array_equal(st.U[0][top], 1.0)
+    assert np.abs(st.U).max() <= 1.0 + 1e-12
