@@ -180,7 +180,9 @@ int cgp_momentum(cgp_ctx* ctx, const double* u_prev, const double* u, const doub
 /* Steps 2-3, right-hand side (Eqs. 22-23): b_c = -(3/(2 dt)) Dbar U~ with
  * Dbar the coarse divergence selected by restrict_mode; zero at the coarse
  * phi = 0 nodes (Eq. 14); projected onto zero mean when no boundary is
- * natural.  u_tilde device [2][N_f], b_c device [N_c]. */
+ * natural.  Evaluated in FP64 on both precision paths (a divergence of a
+ * nearly solenoidal field is a sum of nearly cancelling terms).  u_tilde
+ * device [2][N_f], b_c device [N_c]. */
 int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream);
 
 /* Step 3 (Eq. 23): solves K_c phi_c = b_c (K_c the coarse stiffness matrix,
@@ -194,8 +196,10 @@ int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stat
                   void* stream);
 
 /* Step 4 (Eq. 24): phi_f = P phi_c, linear interpolation applied k times
- * (each fine node is the coarse P1 function evaluated there).  phi_c device
- * [N_c], phi_f device [N_f]. */
+ * (each fine node is the coarse P1 function evaluated there; dyadic weights).
+ * FP64 on both precision paths: the velocity correction differentiates
+ * phi_f, which would amplify FP32 rounding of a large increment.
+ * phi_c device [N_c], phi_f device [N_f]. */
 int cgp_prolong(cgp_ctx* ctx, const double* phi_c, double* phi_f, void* stream);
 
 /* Steps 5-6 (Eqs. 25-26, Sect. 2.3): M dU = -(2/3) dt G phi_f on the

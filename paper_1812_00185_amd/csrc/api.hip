@@ -242,16 +242,16 @@ int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
 }
 
 int run_restrict(cgp_ctx* c, const double* ut, double* b, hipStream_t s) {
+  // The restriction evaluates a divergence: for a nearly solenoidal U~ a sum of
+  // nearly cancelling terms, so it runs in FP64 on both precision paths.
   const cgp_problem& P = c->prob;
-  const bool fp32 = P.precision == CGP_MIXED;
   const double scale = -1.5 / P.dt;
   if (P.restrict_mode == CGP_RESTRICT_GALERKIN) {
-    cgp::launch_restrict_galerkin(c->tri_f, c->tf, c->F.xy, P.levels, ut, c->nf, c->tripart,
-                                  fp32, s);
+    cgp::launch_restrict_galerkin(c->tri_f, c->tf, c->F.xy, P.levels, ut, c->nf, c->tripart, s);
     cgp::launch_restrict_nodes(c->nc, c->cn_ptr, c->cn_tri, c->tripart, c->nat_c, scale, b,
                                c->part, c->nb_c, s);
   } else {
-    cgp::launch_restrict_inject(c->C, c->nat_c, ut, c->nf, scale, b, c->part, c->nb_c, fp32, s);
+    cgp::launch_restrict_inject(c->C, c->nat_c, ut, c->nf, scale, b, c->part, c->nb_c, s);
   }
   if (c->h.n_nat_c == 0) cgp::launch_remove_mean(c->nc, b, c->part, c->nb_c, nullptr, s);
   return CGP_OK;
@@ -530,8 +530,7 @@ int cgp_pcg_solve(cgp_ctx* c, const double* b, double* phi, cgp_solve_stats* st,
 int cgp_prolong(cgp_ctx* c, const double* phic, double* phif, void* stream) {
   if (int rc = check_ready(c)) return rc;
   if (!phic || !phif) return fail(CGP_ERR_INVALID, "null device pointer");
-  cgp::launch_prolong(c->nf, c->nc, c->pcode, c->tri_c, c->prob.levels, phic, phif,
-                      c->prob.precision == CGP_MIXED, as_stream(stream));
+  cgp::launch_prolong(c->nf, c->pcode, c->tri_c, c->prob.levels, phic, phif, as_stream(stream));
   HIPCHK(hipGetLastError());
   return CGP_OK;
 }
@@ -563,8 +562,7 @@ int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double
   cgp::launch_copy(guess ? guess : S->phi_hist[0], phi_new, c->nc, s);
   rc = worst(rc, run_pcg(c, c->bc, phi_new, &T->poisson, s));
   if (rc < 0) return rc;
-  cgp::launch_prolong(c->nf, c->nc, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f,
-                      c->prob.precision == CGP_MIXED, s);
+  cgp::launch_prolong(c->nf, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f, s);
   cgp_solve_stats cs[3];
   rc = worst(rc, run_correct(c, c->ut, c->phi_f, S->p, S->u_prev, S->p, cs, s));
   if (rc < 0) return rc;

@@ -88,19 +88,19 @@ void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, 
 // ---------------------------------------------------------------- restriction / prolongation
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
                               int levels, const double* ut, int64_t stride, double* tripart,
-                              bool fp32, hipStream_t s);
+                              hipStream_t s);
 void launch_restrict_nodes(int32_t n_c, const int32_t* cn_ptr, const int32_t* cn_tri,
                            const double* tripart, const uint8_t* nat, double scale, double* b,
                            double* part, int nb, hipStream_t s);
 void launch_restrict_inject(const DLevel& C, const uint8_t* nat, const double* ut,
                             int64_t stride, double scale, double* b, double* part, int nb,
-                            bool fp32, hipStream_t s);
+                            hipStream_t s);
 void launch_remove_mean(int32_t n, double* v, const double* part, int nb, const double* weights,
                         hipStream_t s);
 void launch_weighted_sums(int32_t n, const double* v, const double* w, double* part, int nb,
                           hipStream_t s);
-void launch_prolong(int32_t n_f, int32_t n_c, const int32_t* pcode, const int32_t* tri_c,
-                    int levels, const double* phic, double* phif, bool fp32, hipStream_t s);
+void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int levels,
+                    const double* phic, double* phif, hipStream_t s);
 
 // ---------------------------------------------------------------- correction
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,

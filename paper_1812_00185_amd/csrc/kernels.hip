@@ -792,16 +792,15 @@ k_pcg_p3(int32_t n32, PcgVecs<T> V, Scal* sc, const double* part, int nb, int it
 // choices (0: corner a, 1: corner b, 2: corner c, 3: middle).  One thread per
 // fine triangle; the 4^k triangles of T are consecutive lanes (4^k <= 64),
 // reduced with a segmented butterfly into tripart[T][3].
-template <typename R>
 __global__ void __launch_bounds__(kBlock)
 k_restrict_galerkin(const int32_t* __restrict__ tri, int32_t nt, const double2* __restrict__ xy,
                     int levels, const double* __restrict__ ut, int64_t stride,
                     double* __restrict__ tripart) {
   const int seg = 1 << (2 * levels);
-  const R wscale = R(1.0) / R(3 << levels);
+  const double wscale = 1.0 / (double)(3 << levels);
   for (int e0 = blockIdx.x * blockDim.x; e0 < nt; e0 += gridDim.x * blockDim.x) {
     const int e = e0 + threadIdx.x;
-    R c[3] = {R(0), R(0), R(0)};
+    double c[3] = {0.0, 0.0, 0.0};
     if (e < nt) {
       int B[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
       for (int l = levels - 1; l >= 0; --l) {
@@ -824,19 +823,19 @@ k_restrict_galerkin(const int32_t* __restrict__ tri, int32_t nt, const double2* 
       }
       const int v0 = tri[3 * e], v1 = tri[3 * e + 1], v2 = tri[3 * e + 2];
       const double2 p0 = xy[v0], p1 = xy[v1], p2 = xy[v2];
-      const R b0 = R(p1.y - p2.y), c0 = R(p2.x - p1.x);
-      const R b1 = R(p2.y - p0.y), c1 = R(p0.x - p2.x);
-      const R b2 = R(p0.y - p1.y), c2 = R(p1.x - p0.x);
+      const double b0 = p1.y - p2.y, c0 = p2.x - p1.x;
+      const double b1 = p2.y - p0.y, c1 = p0.x - p2.x;
+      const double b2 = p0.y - p1.y, c2 = p1.x - p0.x;
       // int_e div u_h = sum_j (b_j u_j + c_j v_j) / 2
-      const R I = R(0.5) * (b0 * R(ut[v0]) + c0 * R(ut[stride + v0]) + b1 * R(ut[v1]) +
-                            c1 * R(ut[stride + v1]) + b2 * R(ut[v2]) + c2 * R(ut[stride + v2]));
-      for (int w = 0; w < 3; ++w) c[w] = I * R(B[0][w] + B[1][w] + B[2][w]) * wscale;
+      const double I = 0.5 * (b0 * ut[v0] + c0 * ut[stride + v0] + b1 * ut[v1] +
+                              c1 * ut[stride + v1] + b2 * ut[v2] + c2 * ut[stride + v2]);
+      for (int w = 0; w < 3; ++w) c[w] = I * (double)(B[0][w] + B[1][w] + B[2][w]) * wscale;
     }
     for (int o = seg >> 1; o > 0; o >>= 1)
       for (int w = 0; w < 3; ++w) c[w] += __shfl_xor(c[w], o, 64);
     if (e < nt && (e & (seg - 1)) == 0) {
       const int T = e >> (2 * levels);
-      for (int w = 0; w < 3; ++w) tripart[3 * T + w] = (double)c[w];
+      for (int w = 0; w < 3; ++w) tripart[3 * T + w] = c[w];
     }
   }
 }
@@ -861,7 +860,6 @@ k_restrict_nodes(int32_t nc, const int32_t* __restrict__ cn_ptr, const int32_t* 
   block_store<1>(vals, part, idx);
 }
 
-template <typename R>
 __global__ void __launch_bounds__(kBlock)
 k_restrict_inject(DLevel C, const uint8_t* __restrict__ nat, const double* __restrict__ ut,
                   int64_t stride, double scale, double* __restrict__ b, double* part) {
@@ -869,21 +867,20 @@ k_restrict_inject(DLevel C, const uint8_t* __restrict__ nat, const double* __res
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C.n; i += gridDim.x * blockDim.x) {
     const int beg = C.rowptr[i], end = C.rowptr[i + 1];
     const double2 pi = C.xy[i];
-    const R ui = R(ut[i]), vi = R(ut[stride + i]);
-    R dv = R(0);
+    const double ui = ut[i], vi = ut[stride + i];
+    double dv = 0.0;
     for (int s = beg + 1; s < end; ++s) {
       const int j = C.col[s];
       const double2 pj = C.xy[j];
-      const R uj = R(ut[j]), vj = R(ut[stride + j]);
+      const double uj = ut[j], vj = ut[stride + j];
       for (int q = 0; q < 2; ++q) {
         const int k = C.side[2 * s + q];
         if (k < 0) continue;
         const SideGeo g = side_geo(pi, pj, C.xy[k], q == 0 ? 1.0 : -1.0);
-        dv += (R(g.bj) * uj + R(g.cj) * vj) * R(1.0 / 6.0) +
-              (R(g.bi) * ui + R(g.ci) * vi) * R(1.0 / 12.0);
+        dv += (g.bj * uj + g.cj * vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
       }
     }
-    const double v = nat[i] ? 0.0 : scale * (double)dv;
+    const double v = nat[i] ? 0.0 : scale * dv;
     b[i] = v;
     sum += v;
   }
@@ -921,19 +918,18 @@ k_weighted_sums(int32_t n, const double* __restrict__ v, const double* __restric
 // Every fine node is the coarse P1 function evaluated there: with the coarse
 // triangle T holding the node and its barycentric coordinates n/2^k,
 // phi_f = (n0 phi[T0] + n1 phi[T1] + n2 phi[T2]) / 2^k (dyadic weights, exact).
-template <typename R>
 __global__ void __launch_bounds__(kBlock)
 k_prolong(int32_t nf, const int32_t* __restrict__ pcode, const int32_t* __restrict__ tri_c,
           int levels, const double* __restrict__ phic, double* __restrict__ phif) {
   const int den = 1 << levels;
-  const R inv = R(1.0) / R(den);
+  const double inv = 1.0 / (double)den;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
     const int2 code = reinterpret_cast<const int2*>(pcode)[i];
     const int T = code.x;
     const int n1 = code.y & 0xffff, n2 = code.y >> 16, n0 = den - n1 - n2;
-    const R f = R(n0) * R(phic[tri_c[3 * T]]) + R(n1) * R(phic[tri_c[3 * T + 1]]) +
-                R(n2) * R(phic[tri_c[3 * T + 2]]);
-    phif[i] = (double)(f * inv);
+    const double f = (double)n0 * phic[tri_c[3 * T]] + (double)n1 * phic[tri_c[3 * T + 1]] +
+                     (double)n2 * phic[tri_c[3 * T + 2]];
+    phif[i] = f * inv;
   }
 }
 
@@ -1144,12 +1140,9 @@ template void launch_pcg_iter<float, 1>(const DLevel&, const PcgVecs<float>&, co
 
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
                               int levels, const double* ut, int64_t stride, double* tripart,
-                              bool fp32, hipStream_t s) {
+                              hipStream_t s) {
   const int g = grid_for(n_fine_tris, kBlock);
-  if (fp32)
-    k_restrict_galerkin<float><<<g, kBlock, 0, s>>>(tri_f, n_fine_tris, xy_f, levels, ut, stride, tripart);
-  else
-    k_restrict_galerkin<double><<<g, kBlock, 0, s>>>(tri_f, n_fine_tris, xy_f, levels, ut, stride, tripart);
+  k_restrict_galerkin<<<g, kBlock, 0, s>>>(tri_f, n_fine_tris, xy_f, levels, ut, stride, tripart);
 }
 
 void launch_restrict_nodes(int32_t n_c, const int32_t* cn_ptr, const int32_t* cn_tri,
@@ -1160,11 +1153,8 @@ void launch_restrict_nodes(int32_t n_c, const int32_t* cn_ptr, const int32_t* cn
 
 void launch_restrict_inject(const DLevel& C, const uint8_t* nat, const double* ut,
                             int64_t stride, double scale, double* b, double* part, int nb,
-                            bool fp32, hipStream_t s) {
-  if (fp32)
-    k_restrict_inject<float><<<nb, kBlock, 0, s>>>(C, nat, ut, stride, scale, b, part);
-  else
-    k_restrict_inject<double><<<nb, kBlock, 0, s>>>(C, nat, ut, stride, scale, b, part);
+                            hipStream_t s) {
+  k_restrict_inject<<<nb, kBlock, 0, s>>>(C, nat, ut, stride, scale, b, part);
 }
 
 void launch_remove_mean(int32_t n, double* v, const double* part, int nb, const double* weights,
@@ -1177,14 +1167,9 @@ void launch_weighted_sums(int32_t n, const double* v, const double* w, double* p
   k_weighted_sums<<<nb, kBlock, 0, s>>>(n, v, w, part);
 }
 
-void launch_prolong(int32_t n_f, int32_t n_c, const int32_t* pcode, const int32_t* tri_c,
-                    int levels, const double* phic, double* phif, bool fp32, hipStream_t s) {
-  (void)n_c;
-  const int g = grid_for(n_f, kBlock);
-  if (fp32)
-    k_prolong<float><<<g, kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
-  else
-    k_prolong<double><<<g, kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
+void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int levels,
+                    const double* phic, double* phif, hipStream_t s) {
+  k_prolong<<<grid_for(n_f, kBlock), kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
 }
 
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
