@@ -29,12 +29,16 @@ METRIC = "fine DOF·steps/s at fixed L2 vs oracle; learned+mixed vs plain PCG ti
 HBM_PEAK_GBS = 8000.0
 
 # algorithmic bytes per launch of each timed kernel (int32 indices, FP64 values):
-# CSR matrix 12 B/nnz + 4 B/row pointer; vectors once each.
+# CSR matrix 12 B/nnz + 4 B/row pointer; every vector once.
+#  mass_spmv:   one fused Chebyshev step over nr right-hand sides: Dirichlet
+#               index 4 B + two Jacobi diagonals 16 B per row, and per rhs the
+#               gathered iterate, the previous iterate, b and the new iterate
+#  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written
+#  coarse_spmv: PCG direction + product kernel: z, p_old read, p_new, q written
 KERNELS = {
-    "mass_spmv": (1, lambda n, z: 12 * z + 4 * (n + 1) + 4 * n + 2 * 8 * n + 2 * 8 * n),
-    "mom_spmv": (2, lambda n, z: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
-    "coarse_spmv": (3, lambda n, z: 12 * z + 4 * (n + 1) + 2 * 8 * n),
-    "rot_spmv": (5, lambda n, z: 12 * z + 4 * (n + 1) + 2 * 8 * n),
+    "mass_spmv": (1, lambda n, z, nr: 12 * z + 4 * (n + 1) + 20 * n + 32 * nr * n),
+    "mom_spmv": (2, lambda n, z, nr: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
+    "coarse_spmv": (3, lambda n, z, nr: 12 * z + 4 * (n + 1) + 4 * 8 * n),
 }
 
 
@@ -140,7 +144,7 @@ def main():
     dof = 3 * g.nf
     value = dof * args.steps / elapsed
     n_rows, nnz = (g.nc, int(g.sizes.nnz_coarse)) if kid == 3 else (g.nf, int(g.sizes.nnz_fine))
-    bpl = kbytes(n_rows, nnz)
+    bpl = kbytes(n_rows, nnz, 3 if w.chi else 2)
     avg_s = (kms / 1e3) / max(nlaunch, 1)
     achieved = bpl / avg_s / 1e9 if nlaunch else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -203,9 +203,12 @@ int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stat
 int cgp_prolong(cgp_ctx* ctx, const double* phi_c, double* phi_f, void* stream);
 
 /* Steps 5-6 (Eqs. 25-26, Sect. 2.3): M dU = -(2/3) dt G phi_f on the
- * non-Dirichlet nodes (consistent mass, Jacobi-PCG to mass_tol), u_out =
- * u_tilde + dU; p_out = p_in + phi_f for chi = 0; for chi = 1 additionally
- * M dp = -nu D u_tilde and p_out = p_in + phi_f + dp.  p_out may alias p_in.
+ * non-Dirichlet nodes (consistent mass), u_out = u_tilde + dU; p_out =
+ * p_in + phi_f for chi = 0; for chi = 1 additionally M dp = -nu D u_tilde and
+ * p_out = p_in + phi_f + dp.  The mass solves run together as Chebyshev
+ * iteration on [1/2, 2] (the spectrum of the Jacobi-scaled P1 mass matrix),
+ * with the iteration count fixed by mass_tol (27 for 1e-12); stats report
+ * that count and its a-priori error bound.  p_out may alias p_in.
  * u_tilde, u_out device [2][N_f]; phi_f, p_in, p_out device [N_f].  stats:
  * [3] (u, v, rotational) or NULL. */
 int cgp_correct(cgp_ctx* ctx, const double* u_tilde, const double* phi_f, const double* p_in,
@@ -228,18 +231,18 @@ int cgp_intermediates(cgp_ctx* ctx, const double** u_tilde, const double** b_c,
 
 /* Measurement hook.  While enabled, every launch of the selected kernel on
  * this context is bracketed by a pair of HIP events recorded on the stream
- * the kernel runs on.  kernel_id: 0 off, CGP_K_MASS_SPMV (velocity-correction
- * mass-matrix product, 2 right-hand sides), CGP_K_MOM_SPMV (momentum BiCGSTAB
- * product v = A p^, 2 right-hand sides), CGP_K_COARSE_SPMV (coarse PCG
- * product), CGP_K_MOM_ASSEMBLE (momentum matrix and right-hand side),
- * CGP_K_ROT_SPMV (rotational pressure mass-matrix product).  Enabling resets
- * the accumulated time.  cgp_timing_read synchronises the recorded events and
- * returns the summed kernel time (ms) and the number of launches. */
+ * the kernel runs on.  kernel_id: 0 off, CGP_K_MASS_SPMV (one Chebyshev step
+ * of the fused mass-matrix solves: velocity correction and, for chi = 1, the
+ * rotational pressure update), CGP_K_MOM_SPMV (momentum BiCGSTAB product
+ * v = A p^, 2 right-hand sides), CGP_K_COARSE_SPMV (coarse PCG product
+ * kernel), CGP_K_MOM_ASSEMBLE (momentum matrix and right-hand side).
+ * Enabling resets the accumulated time.  cgp_timing_read synchronises the
+ * recorded events and returns the summed kernel time (ms) and the number of
+ * launches. */
 #define CGP_K_MASS_SPMV 1
 #define CGP_K_MOM_SPMV 2
 #define CGP_K_COARSE_SPMV 3
 #define CGP_K_MOM_ASSEMBLE 4
-#define CGP_K_ROT_SPMV 5
 int cgp_timing_enable(cgp_ctx* ctx, int kernel_id);
 int cgp_timing_read(cgp_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -23,7 +23,6 @@ CGP_K_MASS_SPMV = 1
 CGP_K_MOM_SPMV = 2
 CGP_K_COARSE_SPMV = 3
 CGP_K_MOM_ASSEMBLE = 4
-CGP_K_ROT_SPMV = 5
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
 

@@ -70,10 +70,14 @@ struct cgp_ctx {
   float *Kc32 = nullptr, *invdKc32 = nullptr;
   double *ut = nullptr, *rhs = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr,
          *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
-  double *phi_f = nullptr, *rot_rhs = nullptr, *dp = nullptr;
-  double *bc = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
-  float *cb32 = nullptr, *cx32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32 = nullptr,
-        *cq32 = nullptr;
+  double* phi_f = nullptr;
+  double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
+  double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
+  int cheb_iters = 0;
+  double *bc = nullptr, *cr = nullptr, *cz = nullptr, *cp0 = nullptr, *cp1 = nullptr,
+         *cq = nullptr;
+  float *cb32 = nullptr, *cx32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32a = nullptr,
+        *cp32b = nullptr, *cq32 = nullptr;
   double* tripart = nullptr;
   double* part = nullptr;
   Scal* scal = nullptr;
@@ -106,11 +110,12 @@ size_t carve(cgp_ctx* c, void* base) {
   c->invdA = w.take<double>(nf);
   c->invdM = w.take<double>(nf);
   c->invdM_int = w.take<double>(nf);
+  int32_t* tile_f = w.take<int32_t>(c->h.gf.tile.size());
   double** vec2[] = {&c->ut, &c->rhs, &c->r, &c->rhat, &c->p, &c->v, &c->phat, &c->shat, &c->t};
   for (double** q : vec2) *q = w.take<double>(2 * nf);
   c->phi_f = w.take<double>(nf);
-  c->rot_rhs = w.take<double>(nf);
-  c->dp = w.take<double>(nf);
+  c->mrhs = w.take<double>(3 * nf);
+  for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
 
   int32_t* rp_c = w.take<int32_t>(nc + 1);
   int32_t* col_c = w.take<int32_t>(nnzc);
@@ -127,16 +132,17 @@ size_t carve(cgp_ctx* c, void* base) {
   c->invdKc = w.take<double>(nc);
   c->invdKc32 = w.take<float>(nc);
   c->lumped_c = w.take<double>(nc);
-  double** cvec[] = {&c->bc, &c->cr, &c->cz, &c->cp, &c->cq};
+  int32_t* tile_c = w.take<int32_t>(c->h.gc.tile.size());
+  double** cvec[] = {&c->bc, &c->cr, &c->cz, &c->cp0, &c->cp1, &c->cq};
   for (double** q : cvec) *q = w.take<double>(nc);
-  float** cvec32[] = {&c->cb32, &c->cx32, &c->cr32, &c->cz32, &c->cp32, &c->cq32};
+  float** cvec32[] = {&c->cb32, &c->cx32, &c->cr32, &c->cz32, &c->cp32a, &c->cp32b, &c->cq32};
   for (float** q : cvec32) *q = w.take<float>(nc);
   c->tripart = w.take<double>(3 * (size_t)c->tc);
   c->part = w.take<double>((size_t)cgp::kSlots * 2 * cgp::kNbMax);
   c->scal = w.take<Scal>(8);
 
-  c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f};
-  c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c};
+  c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
+  c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
   return w.off + 256;
 }
 
@@ -262,14 +268,13 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
   int rc = CGP_OK;
   if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
   if (P.precision == CGP_FP64) {
-    cgp::PcgVecs<double> V{x, c->cr, c->cz, c->cp, c->cq, b, c->invdKc, c->Kc};
-    cgp::launch_pcg_init<double, 1>(c->C, V, nullptr, false, c->scal, c->part, c->nb_c, s);
+    cgp::PcgVecs<double> V{x, c->cr, c->cz, c->cq, {c->cp0, c->cp1}, b, c->invdKc, c->Kc};
+    cgp::launch_pcg_init<double>(c->C, V, false, c->scal, c->part, c->nb_c, s);
     Scal out[1];
-    rc = drive(c, c->scal, 1, P.max_iter, 32, false,
-               [&](int it, bool) {
-                 cgp::launch_pcg_iter<double, 1>(c->C, V, nullptr, c->scal, c->part, c->nb_c,
-                                                 it, P.pcg_tol, false, s,
-                                                 timer(c, CGP_K_COARSE_SPMV));
+    rc = drive(c, c->scal, 1, P.max_iter + 1, 32, true,
+               [&](int it, bool chk) {
+                 cgp::launch_pcg_iter<double>(c->C, V, c->scal, c->part, c->nb_c, it, P.pcg_tol,
+                                              chk, s, chk ? nullptr : timer(c, CGP_K_COARSE_SPMV));
                },
                s, out);
     if (rc) return rc;
@@ -294,15 +299,15 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
         break;
       }
       if (outer >= P.max_outer || inner_total >= P.max_iter) break;
-      cgp::PcgVecs<float> V{c->cx32, c->cr32, c->cz32, c->cp32, c->cq32, c->cb32, c->invdKc32,
-                            c->Kc32};
-      cgp::launch_pcg_init<float, 1>(c->C, V, nullptr, true, c->scal, c->part, c->nb_c, s);
+      cgp::PcgVecs<float> V{c->cx32, c->cr32, c->cz32, c->cq32, {c->cp32a, c->cp32b},
+                            c->cb32, c->invdKc32, c->Kc32};
+      cgp::launch_pcg_init<float>(c->C, V, true, c->scal, c->part, c->nb_c, s);
       Scal out[1];
       const int budget = std::max(1, P.max_iter - inner_total);
-      int r2 = drive(c, c->scal, 1, budget, 32, false,
-                     [&](int it, bool) {
-                       cgp::launch_pcg_iter<float, 1>(c->C, V, nullptr, c->scal, c->part,
-                                                      c->nb_c, it, P.inner_tol, false, s);
+      int r2 = drive(c, c->scal, 1, budget + 1, 32, true,
+                     [&](int it, bool chk2) {
+                       cgp::launch_pcg_iter<float>(c->C, V, c->scal, c->part, c->nb_c, it,
+                                                   P.inner_tol, chk2, s);
                      },
                      s, out);
       if (r2) return r2;
@@ -329,46 +334,27 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
   return rc;
 }
 
+hipEvent_t* cheb_timer(void* c) { return timer(static_cast<cgp_ctx*>(c), CGP_K_MASS_SPMV); }
+
 int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
                 double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   const int chi = P.chi;
-  cgp::launch_correct_rhs(c->F, c->dir_index, P.dt, P.nu, chi, phi_f, ut, c->rhs, c->rot_rhs, s);
-  // velocity: M dU = rhs on the non-Dirichlet nodes (Dirichlet rows masked)
-  double* du = c->phat;
-  cgp::PcgVecs<double> V{du, c->r, c->rhat, c->p, c->v, c->rhs, c->invdM_int, c->Mval};
-  cgp::launch_pcg_init<double, 2>(c->F, V, c->dir_index, true, c->scal, c->part, c->nb_f, s);
-  Scal out[2];
-  int rc = drive(c, c->scal, 2, P.mass_max_iter, 8, false,
-                 [&](int it, bool) {
-                   cgp::launch_pcg_iter<double, 2>(c->F, V, c->dir_index, c->scal, c->part,
-                                                   c->nb_f, it, P.mass_tol, false, s,
-                                                   timer(c, CGP_K_MASS_SPMV));
-                 },
-                 s, out);
-  if (rc) return rc;
-  rc = stats_status(out, 2, P.mass_max_iter, st);
-  const double* dp = nullptr;
-  if (chi) {
-    cgp::PcgVecs<double> W{c->dp, c->t, c->t + c->nf, c->shat, c->shat + c->nf, c->rot_rhs,
-                           c->invdM, c->Mval};
-    cgp::launch_pcg_init<double, 1>(c->F, W, nullptr, true, c->scal + 2, c->part, c->nb_f, s);
-    Scal o1[1];
-    int r2 = drive(c, c->scal + 2, 1, P.mass_max_iter, 8, false,
-                   [&](int it, bool) {
-                     cgp::launch_pcg_iter<double, 1>(c->F, W, nullptr, c->scal + 2, c->part,
-                                                     c->nb_f, it, P.mass_tol, false, s,
-                                                     timer(c, CGP_K_ROT_SPMV));
-                   },
-                   s, o1);
-    if (r2) return r2;
-    rc = worst(rc, stats_status(o1, 1, P.mass_max_iter, st ? st + 2 : nullptr));
-    dp = c->dp;
-  } else if (st) {
-    st[2] = cgp_solve_stats{0, 0, 1, 0, 0.0};
+  // velocity: M dU = -(2/3) dt G phi_f on the non-Dirichlet nodes; rotational
+  // form: M dp = -nu D U~ on all nodes -- one fused Chebyshev solve
+  cgp::launch_correct_rhs(c->F, c->dir_index, P.dt, P.nu, chi, phi_f, ut, c->mrhs, s);
+  const double* du = cgp::launch_cheb(c->F, c->Mval, c->invdM_int, c->invdM, c->dir_index,
+                                      c->mrhs, chi ? 3 : 2, c->mx, c->cheb_iters, s,
+                                      c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
+  if (st) {
+    // a-priori bound of the Chebyshev iteration on [1/2, 2]
+    const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
+    for (int d = 0; d < 3; ++d)
+      st[d] = cgp_solve_stats{(d < 2 || chi) ? c->cheb_iters : 0, 0, 1, 0,
+                              (d < 2 || chi) ? bound : 0.0};
   }
-  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, dp, u_out, p_out, s);
-  return rc;
+  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, chi, u_out, p_out, s);
+  return CGP_OK;
 }
 
 }  // namespace
@@ -424,6 +410,11 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   c->ndir = (int32_t)c->h.dir_nodes.size();
   c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
   c->nb_c = std::min(cgp::kNbMax, std::max(1, (c->nc + cgp::kBlock - 1) / cgp::kBlock));
+  c->cheb_iters = cgp::cheb_iterations(prob->mass_tol);
+  if (c->cheb_iters > prob->mass_max_iter) {
+    delete c;
+    return fail(CGP_ERR_INVALID, "mass_max_iter is below the Chebyshev count for mass_tol");
+  }
   c->ws_bytes = carve(c, nullptr);
   *out = c;
   return CGP_OK;
@@ -470,6 +461,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   HIPCHK(up((void*)c->F.col, h.gf.col.data(), 4 * h.gf.col.size()));
   HIPCHK(up((void*)c->F.side, h.gf.side.data(), 4 * h.gf.side.size()));
   HIPCHK(up((void*)c->F.xy, h.fine.xy.data(), 8 * h.fine.xy.size()));
+  HIPCHK(up((void*)c->F.tile, h.gf.tile.data(), 4 * h.gf.tile.size()));
+  HIPCHK(up((void*)c->C.tile, h.gc.tile.data(), 4 * h.gc.tile.size()));
   HIPCHK(up(c->tri_f, h.fine.tri.data(), 4 * h.fine.tri.size()));
   HIPCHK(up(c->pcode, h.pcode.data(), 4 * h.pcode.size()));
   HIPCHK(up(c->dir_index, h.dir_index.data(), 4 * h.dir_index.size()));
@@ -593,7 +586,7 @@ int cgp_intermediates(cgp_ctx* c, const double** ut, const double** bc, const do
 
 int cgp_timing_enable(cgp_ctx* c, int kernel_id) {
   if (!c) return fail(CGP_ERR_INVALID, "null context");
-  if (kernel_id < 0 || kernel_id > CGP_K_ROT_SPMV) return fail(CGP_ERR_INVALID, "unknown kernel id");
+  if (kernel_id < 0 || kernel_id > CGP_K_MOM_ASSEMBLE) return fail(CGP_ERR_INVALID, "unknown kernel id");
   c->timed_id = kernel_id;
   c->tev_used = 0;
   return CGP_OK;

@@ -20,6 +20,8 @@ struct DLevel {
   const int32_t* col;
   const int32_t* side;
   const double2* xy;
+  const int32_t* tile;   // row tiles of the LDS-staged products
+  int32_t ntiles;
 };
 
 // Per right-hand-side solver scalars.  done_stamp is the (iteration, phase)
@@ -68,22 +70,32 @@ void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Sc
                       double* part, int nb, int it, double tol, bool check_only,
                       hipStream_t s, hipEvent_t* ev = nullptr);
 
-// ---------------------------------------------------------------- PCG
+// ---------------------------------------------------------------- PCG (one rhs)
 template <typename T>
 struct PcgVecs {
-  T *x, *r, *z, *p, *q;
+  T *x, *r, *z, *q;
+  T* p[2];          // direction, alternating between iterations
   const T* b;
   const T* invd;
   const T* val;
 };
-template <typename T, int NR>
-void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, bool zero_x0,
-                     Scal* sc, double* part, int nb, hipStream_t s);
-// `ev`, when not null, is a pair of events recorded around the SpMV kernel.
-template <typename T, int NR>
-void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, Scal* sc,
-                     double* part, int nb, int it, double tol, bool check_only, hipStream_t s,
-                     hipEvent_t* ev = nullptr);
+template <typename T>
+void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, bool zero_x0, Scal* sc, double* part,
+                     int nb, hipStream_t s);
+// `ev`, when not null, is a pair of events recorded around the product kernel.
+template <typename T>
+void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* part, int nb, int it,
+                     double tol, bool check_only, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// ---------------------------------------------------------------- Chebyshev mass solves
+int cheb_iterations(double tol);
+// Solves M x = b for nr (2 or 3) right-hand sides stacked [nr][n]; returns the
+// buffer (one of x[0..2]) holding the result.  `timer(tctx)`, when given,
+// supplies an event pair per product launch.
+double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
+                    const double* invd_full, const int32_t* dir_index, const double* b, int nr,
+                    double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
+                    void* tctx);
 
 // ---------------------------------------------------------------- restriction / prolongation
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
@@ -103,17 +115,17 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
                     const double* phic, double* phif, hipStream_t s);
 
 // ---------------------------------------------------------------- correction
+// rhs [3][n]: velocity right-hand sides, then (chi = 1) the rotational one
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
-                        int chi, const double* phi_f, const double* ut, double* rhs_vel,
-                        double* rhs_rot, hipStream_t s);
+                        int chi, const double* phi_f, const double* ut, double* rhs,
+                        hipStream_t s);
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
-                         const double* phi_f, const double* dp, double* u_out, double* p_out,
+                         const double* phi_f, int chi, double* u_out, double* p_out,
                          hipStream_t s);
 
 // ---------------------------------------------------------------- small vector ops
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
 void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s);
-void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s);
 void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,
                        double* r, float* r32, double* part, int nb, hipStream_t s);

@@ -16,12 +16,20 @@
 // stored and no atomics are used: every output row is owned by one thread or
 // one lane group, and every reduction is a fixed-order two-pass block sum, so
 // results are bitwise reproducible run to run.
+//
+// Sparse products stage a row tile (<= 256 rows, <= kTileNnz nonzeros) of the
+// CSR values and columns in LDS with coalesced loads, then one thread per row
+// gathers the vector; this keeps many full cache lines in flight per CU.
+#include <cmath>
+
 #include "device.hpp"
+#include "mesh.hpp"
 
 namespace cgp {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+static_assert(kTileRows == kBlock, "one thread per tile row");
 
 // reduction slot kinds (x2 right-hand sides)
 enum { SL_RR = 0, SL_RZ = 1, SL_BB = 2, SL_PQ = 3, SL_RHR = 4, SL_RHV = 5, SL_SS = 6, SL_TS = 7 };
@@ -86,31 +94,54 @@ __device__ __forceinline__ bool active(const Scal* sc, int d, int my_stamp) {
   return st == 0 || st >= my_stamp;
 }
 
-// y(row) = sum_s val[s] x[col[s]] for NR right-hand sides (stride n) with
-// LW lanes per row; every lane of the group ends with the full sums.
-template <typename T, int NR, int LW>
-__device__ __forceinline__ void spmv_row(const int32_t* __restrict__ rowptr,
-                                         const int32_t* __restrict__ col,
-                                         const T* __restrict__ val, const T* __restrict__ x,
-                                         int64_t n, int row, int lane, T (&acc)[NR]) {
-#pragma unroll
-  for (int d = 0; d < NR; ++d) acc[d] = T(0);
-  const int beg = rowptr[row], end = rowptr[row + 1];
-  for (int s = beg + lane; s < end; s += LW) {
-    const T a = val[s];
-    const int c = col[s];
-#pragma unroll
-    for (int d = 0; d < NR; ++d) acc[d] += a * x[d * n + c];
-  }
-#pragma unroll
-  for (int o = LW / 2; o > 0; o >>= 1)
-#pragma unroll
-    for (int d = 0; d < NR; ++d) acc[d] += __shfl_xor(acc[d], o, LW);
+__device__ __forceinline__ void reset_scal(Scal& s) {
+  s.rho[0] = s.rho[1] = 0.0;
+  s.rho_old = s.alpha = s.omega = 1.0;
+  s.bb = 0.0;
+  s.rel = 0.0;
+  s.done_stamp = 0;
+  s.iters = 0;
+  s.status = 0;
 }
 
-constexpr int kLanes = 8;   // lanes per CSR row in the SpMV kernels (~7 nonzeros per row)
+// LDS stage of one row tile of a CSR matrix.
+template <typename T>
+struct TileStage {
+  T val[kTileNnz];
+  int32_t col[kTileNnz];
+};
 
-// ------------------------------------------------------------------ assembly
+// Loads the nonzeros of rows [r0, r1) into LDS (coalesced); returns the first
+// nonzero index s0.  Brackets the stage with barriers so a block can loop over
+// tiles.
+template <typename T>
+__device__ __forceinline__ int stage_tile(TileStage<T>& st, const DLevel& L, const T* __restrict__ val,
+                                          int r0, int r1) {
+  const int s0 = L.rowptr[r0], s1 = L.rowptr[r1];
+  __syncthreads();
+#pragma unroll 4
+  for (int k = threadIdx.x; k < s1 - s0; k += kBlock) {
+    st.val[k] = val[s0 + k];
+    st.col[k] = L.col[s0 + k];
+  }
+  __syncthreads();
+  return s0;
+}
+
+// acc[d] = sum over the staged nonzeros of row `row` of val * g(d, col).
+template <typename T, int NR, class G>
+__device__ __forceinline__ void tile_row(const TileStage<T>& st, const DLevel& L, int s0, int row,
+                                         G g, T (&acc)[NR]) {
+#pragma unroll
+  for (int d = 0; d < NR; ++d) acc[d] = T(0);
+  const int a = L.rowptr[row] - s0, b = L.rowptr[row + 1] - s0;
+  for (int s = a; s < b; ++s) {
+    const T v = st.val[s];
+    const int c = st.col[s];
+#pragma unroll
+    for (int d = 0; d < NR; ++d) acc[d] += v * g(d, c);
+  }
+}
 
 struct SideGeo {
   double area, bi, ci, bj, cj;
@@ -126,6 +157,18 @@ __device__ __forceinline__ SideGeo side_geo(double2 pi, double2 pj, double2 pk, 
   g.cj = sg * (pi.x - pk.x);
   return g;
 }
+
+constexpr int kRowLanes = 8;   // lanes per row in the side-based row kernels
+
+template <int NS>
+__device__ __forceinline__ void group_sum(double (&v)[NS]) {
+#pragma unroll
+  for (int o = kRowLanes / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] += __shfl_xor(v[s], o, kRowLanes);
+}
+
+// ------------------------------------------------------------------ assembly
 
 __global__ void __launch_bounds__(kBlock)
 k_mass_assemble(DLevel L, const int32_t* __restrict__ dir_index, double* __restrict__ Mval,
@@ -197,6 +240,12 @@ k_coarse_assemble(DLevel L, const uint8_t* __restrict__ nat, double* __restrict_
   }
 }
 
+
+// Momentum matrix A = 3/2 M + dt nu K + dt N(w), w = 2 U^n - U^{n-1}, and the
+// right-hand side -dt G P + M (2 U^n - 1/2 U^{n-1} + dt F) (Eq. 21), one lane
+// group per row, one lane per off-diagonal slot; Dirichlet rows become
+// identity rows with the boundary value as right-hand side and as initial
+// guess.
 __global__ void __launch_bounds__(kBlock)
 k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
                     const double* __restrict__ up, const double* __restrict__ u,
@@ -205,35 +254,35 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
                     double* __restrict__ invdA, double* __restrict__ rhs,
                     double* __restrict__ x0) {
   const int64_t n = L.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int i = base + threadIdx.x / kRowLanes;
+    if (i >= n) continue;  // uniform within the lane group
     const int beg = L.rowptr[i], end = L.rowptr[i + 1];
-    const double wix = 2.0 * u[i] - up[i], wiy = 2.0 * u[n + i] - up[n + i];
-    x0[i] = wix;
-    x0[n + i] = wiy;
     const int di = dir_index[i];
     if (di >= 0) {  // Dirichlet row: identity, right-hand side = boundary value
-      A[beg] = 1.0;
-      for (int s = beg + 1; s < end; ++s) A[s] = 0.0;
-      invdA[i] = 1.0;
-      const double gx = udir[di], gy = udir[ndir + di];
-      rhs[i] = gx;
-      rhs[n + i] = gy;
-      // the initial guess satisfies the Dirichlet condition exactly, so these
-      // rows keep a zero residual and BiCGSTAB works on the free rows only
-      x0[i] = gx;
-      x0[n + i] = gy;
+      for (int s = beg + lane; s < end; s += kRowLanes) A[s] = s == beg ? 1.0 : 0.0;
+      if (lane == 0) {
+        invdA[i] = 1.0;
+        const double gx = udir[di], gy = udir[ndir + di];
+        rhs[i] = gx;
+        rhs[n + i] = gy;
+        // the initial guess satisfies the Dirichlet condition exactly, so these
+        // rows keep a zero residual and BiCGSTAB works on the free rows only
+        x0[i] = gx;
+        x0[n + i] = gy;
+      }
       continue;
     }
     const double2 pi = L.xy[i];
     const double Pi = p[i];
-    double bxi = 2.0 * u[i] - 0.5 * up[i], byi = 2.0 * u[n + i] - 0.5 * up[n + i];
-    if (f) {
-      bxi += dt * f[i];
-      byi += dt * f[n + i];
-    }
-    double dm = 0.0, dk = 0.0, dn = 0.0, rx = 0.0, ry = 0.0, gx = 0.0, gy = 0.0;
-    for (int s = beg + 1; s < end; ++s) {
+    const double uix = u[i], uiy = u[n + i], upix = up[i], upiy = up[n + i];
+    const double wix = 2.0 * uix - upix, wiy = 2.0 * uiy - upiy;
+    // dm, dk, dn, rx, ry, gx, gy
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
       const int j = L.col[s];
+      const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
       const double2 pj = L.xy[j];
       const double ujx = u[j], ujy = u[n + j], upjx = up[j], upjy = up[n + j];
       const double wjx = 2.0 * ujx - upjx, wjy = 2.0 * ujy - upjy;
@@ -241,33 +290,43 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       double m = 0.0, kk = 0.0, nn = 0.0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int k = L.side[2 * s + q];
+        const int k = q == 0 ? sd.x : sd.y;
         if (k < 0) continue;
         const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
         const double wkx = 2.0 * u[k] - up[k], wky = 2.0 * u[n + k] - up[n + k];
         m += g.area * (1.0 / 12.0);
         kk += (g.bi * g.bj + g.ci * g.cj) / (4.0 * g.area);
         nn += ((2.0 * wix + wjx + wkx) * g.bj + (2.0 * wiy + wjy + wky) * g.cj) * (1.0 / 24.0);
-        gx += g.bi * (Pj + 0.5 * Pi);
-        gy += g.ci * (Pj + 0.5 * Pi);
+        acc[5] += g.bi * (Pj + 0.5 * Pi);
+        acc[6] += g.ci * (Pj + 0.5 * Pi);
       }
       A[s] = 1.5 * m + dtnu * kk + dt * nn;
-      dm += m;
-      dk += kk;
-      dn += nn;
+      acc[0] += m;
+      acc[1] += kk;
+      acc[2] += nn;
       double bx = 2.0 * ujx - 0.5 * upjx, by = 2.0 * ujy - 0.5 * upjy;
       if (f) {
         bx += dt * f[j];
         by += dt * f[n + j];
       }
-      rx += m * bx;
-      ry += m * by;
+      acc[3] += m * bx;
+      acc[4] += m * by;
     }
-    const double aii = 1.5 * dm - dtnu * dk - dt * dn;
-    A[beg] = aii;
-    invdA[i] = 1.0 / aii;
-    rhs[i] = rx + dm * bxi + (dt / 6.0) * gx;
-    rhs[n + i] = ry + dm * byi + (dt / 6.0) * gy;
+    group_sum<7>(acc);
+    if (lane == 0) {
+      double bxi = 2.0 * uix - 0.5 * upix, byi = 2.0 * uiy - 0.5 * upiy;
+      if (f) {
+        bxi += dt * f[i];
+        byi += dt * f[n + i];
+      }
+      const double aii = 1.5 * acc[0] - dtnu * acc[1] - dt * acc[2];
+      A[beg] = aii;
+      invdA[i] = 1.0 / aii;
+      rhs[i] = acc[3] + acc[0] * bxi + (dt / 6.0) * acc[5];
+      rhs[n + i] = acc[4] + acc[0] * byi + (dt / 6.0) * acc[6];
+      x0[i] = wix;
+      x0[n + i] = wiy;
+    }
   }
 }
 
@@ -282,26 +341,26 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
 
 __global__ void __launch_bounds__(kBlock)
 k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part) {
+  __shared__ TileStage<double> st;
   const int64_t n = L.n;
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
   double rr[2] = {0, 0}, bb[2] = {0, 0};
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
       double ax[2];
-      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.x, n, row, lane, ax);
-      if (lane == 0) {
+      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.x[d * n + c]; }, ax);
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          const double b = V.b[d * n + row];
-          const double r = b - ax[d];
-          V.r[d * n + row] = r;
-          V.rhat[d * n + row] = r;
-          V.p[d * n + row] = 0.0;
-          V.v[d * n + row] = 0.0;
-          rr[d] += r * r;
-          bb[d] += b * b;
-        }
+      for (int d = 0; d < 2; ++d) {
+        const double b = V.b[d * n + row];
+        const double r = b - ax[d];
+        V.r[d * n + row] = r;
+        V.rhat[d * n + row] = r;
+        V.p[d * n + row] = 0.0;
+        V.v[d * n + row] = 0.0;
+        rr[d] += r * r;
+        bb[d] += b * b;
       }
     }
   }
@@ -309,16 +368,7 @@ k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double
   const int idx[6] = {slot(SL_RR, 0), slot(SL_RR, 1), slot(SL_RHR, 0), slot(SL_RHR, 1),
                       slot(SL_BB, 0), slot(SL_BB, 1)};
   block_store<6>(vals, part, idx);
-  if (blockIdx.x == 0 && threadIdx.x < 2) {
-    Scal& s = sc[threadIdx.x];
-    s.rho[0] = s.rho[1] = 0.0;
-    s.rho_old = s.alpha = s.omega = 1.0;
-    s.bb = 0.0;
-    s.rel = 0.0;
-    s.done_stamp = 0;
-    s.iters = 0;
-    s.status = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) reset_scal(sc[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -338,13 +388,8 @@ k_bicg_b1(int32_t n32, BicgVecs V, Scal* sc, const double* part, int nb, int it,
     const double bb = it == 1 ? s6[4 + d] : sc[d].bb;
     const double rel = bb > 0.0 ? sqrt(s6[d] / bb) : 0.0;
     const bool nan = !isfinite(bb) || !isfinite(s6[d]) || !isfinite(rel);
-    bool fin = false;
-    if (bb == 0.0) {
-      zero_rhs[d] = true;
-      fin = true;
-    } else if (nan || rel <= tol || check_only) {
-      fin = nan || rel <= tol;
-    }
+    const bool fin = bb == 0.0 || nan || rel <= tol;
+    zero_rhs[d] = bb == 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (it == 1) sc[d].bb = bb;
       sc[d].rel = rel;
@@ -362,6 +407,7 @@ k_bicg_b1(int32_t n32, BicgVecs V, Scal* sc, const double* part, int nb, int it,
       omega[d] = sc[d].omega;
     }
   }
+  if (!upd[0] && !upd[1] && !zero_rhs[0] && !zero_rhs[1]) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double dinv = V.invd[i];
 #pragma unroll
@@ -379,20 +425,20 @@ __global__ void __launch_bounds__(kBlock)
 k_bicg_b2(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part,
           int my_stamp) {
   if (!active(sc, 0, my_stamp) && !active(sc, 1, my_stamp)) return;
+  __shared__ TileStage<double> st;
   const int64_t n = L.n;
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
   double dot[2] = {0, 0};
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
       double av[2];
-      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.phat, n, row, lane, av);
-      if (lane == 0) {
+      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.phat[d * n + c]; }, av);
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          V.v[d * n + row] = av[d];
-          dot[d] += V.rhat[d * n + row] * av[d];
-        }
+      for (int d = 0; d < 2; ++d) {
+        V.v[d * n + row] = av[d];
+        dot[d] += V.rhat[d * n + row] * av[d];
       }
     }
   }
@@ -435,6 +481,7 @@ k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
   const int64_t n = L.n;
   bool act[2] = {active(sc, 0, my_stamp), active(sc, 1, my_stamp)};
   if (!act[0] && !act[1]) return;
+  __shared__ TileStage<double> st;
   const int idx[2] = {slot(SL_SS, 0), slot(SL_SS, 1)};
   double ss[2];
   block_sums<2>(part, nb, idx, ss);
@@ -465,20 +512,19 @@ k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
     }
   }
   if (!need_t) return;
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
   double ts[2] = {0, 0}, tt[2] = {0, 0};
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
       double at[2];
-      spmv_row<double, 2, kLanes>(L.rowptr, L.col, A, V.shat, n, row, lane, at);
-      if (lane == 0) {
+      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.shat[d * n + c]; }, at);
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          V.t[d * n + row] = at[d];
-          ts[d] += at[d] * V.r[d * n + row];
-          tt[d] += at[d] * at[d];
-        }
+      for (int d = 0; d < 2; ++d) {
+        V.t[d * n + row] = at[d];
+        ts[d] += at[d] * V.r[d * n + row];
+        tt[d] += at[d] * at[d];
       }
     }
   }
@@ -527,257 +573,167 @@ k_bicg_b5(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp)
 }
 
 // ------------------------------------------------------------------ PCG
-// Jacobi-preconditioned CG on NR right-hand sides (vectors of type T, dot
-// products in FP64).  Rows with mask[i] >= 0 are removed (their residual,
-// update and matrix-vector product are zero).  One iteration = three kernels:
-//   P1  (first iteration: stopping test on r_0)  q = A p, partial (p, q)
-//   P2  alpha = rho / (p, q), x += alpha p, r -= alpha q, z = D^-1 r, partials (r, z), (r, r)
-//   P3  stopping test on r, beta = rho' / rho, p = z + beta p
+// Jacobi-preconditioned CG (vectors of type T, dot products in FP64) in two
+// kernels per iteration; the direction update is folded into the product:
+//   K1(it)  stopping test on r_{it-1} (iters = it - 1), beta = rho_{it-1} / rho_{it-2},
+//           p_it = z + beta p_{it-1} (written to the other p buffer) and
+//           q = A p_it with p_it formed on the fly at the gathered columns,
+//           partial (p_it, q)
+//   K2(it)  alpha = rho_{it-1} / (p, q), x += alpha p, r -= alpha q, z = D^-1 r,
+//           partials (r, z), (r, r)
+// Same arithmetic as the textbook loop (test after the update, then the
+// direction update), one launch fewer per iteration.
 
-template <typename T, int NR, bool MASK>
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_init(DLevel L, PcgVecs<T> V, const int32_t* __restrict__ mask, int zero_x0, Scal* sc,
-           double* part) {
+k_pcg_init(DLevel L, PcgVecs<T> V, int zero_x0, Scal* sc, double* part) {
+  __shared__ TileStage<T> st;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    int s0 = 0;
+    if (!zero_x0) s0 = stage_tile(st, L, V.val, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
+      T ax[1] = {T(0)};
+      if (!zero_x0) tile_row<T, 1>(st, L, s0, row, [&](int, int c) { return V.x[c]; }, ax);
+      const T b = V.b[row];
+      if (zero_x0) V.x[row] = T(0);
+      const T r = b - ax[0];
+      const T z = V.invd[row] * r;
+      V.r[row] = r;
+      V.z[row] = z;
+      V.p[0][row] = z;
+      rz += (double)r * (double)z;
+      rr += (double)r * (double)r;
+      bb += (double)b * (double)b;
+    }
+  }
+  const double vals[3] = {rz, rr, bb};
+  const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
+  block_store<3>(vals, part, idx);
+  if (blockIdx.x == 0 && threadIdx.x == 0) reset_scal(sc[0]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double tol,
+         int my_stamp, int check_only) {
+  if (!active(sc, 0, my_stamp)) return;
   const int64_t n = L.n;
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
-  double rz[NR], rr[NR], bb[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) rz[d] = rr[d] = bb[d] = 0.0;
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
-      T ax[NR];
-      if (zero_x0) {
-#pragma unroll
-        for (int d = 0; d < NR; ++d) ax[d] = T(0);
-      } else {
-        spmv_row<T, NR, kLanes>(L.rowptr, L.col, V.val, V.x, n, row, lane, ax);
-      }
-      if (lane == 0) {
-        const bool masked = MASK && mask[row] >= 0;
-        const T dinv = V.invd[row];
-#pragma unroll
-        for (int d = 0; d < NR; ++d) {
-          const int64_t k = d * n + row;
-          const T b = V.b[k];
-          if (zero_x0 || masked) V.x[k] = T(0);
-          const T r = masked ? T(0) : (zero_x0 ? b : b - ax[d]);
-          const T z = masked ? T(0) : dinv * r;
-          V.r[k] = r;
-          V.z[k] = z;
-          V.p[k] = z;
-          rz[d] += (double)r * (double)z;
-          rr[d] += (double)r * (double)r;
-          bb[d] += masked ? 0.0 : (double)b * (double)b;
-        }
-      }
+  const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
+  double s[3];
+  block_sums<3>(part, nb, idx, s);
+  const double bb = it == 1 ? s[2] : sc[0].bb;
+  const double rel = bb > 0.0 ? sqrt(s[1] / bb) : 0.0;
+  const bool nan = !isfinite(bb) || !isfinite(s[1]) || !isfinite(rel);
+  const bool fin = bb == 0.0 || nan || rel <= tol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (it == 1) sc[0].bb = bb;
+    sc[0].rel = rel;
+    if (fin) {
+      sc[0].done_stamp = my_stamp;
+      sc[0].iters = it - 1;
+      sc[0].status = nan ? 2 : 0;
+    } else {
+      sc[0].rho[(it - 1) & 1] = s[0];
     }
   }
-  double vals[3 * NR];
-  int idx[3 * NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    vals[d] = rz[d];
-    idx[d] = slot(SL_RZ, d);
-    vals[NR + d] = rr[d];
-    idx[NR + d] = slot(SL_RR, d);
-    vals[2 * NR + d] = bb[d];
-    idx[2 * NR + d] = slot(SL_BB, d);
+  if (bb == 0.0) {  // zero right-hand side: the solution is zero
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+      V.x[i] = T(0);
+    return;
   }
-  block_store<3 * NR>(vals, part, idx);
-  if (blockIdx.x == 0 && threadIdx.x < NR) {
-    Scal& s = sc[threadIdx.x];
-    s.rho[0] = s.rho[1] = 0.0;
-    s.rho_old = s.alpha = s.omega = 1.0;
-    s.bb = 0.0;
-    s.rel = 0.0;
-    s.done_stamp = 0;
-    s.iters = 0;
-    s.status = 0;
+  if (fin || check_only) return;
+  __shared__ TileStage<T> st;
+  const T beta = it == 1 ? T(0) : (T)(s[0] / sc[0].rho[(it - 2) & 1]);
+  const T* __restrict__ pold = V.p[(it - 1) & 1];
+  T* __restrict__ pnew = V.p[it & 1];
+  const T* __restrict__ z = V.z;
+  double pq = 0.0;
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    const int s0 = stage_tile(st, L, V.val, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
+      T q[1];
+      tile_row<T, 1>(st, L, s0, row, [&](int, int c) { return z[c] + beta * pold[c]; }, q);
+      const T pr = z[row] + beta * pold[row];
+      pnew[row] = pr;
+      V.q[row] = q[0];
+      pq += (double)pr * (double)q[0];
+    }
   }
+  const double vals[1] = {pq};
+  const int o[1] = {slot(SL_PQ, 0)};
+  block_store<1>(vals, part, o);
 }
 
-template <typename T, int NR, bool MASK>
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_p1(DLevel L, PcgVecs<T> V, const int32_t* __restrict__ mask, Scal* sc, double* part,
-         int nb, int it, double tol, int my_stamp) {
+k_pcg_k2(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my_stamp) {
+  if (!active(sc, 0, my_stamp)) return;
+  const int idx[1] = {slot(SL_PQ, 0)};
+  double pq[1];
+  block_sums<1>(part, nb, idx, pq);
+  const double a = sc[0].rho[(it - 1) & 1] / pq[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[0].alpha = a;
+  const T alpha = (T)a;
+  const T* __restrict__ p = V.p[it & 1];
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    V.x[i] += alpha * p[i];
+    const T r = V.r[i] - alpha * V.q[i];
+    V.r[i] = r;
+    const T z = V.invd[i] * r;
+    V.z[i] = z;
+    rz += (double)r * (double)z;
+    rr += (double)r * (double)r;
+  }
+  const double vals[2] = {rz, rr};
+  const int o[2] = {slot(SL_RZ, 0), slot(SL_RR, 0)};
+  block_store<2>(vals, part, o);
+}
+
+// ------------------------------------------------------------------ Chebyshev
+// Mass-matrix solves M x = b on NR right-hand sides at once (the first two
+// with the Dirichlet rows removed, a third -- the rotational pressure update --
+// on all rows).  The Jacobi-scaled P1 mass matrix has its spectrum in
+// [1/2, 2], so Chebyshev acceleration on that interval needs no inner
+// products: x_{k+1} = x_k + a_k (x_k - x_{k-1}) + c_k D^-1 (b - M x_k), one
+// fused kernel per iteration with the iterates in three rotating buffers.
+template <int NR>
+__global__ void __launch_bounds__(kBlock)
+k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_int,
+       const double* __restrict__ invd_full, const int32_t* __restrict__ dir_index,
+       const double* __restrict__ b, double* __restrict__ xk, const double* __restrict__ xkm,
+       double* __restrict__ xnew, double ca, double cb, int first) {
+  __shared__ TileStage<double> st;
   const int64_t n = L.n;
-  bool act[NR];
-  bool any = false;
-#pragma unroll
-  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
-  if (!any) return;
-  if (it == 1) {
-    double s[3 * NR];
-    int idx[3 * NR];
-#pragma unroll
-    for (int d = 0; d < NR; ++d) {
-      idx[d] = slot(SL_RZ, d);
-      idx[NR + d] = slot(SL_RR, d);
-      idx[2 * NR + d] = slot(SL_BB, d);
-    }
-    block_sums<3 * NR>(part, nb, idx, s);
-    bool zero_rhs[NR];
-    any = false;
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    int s0 = 0;
+    if (!first) s0 = stage_tile(st, L, M, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row >= r1) continue;
+    double mx[NR];
+    if (!first)
+      tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[d * n + c]; }, mx);
+    const bool masked = dir_index[row] >= 0;
+    const double di_int = invd_int[row], di_full = NR > 2 ? invd_full[row] : 0.0;
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
-      zero_rhs[d] = false;
-      if (!act[d]) continue;
-      const double bb = s[2 * NR + d];
-      const double rel = bb > 0.0 ? sqrt(s[NR + d] / bb) : 0.0;
-      const bool nan = !isfinite(bb) || !isfinite(s[NR + d]) || !isfinite(rel);
-      const bool fin = bb == 0.0 || nan || rel <= tol;
-      zero_rhs[d] = bb == 0.0;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc[d].bb = bb;
-        sc[d].rel = rel;
-        sc[d].rho[0] = s[d];
-        if (fin) {
-          sc[d].done_stamp = my_stamp;
-          sc[d].iters = 0;
-          sc[d].status = nan ? 2 : 0;
-        }
-      }
-      act[d] = !fin;
-      any |= act[d];
-    }
-    bool any_zero = false;
-#pragma unroll
-    for (int d = 0; d < NR; ++d) any_zero |= zero_rhs[d];
-    if (any_zero) {
-      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int d = 0; d < NR; ++d)
-          if (zero_rhs[d]) V.x[d * n + i] = T(0);
-      }
-    }
-    if (!any) return;
-  }
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
-  double pq[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) pq[d] = 0.0;
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
-      T ap[NR];
-      spmv_row<T, NR, kLanes>(L.rowptr, L.col, V.val, V.p, n, row, lane, ap);
-      if (lane == 0) {
-        const bool masked = MASK && mask[row] >= 0;
-#pragma unroll
-        for (int d = 0; d < NR; ++d) {
-          const T q = masked ? T(0) : ap[d];
-          V.q[d * n + row] = q;
-          pq[d] += (double)V.p[d * n + row] * (double)q;
-        }
-      }
-    }
-  }
-  int idx[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) idx[d] = slot(SL_PQ, d);
-  block_store<NR>(pq, part, idx);
-}
-
-template <typename T, int NR>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_p2(int32_t n32, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my_stamp) {
-  const int64_t n = n32;
-  bool act[NR];
-  bool any = false;
-#pragma unroll
-  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
-  if (!any) return;
-  int idx[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) idx[d] = slot(SL_PQ, d);
-  double pq[NR];
-  block_sums<NR>(part, nb, idx, pq);
-  T alpha[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    const double a = act[d] ? sc[d].rho[(it - 1) & 1] / pq[d] : 0.0;
-    alpha[d] = (T)a;
-    if (act[d] && blockIdx.x == 0 && threadIdx.x == 0) sc[d].alpha = a;
-  }
-  double rz[NR], rr[NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) rz[d] = rr[d] = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const T dinv = V.invd[i];
-#pragma unroll
-    for (int d = 0; d < NR; ++d) {
-      if (!act[d]) continue;
-      const int64_t k = d * n + i;
-      V.x[k] += alpha[d] * V.p[k];
-      const T r = V.r[k] - alpha[d] * V.q[k];
-      V.r[k] = r;
-      const T z = dinv * r;
-      V.z[k] = z;
-      rz[d] += (double)r * (double)z;
-      rr[d] += (double)r * (double)r;
-    }
-  }
-  double vals[2 * NR];
-  int o[2 * NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    vals[d] = rz[d];
-    o[d] = slot(SL_RZ, d);
-    vals[NR + d] = rr[d];
-    o[NR + d] = slot(SL_RR, d);
-  }
-  block_store<2 * NR>(vals, part, o);
-}
-
-template <typename T, int NR>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_p3(int32_t n32, PcgVecs<T> V, Scal* sc, const double* part, int nb, int it, double tol,
-         int my_stamp) {
-  const int64_t n = n32;
-  bool act[NR];
-  bool any = false;
-#pragma unroll
-  for (int d = 0; d < NR; ++d) any |= (act[d] = active(sc, d, my_stamp));
-  if (!any) return;
-  double s[2 * NR];
-  int idx[2 * NR];
-#pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    idx[d] = slot(SL_RZ, d);
-    idx[NR + d] = slot(SL_RR, d);
-  }
-  block_sums<2 * NR>(part, nb, idx, s);
-  T beta[NR];
-  any = false;
-#pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    beta[d] = T(0);
-    if (!act[d]) continue;
-    const double rel = sqrt(s[NR + d] / sc[d].bb);
-    const bool nan = !isfinite(rel);
-    const bool fin = nan || rel <= tol;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc[d].rel = rel;
-      if (fin) {
-        sc[d].done_stamp = my_stamp;
-        sc[d].iters = it;
-        sc[d].status = nan ? 2 : 0;
-      } else {
-        sc[d].rho[it & 1] = s[d];
-      }
-    }
-    act[d] = !fin;
-    any |= act[d];
-    if (!fin) beta[d] = (T)(s[d] / sc[d].rho[(it - 1) & 1]);
-  }
-  if (!any) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int d = 0; d < NR; ++d) {
-      if (!act[d]) continue;
-      const int64_t k = d * n + i;
-      V.p[k] = V.z[k] + beta[d] * V.p[k];
+      const int64_t k = d * n + row;
+      const double di = d < 2 ? di_int : di_full;
+      double v;
+      if (d < 2 && masked)
+        v = 0.0;
+      else if (first)
+        v = cb * di * b[k];
+      else
+        v = xk[k] + ca * (xk[k] - xkm[k]) + cb * di * (b[k] - mx[d]);
+      xnew[k] = v;
+      if (first) xk[k] = 0.0;  // x_0 = 0 is read back as x_{k-1} by the next step
     }
   }
 }
@@ -933,52 +889,62 @@ k_prolong(int32_t nf, const int32_t* __restrict__ pcode, const int32_t* __restri
   }
 }
 
+
 // ------------------------------------------------------------------ correction
-// rhs_vel = -(2/3) dt G phi_f on non-Dirichlet rows (0 on Dirichlet rows),
-// rhs_rot = -nu D U~ (rotational form only).
+// rhs[0..2n) = -(2/3) dt G phi_f on non-Dirichlet rows (0 on Dirichlet rows),
+// rhs[2n..3n) = -nu D U~ (rotational form only); one lane group per row.
 __global__ void __launch_bounds__(kBlock)
 k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double nu, int chi,
               const double* __restrict__ phi, const double* __restrict__ ut,
-              double* __restrict__ rhs_vel, double* __restrict__ rhs_rot) {
+              double* __restrict__ rhs) {
   const int64_t n = L.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
+  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+    const int i = base + threadIdx.x / kRowLanes;
+    if (i >= n) continue;  // uniform within the lane group
     const int beg = L.rowptr[i], end = L.rowptr[i + 1];
     const double2 pi = L.xy[i];
     const double phii = phi[i];
     const double ui = ut[i], vi = ut[n + i];
-    double gx = 0.0, gy = 0.0, dv = 0.0;
-    for (int s = beg + 1; s < end; ++s) {
+    double acc[3] = {0.0, 0.0, 0.0};  // gx, gy, div
+    for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
       const int j = L.col[s];
+      const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
       const double2 pj = L.xy[j];
       const double ph = phi[j] + 0.5 * phii;
       const double uj = chi ? ut[j] : 0.0, vj = chi ? ut[n + j] : 0.0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int k = L.side[2 * s + q];
+        const int k = q == 0 ? sd.x : sd.y;
         if (k < 0) continue;
         const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
-        gx += g.bi * ph;
-        gy += g.ci * ph;
-        if (chi) dv += (g.bj * uj + g.cj * vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
+        acc[0] += g.bi * ph;
+        acc[1] += g.ci * ph;
+        if (chi)
+          acc[2] += (g.bj * uj + g.cj * vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
       }
     }
-    const bool dir = dir_index[i] >= 0;
-    rhs_vel[i] = dir ? 0.0 : (dt / 9.0) * gx;
-    rhs_vel[n + i] = dir ? 0.0 : (dt / 9.0) * gy;
-    if (chi) rhs_rot[i] = -nu * dv;
+    group_sum<3>(acc);
+    if (lane == 0) {
+      const bool dir = dir_index[i] >= 0;
+      rhs[i] = dir ? 0.0 : (dt / 9.0) * acc[0];
+      rhs[n + i] = dir ? 0.0 : (dt / 9.0) * acc[1];
+      if (chi) rhs[2 * n + i] = -nu * acc[2];
+    }
   }
 }
 
+// u_out = U~ + dU, p_out = p_in + phi_f (+ dp); du holds dU (and dp at 2n)
 __global__ void __launch_bounds__(kBlock)
 k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restrict__ du,
-               const double* p_in, const double* __restrict__ phi, const double* __restrict__ dp,
+               const double* p_in, const double* __restrict__ phi, int chi,
                double* __restrict__ u_out, double* p_out) {
   const int64_t n = n32;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     u_out[i] = ut[i] + du[i];
     u_out[n + i] = ut[n + i] + du[n + i];
     const double pv = p_in[i] + phi[i];
-    p_out[i] = dp ? pv + dp[i] : pv;
+    p_out[i] = chi ? pv + du[2 * n + i] : pv;
   }
 }
 
@@ -992,11 +958,6 @@ __global__ void k_zero_masked(double* __restrict__ x, const uint8_t* __restrict_
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (nat[i]) x[i] = 0.0;
 }
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = (float)a[i];
-}
 __global__ void k_axpy_f32(const float* __restrict__ d, double* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1008,22 +969,21 @@ __global__ void __launch_bounds__(kBlock)
 k_residual64(DLevel C, const double* __restrict__ K, const double* __restrict__ b,
              const double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
              double* part) {
-  const int64_t n = C.n;
-  const int rpb = kBlock / kLanes, lane = threadIdx.x % kLanes;
+  __shared__ TileStage<double> st;
   double rr = 0.0, bb = 0.0;
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
-    const int row = base + threadIdx.x / kLanes;
-    if (row < n) {
+  for (int t = blockIdx.x; t < C.ntiles; t += gridDim.x) {
+    const int r0 = C.tile[t], r1 = C.tile[t + 1];
+    const int s0 = stage_tile(st, C, K, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
       double ax[1];
-      spmv_row<double, 1, kLanes>(C.rowptr, C.col, K, x, n, row, lane, ax);
-      if (lane == 0) {
-        const double bv = b[row];
-        const double rv = bv - ax[0];
-        r[row] = rv;
-        r32[row] = (float)rv;
-        rr += rv * rv;
-        bb += bv * bv;
-      }
+      tile_row<double, 1>(st, C, s0, row, [&](int, int c) { return x[c]; }, ax);
+      const double bv = b[row];
+      const double rv = bv - ax[0];
+      r[row] = rv;
+      r32[row] = (float)rv;
+      rr += rv * rv;
+      bb += bv * bv;
     }
   }
   const double vals[2] = {rr, bb};
@@ -1053,6 +1013,8 @@ inline int grid_for(int64_t units, int per_block, int cap = 4096) {
   return (int)g;
 }
 
+inline int row_group_grid(int64_t rows) { return grid_for(rows, kBlock / kRowLanes, 8192); }
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1075,7 +1037,7 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               double* Aval, double* invdA, double* rhs, double* x0,
                               hipStream_t s, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
-  k_momentum_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(
+  k_momentum_assemble<<<row_group_grid(L.n), kBlock, 0, s>>>(
       L, dir_index, dt, dt * nu, u_prev, u, p, u_dir, n_dir, f, Aval, invdA, rhs, x0);
   if (ev) (void)hipEventRecord(ev[1], s);
 }
@@ -1098,45 +1060,70 @@ void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Sc
   k_bicg_b5<<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, stamp(it, 5));
 }
 
-template <typename T, int NR>
-void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, bool zero_x0,
-                     Scal* sc, double* part, int nb, hipStream_t s) {
-  if (mask)
-    k_pcg_init<T, NR, true><<<nb, kBlock, 0, s>>>(L, V, mask, zero_x0 ? 1 : 0, sc, part);
-  else
-    k_pcg_init<T, NR, false><<<nb, kBlock, 0, s>>>(L, V, mask, zero_x0 ? 1 : 0, sc, part);
+template <typename T>
+void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, bool zero_x0, Scal* sc, double* part,
+                     int nb, hipStream_t s) {
+  k_pcg_init<T><<<nb, kBlock, 0, s>>>(L, V, zero_x0 ? 1 : 0, sc, part);
 }
 
-template <typename T, int NR>
-void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, const int32_t* mask, Scal* sc,
-                     double* part, int nb, int it, double tol, bool check_only, hipStream_t s,
-                     hipEvent_t* ev) {
-  (void)check_only;
+template <typename T>
+void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* part, int nb, int it,
+                     double tol, bool check_only, hipStream_t s, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (mask)
-    k_pcg_p1<T, NR, true><<<nb, kBlock, 0, s>>>(L, V, mask, sc, part, nb, it, tol, stamp(it, 1));
-  else
-    k_pcg_p1<T, NR, false><<<nb, kBlock, 0, s>>>(L, V, mask, sc, part, nb, it, tol, stamp(it, 1));
+  k_pcg_k1<T><<<nb, kBlock, 0, s>>>(L, V, sc, part, nb, it, tol, stamp(it, 1), check_only ? 1 : 0);
   if (ev) (void)hipEventRecord(ev[1], s);
-  k_pcg_p2<T, NR><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, stamp(it, 2));
-  k_pcg_p3<T, NR><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, tol, stamp(it, 3));
+  if (check_only) return;
+  k_pcg_k2<T><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, stamp(it, 2));
 }
 
-template void launch_pcg_init<double, 1>(const DLevel&, const PcgVecs<double>&, const int32_t*,
-                                         bool, Scal*, double*, int, hipStream_t);
-template void launch_pcg_init<double, 2>(const DLevel&, const PcgVecs<double>&, const int32_t*,
-                                         bool, Scal*, double*, int, hipStream_t);
-template void launch_pcg_init<float, 1>(const DLevel&, const PcgVecs<float>&, const int32_t*,
-                                        bool, Scal*, double*, int, hipStream_t);
-template void launch_pcg_iter<double, 1>(const DLevel&, const PcgVecs<double>&, const int32_t*,
-                                         Scal*, double*, int, int, double, bool, hipStream_t,
-                                         hipEvent_t*);
-template void launch_pcg_iter<double, 2>(const DLevel&, const PcgVecs<double>&, const int32_t*,
-                                         Scal*, double*, int, int, double, bool, hipStream_t,
-                                         hipEvent_t*);
-template void launch_pcg_iter<float, 1>(const DLevel&, const PcgVecs<float>&, const int32_t*,
-                                        Scal*, double*, int, int, double, bool, hipStream_t,
-                                        hipEvent_t*);
+template void launch_pcg_init<double>(const DLevel&, const PcgVecs<double>&, bool, Scal*, double*,
+                                      int, hipStream_t);
+template void launch_pcg_init<float>(const DLevel&, const PcgVecs<float>&, bool, Scal*, double*,
+                                     int, hipStream_t);
+template void launch_pcg_iter<double>(const DLevel&, const PcgVecs<double>&, Scal*, double*, int,
+                                      int, double, bool, hipStream_t, hipEvent_t*);
+template void launch_pcg_iter<float>(const DLevel&, const PcgVecs<float>&, Scal*, double*, int,
+                                     int, double, bool, hipStream_t, hipEvent_t*);
+
+int cheb_iterations(double tol) {
+  // error reduction 2 ((sqrt(k)-1)/(sqrt(k)+1))^m with k = 4 (interval [1/2, 2]),
+  // times sqrt(k) from the energy norm to the scaled residual
+  const double rate = 1.0 / 3.0;
+  int m = (int)std::ceil(std::log(4.0 / tol) / std::log(1.0 / rate));
+  return m < 1 ? 1 : m;
+}
+
+double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
+                    const double* invd_full, const int32_t* dir_index, const double* b, int nr,
+                    double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
+                    void* tctx) {
+  const double lo = 0.5, hi = 2.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  const int g = L.ntiles;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < iters; ++k) {
+    double ca = 0.0, cb = 1.0 / theta;
+    if (k > 0) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      ca = rn * rho;
+      cb = 2.0 * rn / delta;
+      rho = rn;
+    }
+    double* xk = x[k % 3];
+    const double* xkm = x[(k + 2) % 3];
+    double* xn = x[(k + 1) % 3];
+    hipEvent_t* ev = (timer && k > 0) ? timer(tctx) : nullptr;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (nr == 3)
+      k_cheb<3><<<g, kBlock, 0, s>>>(L, Mval, invd_int, invd_full, dir_index, b, xk, xkm, xn, ca,
+                                     cb, k == 0);
+    else
+      k_cheb<2><<<g, kBlock, 0, s>>>(L, Mval, invd_int, invd_full, dir_index, b, xk, xkm, xn, ca,
+                                     cb, k == 0);
+    if (ev) (void)hipEventRecord(ev[1], s);
+  }
+  return x[iters % 3];
+}
 
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
                               int levels, const double* ut, int64_t stride, double* tripart,
@@ -1173,16 +1160,15 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
 }
 
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
-                        int chi, const double* phi_f, const double* ut, double* rhs_vel,
-                        double* rhs_rot, hipStream_t s) {
-  k_correct_rhs<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, dir_index, dt, nu, chi, phi_f, ut,
-                                                         rhs_vel, rhs_rot);
+                        int chi, const double* phi_f, const double* ut, double* rhs,
+                        hipStream_t s) {
+  k_correct_rhs<<<row_group_grid(L.n), kBlock, 0, s>>>(L, dir_index, dt, nu, chi, phi_f, ut, rhs);
 }
 
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
-                         const double* phi_f, const double* dp, double* u_out, double* p_out,
+                         const double* phi_f, int chi, double* u_out, double* p_out,
                          hipStream_t s) {
-  k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, dp, u_out, p_out);
+  k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, chi, u_out, p_out);
 }
 
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
@@ -1190,9 +1176,6 @@ void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
 }
 void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s) {
   k_zero_masked<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, nat, n);
-}
-void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
-  k_to_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, dst, n);
 }
 void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s) {
   k_axpy_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(d, x, n);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <numeric>
+#include <stdexcept>
 
 namespace cgp {
 
@@ -182,6 +183,14 @@ Graph build_graph(const Mesh& m) {
       g.side.push_back(kw);
     }
     g.rowptr[i + 1] = (int32_t)g.col.size();
+  }
+  // greedy row tiles: <= kTileRows rows and <= kTileNnz nonzeros each
+  g.tile.assign(1, 0);
+  for (int64_t r = 0; r < n;) {
+    const int64_t start = r;
+    while (r < n && r - start < kTileRows && g.rowptr[r + 1] - g.rowptr[start] <= kTileNnz) ++r;
+    if (r == start) throw std::runtime_error("a node has more than kTileNnz neighbours");
+    g.tile.push_back((int32_t)r);
   }
   return g;
 }

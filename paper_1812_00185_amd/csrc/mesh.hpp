@@ -32,8 +32,15 @@ struct Graph {
   std::vector<int32_t> rowptr;  // [n + 1]
   std::vector<int32_t> col;     // [nnz]
   std::vector<int32_t> side;    // [2 nnz]
+  // row tiles for the LDS-staged SpMV: tile t holds rows [tile[t], tile[t+1]),
+  // at most kTileRows rows and kTileNnz nonzeros
+  std::vector<int32_t> tile;
   int64_t nnz() const { return (int64_t)col.size(); }
+  int32_t ntiles() const { return (int32_t)tile.size() - 1; }
 };
+
+constexpr int kTileRows = 256;
+constexpr int kTileNnz = 2560;
 
 struct Hierarchy {
   int levels = 0;

@@ -143,3 +143,21 @@ def test_channel_mesh_valid():
     op = fem.Operators(m)
     assert np.all(op.area > 0)
     assert abs(op.area.sum() - (2.2 * 0.41 - np.pi * 0.05 ** 2)) < 2e-3
+
+
+@pytest.mark.parametrize("name", list(MESHES) + ["channel"])
+def test_wathen_mass_matrix_spectrum(name):
+    """Wathen's bound for P1 triangles: the eigenvalues of D^-1 M (D = diag M)
+    lie in [1/2, 2], also for the principal submatrix left after removing
+    boundary rows and columns (Rayleigh quotients over a subspace)."""
+    m = MESHES[name]() if name in MESHES else channel_cylinder(h=0.06)
+    op = fem.Operators(m)
+    M = op.M.toarray()
+    d = np.diag(M)
+    lam = np.linalg.eigvalsh(M / np.sqrt(np.outer(d, d)))
+    assert lam.min() >= 0.5 - 1e-12 and lam.max() <= 2.0 + 1e-12
+    inner = _interior(m)
+    Mi = M[np.ix_(inner, inner)]
+    di = np.diag(Mi)
+    lam = np.linalg.eigvalsh(Mi / np.sqrt(np.outer(di, di)))
+    assert lam.min() >= 0.5 - 1e-12 and lam.max() <= 2.0 + 1e-12
