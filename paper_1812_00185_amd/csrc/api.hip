@@ -409,7 +409,8 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   c->tc = c->h.coarse.n_tris;
   c->ndir = (int32_t)c->h.dir_nodes.size();
   c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
-  c->nb_c = std::min(cgp::kNbMax, std::max(1, (c->nc + cgp::kBlock - 1) / cgp::kBlock));
+  // the coarse PCG product kernel requires every block to own a tile
+  c->nb_c = std::min(cgp::kNbMax, std::max(1, c->h.gc.ntiles()));
   c->cheb_iters = cgp::cheb_iterations(prob->mass_tol);
   if (c->cheb_iters > prob->mass_max_iter) {
     delete c;

@@ -89,7 +89,7 @@ void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* par
 
 // ---------------------------------------------------------------- Chebyshev mass solves
 int cheb_iterations(double tol);
-// Solves M x = b for nr (2 or 3) right-hand sides stacked [nr][n]; returns the
+// Solves M x = b for nr (2 or 3) right-hand sides interleaved [n][nr]; returns the
 // buffer (one of x[0..2]) holding the result.  `timer(tctx)`, when given,
 // supplies an event pair per product launch.
 double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
@@ -115,7 +115,7 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
                     const double* phic, double* phif, hipStream_t s);
 
 // ---------------------------------------------------------------- correction
-// rhs [3][n]: velocity right-hand sides, then (chi = 1) the rotational one
+// rhs [n][2 + chi]: velocity right-hand sides, then (chi = 1) the rotational one
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
                         int chi, const double* phi_f, const double* ut, double* rhs,
                         hipStream_t s);

@@ -128,19 +128,41 @@ __device__ __forceinline__ int stage_tile(TileStage<T>& st, const DLevel& L, con
   return s0;
 }
 
-// acc[d] = sum over the staged nonzeros of row `row` of val * g(d, col).
+constexpr int kRowBatch = 8;   // gathers of a row issued together
+
+// acc[d] = sum over the staged nonzeros [a, b) of val * g(d, col), the
+// gathers of up to kRowBatch nonzeros in flight at once (in order, so the
+// summation order is that of the row).
+template <typename T, int NR, class G>
+__device__ __forceinline__ void tile_row_range(const TileStage<T>& st, int a, int b, G g,
+                                               T (&acc)[NR]) {
+#pragma unroll
+  for (int d = 0; d < NR; ++d) acc[d] = T(0);
+  for (int s = a; s < b; s += kRowBatch) {
+    T v[kRowBatch];
+    T x[kRowBatch][NR];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      if (s + u < b) {
+        v[u] = st.val[s + u];
+        const int c = st.col[s + u];
+#pragma unroll
+        for (int d = 0; d < NR; ++d) x[u][d] = g(d, c);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (s + u < b) {
+#pragma unroll
+        for (int d = 0; d < NR; ++d) acc[d] += v[u] * x[u][d];
+      }
+  }
+}
+
 template <typename T, int NR, class G>
 __device__ __forceinline__ void tile_row(const TileStage<T>& st, const DLevel& L, int s0, int row,
                                          G g, T (&acc)[NR]) {
-#pragma unroll
-  for (int d = 0; d < NR; ++d) acc[d] = T(0);
-  const int a = L.rowptr[row] - s0, b = L.rowptr[row + 1] - s0;
-  for (int s = a; s < b; ++s) {
-    const T v = st.val[s];
-    const int c = st.col[s];
-#pragma unroll
-    for (int d = 0; d < NR; ++d) acc[d] += v * g(d, c);
-  }
+  tile_row_range<T, NR>(st, L.rowptr[row] - s0, L.rowptr[row + 1] - s0, g, acc);
 }
 
 struct SideGeo {
@@ -620,48 +642,84 @@ __global__ void __launch_bounds__(kBlock)
 k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double tol,
          int my_stamp, int check_only) {
   if (!active(sc, 0, my_stamp)) return;
-  const int64_t n = L.n;
-  const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
-  double s[3];
-  block_sums<3>(part, nb, idx, s);
-  const double bb = it == 1 ? s[2] : sc[0].bb;
-  const double rel = bb > 0.0 ? sqrt(s[1] / bb) : 0.0;
-  const bool nan = !isfinite(bb) || !isfinite(s[1]) || !isfinite(rel);
-  const bool fin = bb == 0.0 || nan || rel <= tol;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (it == 1) sc[0].bb = bb;
-    sc[0].rel = rel;
-    if (fin) {
-      sc[0].done_stamp = my_stamp;
-      sc[0].iters = it - 1;
-      sc[0].status = nan ? 2 : 0;
-    } else {
-      sc[0].rho[(it - 1) & 1] = s[0];
-    }
-  }
-  if (bb == 0.0) {  // zero right-hand side: the solution is zero
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-      V.x[i] = T(0);
-    return;
-  }
-  if (fin || check_only) return;
   __shared__ TileStage<T> st;
-  const T beta = it == 1 ? T(0) : (T)(s[0] / sc[0].rho[(it - 2) & 1]);
+  constexpr int kPer = kTileNnz / kBlock;
+  const int64_t n = L.n;
   const T* __restrict__ pold = V.p[(it - 1) & 1];
   T* __restrict__ pnew = V.p[it & 1];
   const T* __restrict__ z = V.z;
+  T beta = T(0);
   double pq = 0.0;
+  // every block owns at least one tile (nb <= ntiles); the first tile's loads
+  // are issued before the reduction of the partial sums so that both
+  // latencies overlap
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = stage_tile(st, L, V.val, r0, r1);
+    const int s0 = L.rowptr[r0], cnt = L.rowptr[r1] - s0;
+    T pv[kPer];
+    int32_t pc[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = threadIdx.x + q * kBlock;
+      if (k < cnt) {
+        pv[q] = V.val[s0 + k];
+        pc[q] = L.col[s0 + k];
+      }
+    }
     const int row = r0 + threadIdx.x;
-    if (row < r1) {
-      T q[1];
-      tile_row<T, 1>(st, L, s0, row, [&](int, int c) { return z[c] + beta * pold[c]; }, q);
-      const T pr = z[row] + beta * pold[row];
+    const bool own = row < r1;
+    int a = 0, b = 0;
+    T zr = T(0), por = T(0);
+    if (own) {
+      a = L.rowptr[row] - s0;
+      b = L.rowptr[row + 1] - s0;
+      zr = z[row];
+      por = pold[row];
+    }
+    if (t == (int)blockIdx.x) {
+      const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
+      double s[3];
+      block_sums<3>(part, nb, idx, s);
+      const double bb = it == 1 ? s[2] : sc[0].bb;
+      const double rel = bb > 0.0 ? sqrt(s[1] / bb) : 0.0;
+      const bool nan = !isfinite(bb) || !isfinite(s[1]) || !isfinite(rel);
+      const bool fin = bb == 0.0 || nan || rel <= tol;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (it == 1) sc[0].bb = bb;
+        sc[0].rel = rel;
+        if (fin) {
+          sc[0].done_stamp = my_stamp;
+          sc[0].iters = it - 1;
+          sc[0].status = nan ? 2 : 0;
+        } else {
+          sc[0].rho[(it - 1) & 1] = s[0];
+        }
+      }
+      if (bb == 0.0) {  // zero right-hand side: the solution is zero
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+          V.x[i] = T(0);
+        return;
+      }
+      if (fin || check_only) return;
+      beta = it == 1 ? T(0) : (T)(s[0] / sc[0].rho[(it - 2) & 1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = threadIdx.x + q * kBlock;
+      if (k < cnt) {
+        st.val[k] = pv[q];
+        st.col[k] = pc[q];
+      }
+    }
+    __syncthreads();
+    if (own) {
+      T acc[1];
+      tile_row_range<T, 1>(st, a, b, [&](int, int c) { return z[c] + beta * pold[c]; }, acc);
+      const T pr = zr + beta * por;
       pnew[row] = pr;
-      V.q[row] = q[0];
-      pq += (double)pr * (double)q[0];
+      V.q[row] = acc[0];
+      pq += (double)pr * (double)acc[0];
     }
   }
   const double vals[1] = {pq};
@@ -673,19 +731,36 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_k2(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my_stamp) {
   if (!active(sc, 0, my_stamp)) return;
+  const T* __restrict__ p = V.p[it & 1];
+  // the first row's operands are loaded before the reduction (latency overlap)
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  T xi = T(0), pi = T(0), ri = T(0), qi = T(0), di = T(0);
+  if (i < n) {
+    xi = V.x[i];
+    pi = p[i];
+    ri = V.r[i];
+    qi = V.q[i];
+    di = V.invd[i];
+  }
   const int idx[1] = {slot(SL_PQ, 0)};
   double pq[1];
   block_sums<1>(part, nb, idx, pq);
   const double a = sc[0].rho[(it - 1) & 1] / pq[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[0].alpha = a;
   const T alpha = (T)a;
-  const T* __restrict__ p = V.p[it & 1];
   double rz = 0.0, rr = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    V.x[i] += alpha * p[i];
-    const T r = V.r[i] - alpha * V.q[i];
+  for (; i < n; i += gridDim.x * blockDim.x) {
+    if (i != (int)(blockIdx.x * blockDim.x + threadIdx.x)) {
+      xi = V.x[i];
+      pi = p[i];
+      ri = V.r[i];
+      qi = V.q[i];
+      di = V.invd[i];
+    }
+    V.x[i] = xi + alpha * pi;
+    const T r = ri - alpha * qi;
     V.r[i] = r;
-    const T z = V.invd[i] * r;
+    const T z = di * r;
     V.z[i] = z;
     rz += (double)r * (double)z;
     rr += (double)r * (double)r;
@@ -702,6 +777,8 @@ k_pcg_k2(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my
 // [1/2, 2], so Chebyshev acceleration on that interval needs no inner
 // products: x_{k+1} = x_k + a_k (x_k - x_{k-1}) + c_k D^-1 (b - M x_k), one
 // fused kernel per iteration with the iterates in three rotating buffers.
+// Right-hand sides and iterates are interleaved per node ([n][NR]) so that a
+// gathered neighbour costs one contiguous access.
 template <int NR>
 __global__ void __launch_bounds__(kBlock)
 k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_int,
@@ -709,7 +786,6 @@ k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_i
        const double* __restrict__ b, double* __restrict__ xk, const double* __restrict__ xkm,
        double* __restrict__ xnew, double ca, double cb, int first) {
   __shared__ TileStage<double> st;
-  const int64_t n = L.n;
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
     int s0 = 0;
@@ -718,12 +794,14 @@ k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_i
     if (row >= r1) continue;
     double mx[NR];
     if (!first)
-      tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[d * n + c]; }, mx);
+      tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[(int64_t)c * NR + d]; },
+                           mx);
     const bool masked = dir_index[row] >= 0;
     const double di_int = invd_int[row], di_full = NR > 2 ? invd_full[row] : 0.0;
+    const int64_t base = (int64_t)row * NR;
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
-      const int64_t k = d * n + row;
+      const int64_t k = base + d;
       const double di = d < 2 ? di_int : di_full;
       double v;
       if (d < 2 && masked)
@@ -891,8 +969,9 @@ k_prolong(int32_t nf, const int32_t* __restrict__ pcode, const int32_t* __restri
 
 
 // ------------------------------------------------------------------ correction
-// rhs[0..2n) = -(2/3) dt G phi_f on non-Dirichlet rows (0 on Dirichlet rows),
-// rhs[2n..3n) = -nu D U~ (rotational form only); one lane group per row.
+// Mass-solve right-hand sides, interleaved per node ([n][2] or, for the
+// rotational form, [n][3]): -(2/3) dt G phi_f on non-Dirichlet rows (0 on
+// Dirichlet rows), then -nu D U~; one lane group per row.
 __global__ void __launch_bounds__(kBlock)
 k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double nu, int chi,
               const double* __restrict__ phi, const double* __restrict__ ut,
@@ -927,24 +1006,28 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double
     group_sum<3>(acc);
     if (lane == 0) {
       const bool dir = dir_index[i] >= 0;
-      rhs[i] = dir ? 0.0 : (dt / 9.0) * acc[0];
-      rhs[n + i] = dir ? 0.0 : (dt / 9.0) * acc[1];
-      if (chi) rhs[2 * n + i] = -nu * acc[2];
+      const int nr = chi ? 3 : 2;
+      rhs[(int64_t)i * nr] = dir ? 0.0 : (dt / 9.0) * acc[0];
+      rhs[(int64_t)i * nr + 1] = dir ? 0.0 : (dt / 9.0) * acc[1];
+      if (chi) rhs[(int64_t)i * nr + 2] = -nu * acc[2];
     }
   }
 }
 
-// u_out = U~ + dU, p_out = p_in + phi_f (+ dp); du holds dU (and dp at 2n)
+// u_out = U~ + dU, p_out = p_in + phi_f (+ dp); du holds (dU_x, dU_y[, dp])
+// interleaved per node
 __global__ void __launch_bounds__(kBlock)
 k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restrict__ du,
                const double* p_in, const double* __restrict__ phi, int chi,
                double* __restrict__ u_out, double* p_out) {
   const int64_t n = n32;
+  const int nr = chi ? 3 : 2;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    u_out[i] = ut[i] + du[i];
-    u_out[n + i] = ut[n + i] + du[n + i];
+    const int64_t k = (int64_t)i * nr;
+    u_out[i] = ut[i] + du[k];
+    u_out[n + i] = ut[n + i] + du[k + 1];
     const double pv = p_in[i] + phi[i];
-    p_out[i] = chi ? pv + du[2 * n + i] : pv;
+    p_out[i] = chi ? pv + du[k + 2] : pv;
   }
 }
 
