@@ -123,6 +123,8 @@ typedef struct cgp_step_stats {
   cgp_solve_stats poisson;     /* coarse pressure increment     */
   cgp_solve_stats mass[2];     /* velocity correction u, v      */
   cgp_solve_stats prot;        /* rotational pressure mass solve */
+  int32_t guess_net;           /* 1: the learned guess was used  */
+  int32_t pad_;
 } cgp_step_stats;
 
 /* Time-stepping state, device pointers owned by the caller.  The step writes
@@ -222,6 +224,52 @@ int cgp_correct(cgp_ctx* ctx, const double* u_tilde, const double* phi_f, const 
  * synchronises `stream` to fill it. */
 int cgp_project_step(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const double* f,
                      const double* guess, cgp_step_stats* stats, void* stream);
+
+/* ---- Learned initial guess for the coarse solve ------------------------
+ * Not part of the paper's method: an accelerator of step 3.  A 3-round
+ * message-passing network (hidden width 32) on the coarse node graph maps
+ * the coarse right-hand side and the last four increments (newest first) to
+ * a predicted increment; its dense layers run on BF16 MFMA with FP32
+ * accumulation.  The coarse solve then starts from the prediction only if
+ * its FP64 residual ||b - K x0|| is not larger than that of the previous
+ * increment, and always runs to pcg_tol, so the result never depends on the
+ * network beyond the solver tolerance.
+ * Parameters: CGP_NET_PARAMS float32 values, device, caller-owned, in the
+ * order W_e [32][5], c_e [32], then per round A [32][32], B [32][32],
+ * C [32][3], d [32], U [32][64], v [32], then w [32], c [1] (row-major,
+ * output x input).  `hist` is a host array of 4 device pointers [N_c]. */
+#define CGP_NET_PARAMS 12993
+
+/* Seeded fan-in uniform initialisation of a host parameter vector. */
+int cgp_net_init(float* theta_host, uint64_t seed);
+
+/* guess [N_c] (device) = the network's predicted increment. */
+int cgp_net_guess(cgp_ctx* ctx, const float* theta, const double* b_c,
+                  const double* const* hist, double* guess, void* stream);
+
+/* Gradient (device float [CGP_NET_PARAMS], may be NULL) and loss (device
+ * float, may be NULL) of the mean squared error between the prediction and
+ * target (the solved increment), both normalised by the scale of hist[0]. */
+int cgp_net_grad(cgp_ctx* ctx, const float* theta, const double* b_c,
+                 const double* const* hist, const double* target, float* grad, float* loss,
+                 void* stream);
+
+/* One Adam step (beta 0.9, 0.999, eps 1e-8; step counts from 1) on theta
+ * with moments m, v (device float [CGP_NET_PARAMS], caller-owned). */
+int cgp_net_train_step(cgp_ctx* ctx, float* theta, float* m, float* v, int32_t step, float lr,
+                       const double* b_c, const double* const* hist, const double* target,
+                       float* loss, void* stream);
+
+/* Copies whichever of cand and prev (device [N_c]) has the smaller FP64
+ * residual against the coarse system (cand on ties) into out; *chose
+ * (device int32, may be NULL) receives 0 for cand, 1 for prev. */
+int cgp_guess_guard(cgp_ctx* ctx, const double* b_c, const double* cand, const double* prev,
+                    double* out, int32_t* chose, void* stream);
+
+/* cgp_project_step with the guarded learned guess for the coarse solve;
+ * stats->guess_net reports whether the network's candidate was used. */
+int cgp_project_step_net(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const double* f,
+                         const float* theta, cgp_step_stats* stats, void* stream);
 
 /* Device buffers of the last step's intermediates (read-only views into the
  * workspace, valid until the next call on ctx): U~ [2][N_f], b_c [N_c],

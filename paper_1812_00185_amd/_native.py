@@ -23,6 +23,7 @@ CGP_K_MASS_SPMV = 1
 CGP_K_MOM_SPMV = 2
 CGP_K_COARSE_SPMV = 3
 CGP_K_MOM_ASSEMBLE = 4
+CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
 
@@ -62,11 +63,12 @@ class SolveStats(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("momentum", SolveStats * 2), ("poisson", SolveStats), ("mass", SolveStats * 2),
-                ("prot", SolveStats)]
+                ("prot", SolveStats), ("guess_net", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return dict(momentum=[s.as_dict() for s in self.momentum], poisson=self.poisson.as_dict(),
-                    mass=[s.as_dict() for s in self.mass], prot=self.prot.as_dict())
+                    mass=[s.as_dict() for s in self.mass], prot=self.prot.as_dict(),
+                    guess_net=bool(self.guess_net))
 
 
 class State(C.Structure):
@@ -93,6 +95,18 @@ SIGNATURES = [
                                    C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
     ("cgp_intermediates", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_void_p)]),
+    ("cgp_project_step_net", C.c_int, [C.c_void_p, C.POINTER(State), C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
+    ("cgp_net_init", C.c_int, [C.POINTER(C.c_float), C.c_uint64]),
+    ("cgp_net_guess", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
+                                C.c_void_p, C.c_void_p]),
+    ("cgp_net_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cgp_net_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_float, C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    ("cgp_guess_guard", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]),
     ("cgp_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("cgp_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("cgp_destroy", None, [C.c_void_p]),

@@ -16,6 +16,7 @@
 #include "cgp.h"
 #include "device.hpp"
 #include "mesh.hpp"
+#include "mpnn.hpp"
 
 using cgp::DLevel;
 using cgp::Scal;
@@ -85,6 +86,17 @@ struct cgp_ctx {
   Scal* pinned = nullptr;  // [2][8] host-pinned copies of the solver scalars
   hipEvent_t ev[2] = {nullptr, nullptr};
 
+  // learned initial guess
+  cgp::net::Buffers net;
+  __bf16* net_wb = nullptr;
+  double* net_scal = nullptr;   // (s_b, s)
+  double* net_dpart = nullptr;  // reduction scratch
+  double* net_lpart = nullptr;
+  float* net_loss = nullptr;
+  int32_t* chose = nullptr;     // guard decision
+  double* guess_tmp = nullptr;  // [N_c]
+  double hbar = 1.0;
+
   // measurement hook (cgp_timing_enable)
   int timed_id = 0;
   std::vector<hipEvent_t> tev;
@@ -140,6 +152,15 @@ size_t carve(cgp_ctx* c, void* base) {
   c->tripart = w.take<double>(3 * (size_t)c->tc);
   c->part = w.take<double>((size_t)cgp::kSlots * 2 * cgp::kNbMax);
   c->scal = w.take<Scal>(8);
+  float* netf = w.take<float>(cgp::net::workspace_floats(c->nc, (int)nnzc));
+  if (base) c->net.carve(netf, c->nc, (int)nnzc);
+  c->net_wb = w.take<__bf16>(cgp::net::kWeightsB);
+  c->net_scal = w.take<double>(4);
+  c->net_dpart = w.take<double>(2 * cgp::kNbMax);
+  c->net_lpart = w.take<double>(cgp::kNbMax);
+  c->net_loss = w.take<float>(4);
+  c->chose = w.take<int32_t>(4);
+  c->guess_tmp = w.take<double>(nc);
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
   c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
@@ -411,6 +432,19 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
   // the coarse PCG product kernel requires every block to own a tile
   c->nb_c = std::min(cgp::kNbMax, std::max(1, c->h.gc.ntiles()));
+  {  // mean coarse edge length (scale of the learned guess's edge features)
+    const cgp::Graph& g = c->h.gc;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int32_t i = 0; i < c->nc; ++i)
+      for (int32_t k = g.rowptr[i] + 1; k < g.rowptr[i + 1]; ++k) {
+        const int32_t j = g.col[k];
+        sum += std::hypot(c->h.coarse.xy[2 * j] - c->h.coarse.xy[2 * i],
+                          c->h.coarse.xy[2 * j + 1] - c->h.coarse.xy[2 * i + 1]);
+        ++cnt;
+      }
+    c->hbar = cnt ? sum / cnt : 1.0;
+  }
   c->cheb_iters = cgp::cheb_iterations(prob->mass_tol);
   if (c->cheb_iters > prob->mass_max_iter) {
     delete c;
@@ -485,6 +519,7 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   cgp::launch_mass_assemble(c->F, c->dir_index, c->Mval, c->invdM, c->invdM_int, s);
   cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
                               c->invdKc32, c->lumped_c, s);
+  cgp::net::launch_edge_features(c->C, c->hbar, c->net, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   c->assembled = true;
@@ -539,8 +574,13 @@ int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   return rc;
 }
 
-int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
-                     const double* guess, cgp_step_stats* st, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One step (Eqs. 21-26); `theta` (learned guess) or `guess` may be given.
+int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
+                 const double* guess, const float* theta, cgp_step_stats* st, void* stream) {
   if (int rc = check_ready(c)) return rc;
   if (!S || !S->u_prev || !S->u || !S->p || (c->ndir && !u_dir))
     return fail(CGP_ERR_INVALID, "null state or boundary pointer");
@@ -553,7 +593,20 @@ int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double
   if (rc < 0) return rc;
   run_restrict(c, c->ut, c->bc, s);
   double* phi_new = S->phi_hist[3];
-  cgp::launch_copy(guess ? guess : S->phi_hist[0], phi_new, c->nc, s);
+  if (theta) {
+    // learned candidate, kept only if its FP64 initial residual is not worse
+    // than that of the previous increment
+    const double* hist[4] = {S->phi_hist[0], S->phi_hist[1], S->phi_hist[2], S->phi_hist[3]};
+    cgp::net::launch_pack(theta, c->net_wb, s);
+    cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, c->bc, hist, c->hbar, c->net_dpart,
+                             c->net_scal, s);
+    cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, S->phi_hist[0], nullptr,
+                            c->guess_tmp, c->nat_c, c->net_lpart, s);
+    cgp::launch_guard(c->C, c->Kc, c->bc, c->guess_tmp, S->phi_hist[0], phi_new, c->chose,
+                      c->part, c->nb_c, s);
+  } else {
+    cgp::launch_copy(guess ? guess : S->phi_hist[0], phi_new, c->nc, s);
+  }
   rc = worst(rc, run_pcg(c, c->bc, phi_new, &T->poisson, s));
   if (rc < 0) return rc;
   cgp::launch_prolong(c->nf, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f, s);
@@ -573,8 +626,129 @@ int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double
   S->phi_hist[0] = h3;
   S->step += 1;
   HIPCHK(hipGetLastError());
-  if (st) HIPCHK(hipStreamSynchronize(s));
+  T->guess_net = 0;
+  if (st) {
+    if (theta) {
+      HIPCHK(hipMemcpyAsync(&c->pinned[15].iters, c->chose, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      T->guess_net = c->pinned[15].iters == 0 ? 1 : 0;
+    } else {
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  }
   return rc;
+}
+
+// host-side seeded uniform generator (xorshift64*)
+struct Rng {
+  uint64_t x;
+  explicit Rng(uint64_t seed) : x(seed * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull) {
+    if (!x) x = 1;
+  }
+  double uniform() {
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return (double)((x * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0);
+  }
+};
+
+int net_check(cgp_ctx* c, const float* theta, const double* b, const double* const* hist) {
+  if (int rc = check_ready(c)) return rc;
+  if (!theta || !b || !hist) return fail(CGP_ERR_INVALID, "null argument");
+  for (int k = 0; k < 4; ++k)
+    if (!hist[k]) return fail(CGP_ERR_INVALID, "null history pointer");
+  return CGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
+                     const double* guess, cgp_step_stats* st, void* stream) {
+  return project_step(c, S, u_dir, f, guess, nullptr, st, stream);
+}
+
+int cgp_project_step_net(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
+                         const float* theta, cgp_step_stats* st, void* stream) {
+  if (!theta) return fail(CGP_ERR_INVALID, "null network parameters");
+  return project_step(c, S, u_dir, f, nullptr, theta, st, stream);
+}
+
+int cgp_net_init(float* theta, uint64_t seed) {
+  if (!theta) return fail(CGP_ERR_INVALID, "null argument");
+  namespace N = cgp::net;
+  Rng rng(seed);
+  std::memset(theta, 0, sizeof(float) * N::kParams);
+  auto fill = [&](int ofs, int rows, int cols, double scale) {
+    const double lim = scale * std::sqrt(6.0 / cols);
+    for (int k = 0; k < rows * cols; ++k) theta[ofs + k] = (float)((2.0 * rng.uniform() - 1.0) * lim);
+  };
+  fill(N::kWe, 32, 5, 1.0);
+  for (int r = 0; r < N::kRounds; ++r) {
+    const int o = N::round_ofs(r);
+    fill(o + N::kA, 32, 32, 1.0);
+    fill(o + N::kBm, 32, 32, 1.0);
+    fill(o + N::kC, 32, 3, 1.0);
+    fill(o + N::kU, 32, 64, 0.1);
+  }
+  for (int k = 0; k < 32; ++k) theta[N::kW + k] = (float)((2.0 * rng.uniform() - 1.0) * 0.01);
+  return CGP_OK;
+}
+
+int cgp_net_guess(cgp_ctx* c, const float* theta, const double* b, const double* const* hist,
+                  double* guess, void* stream) {
+  if (int rc = net_check(c, theta, b, hist)) return rc;
+  if (!guess) return fail(CGP_ERR_INVALID, "null guess pointer");
+  hipStream_t s = as_stream(stream);
+  cgp::net::launch_pack(theta, c->net_wb, s);
+  cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, b, hist, c->hbar, c->net_dpart,
+                           c->net_scal, s);
+  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, hist[0], nullptr, guess, c->nat_c,
+                          c->net_lpart, s);
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
+int cgp_net_grad(cgp_ctx* c, const float* theta, const double* b, const double* const* hist,
+                 const double* target, float* grad, float* loss, void* stream) {
+  if (int rc = net_check(c, theta, b, hist)) return rc;
+  if (!target) return fail(CGP_ERR_INVALID, "null target");
+  hipStream_t s = as_stream(stream);
+  cgp::net::launch_pack(theta, c->net_wb, s);
+  cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, b, hist, c->hbar, c->net_dpart,
+                           c->net_scal, s);
+  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, hist[0], target, nullptr, nullptr,
+                          c->net_lpart, s);
+  cgp::net::launch_backward(c->C, theta, c->net_wb, c->net, c->net_lpart,
+                            loss ? loss : c->net_loss, s);
+  if (grad)
+    HIPCHK(hipMemcpyAsync(grad, c->net.grad, sizeof(float) * cgp::net::kParams,
+                          hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
+int cgp_net_train_step(cgp_ctx* c, float* theta, float* m, float* v, int32_t step, float lr,
+                       const double* b, const double* const* hist, const double* target,
+                       float* loss, void* stream) {
+  if (!m || !v || step < 1 || !(lr > 0.0f)) return fail(CGP_ERR_INVALID, "bad Adam arguments");
+  if (int rc = cgp_net_grad(c, theta, b, hist, target, nullptr, loss, stream)) return rc;
+  cgp::net::launch_adam(theta, c->net.grad, m, v, step, lr, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
+int cgp_guess_guard(cgp_ctx* c, const double* b, const double* cand, const double* prev,
+                    double* out, int32_t* chose, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!b || !cand || !prev || !out) return fail(CGP_ERR_INVALID, "null argument");
+  cgp::launch_guard(c->C, c->Kc, b, cand, prev, out, chose ? chose : c->chose, c->part, c->nb_c,
+                    as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
 }
 
 int cgp_intermediates(cgp_ctx* c, const double** ut, const double** bc, const double** phif) {

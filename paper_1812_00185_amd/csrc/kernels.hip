@@ -24,6 +24,7 @@
 
 #include "device.hpp"
 #include "mesh.hpp"
+#include "mpnn.hpp"
 
 namespace cgp {
 namespace {
@@ -1031,6 +1032,44 @@ k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restr
   }
 }
 
+
+// ------------------------------------------------------------------ guess guard
+// Partial sums of ||b - K x||^2 for two candidate initial guesses (FP64).
+__global__ void __launch_bounds__(kBlock)
+k_guard_residuals(DLevel C, const double* __restrict__ K, const double* __restrict__ b,
+                  const double* __restrict__ x0, const double* __restrict__ x1, double* part) {
+  __shared__ TileStage<double> st;
+  double rr[2] = {0.0, 0.0};
+  for (int t = blockIdx.x; t < C.ntiles; t += gridDim.x) {
+    const int r0 = C.tile[t], r1 = C.tile[t + 1];
+    const int s0 = stage_tile(st, C, K, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
+      double kx[2];
+      tile_row<double, 2>(st, C, s0, row, [&](int d, int c) { return d ? x1[c] : x0[c]; }, kx);
+      const double bv = b[row];
+#pragma unroll
+      for (int d = 0; d < 2; ++d) rr[d] += (bv - kx[d]) * (bv - kx[d]);
+    }
+  }
+  const int idx[2] = {slot(SL_RR, 0), slot(SL_RR, 1)};
+  block_store<2>(rr, part, idx);
+}
+
+// Copies the candidate with the smaller residual (x0 on ties) into out.
+__global__ void __launch_bounds__(kBlock)
+k_guard_select(int32_t n, const double* __restrict__ x0, const double* __restrict__ x1,
+               double* __restrict__ out, int32_t* chose, const double* part, int nb) {
+  const int idx[2] = {slot(SL_RR, 0), slot(SL_RR, 1)};
+  double s[2];
+  block_sums<2>(part, nb, idx, s);
+  const bool first = s[0] <= s[1] && isfinite(s[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *chose = first ? 0 : 1;
+  const double* src = first ? x0 : x1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = src[i];
+}
+
 // ------------------------------------------------------------------ small ops
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -1270,6 +1309,13 @@ void launch_residual64(const DLevel& C, const double* Kval, const double* b, con
 void launch_reduce_check(const double* part, int nb, double tol, Scal* sc, int outer,
                          hipStream_t s) {
   k_reduce_check<<<1, kBlock, 0, s>>>(part, nb, tol, sc, outer);
+}
+
+void launch_guard(const DLevel& C, const double* Kval, const double* b, const double* cand,
+                  const double* prev, double* out, int32_t* chose, double* part, int nb,
+                  hipStream_t s) {
+  k_guard_residuals<<<nb, kBlock, 0, s>>>(C, Kval, b, cand, prev, part);
+  k_guard_select<<<nb, kBlock, 0, s>>>(C.n, cand, prev, out, chose, part, nb);
 }
 
 }  // namespace cgp

@@ -174,18 +174,91 @@ class CGP:
     def new_state(self, U_prev, U, P):
         return StepState(self, U_prev, U, P)
 
-    def step(self, state: "StepState", u_dir, f=None, guess=None, stats=False):
+    def step(self, state: "StepState", u_dir, f=None, guess=None, stats=False, theta=None):
+        """One CGP step; with `theta` the coarse solve starts from the guarded
+        learned guess."""
         import torch
 
         f64 = torch.float64
         st = N.StepStats() if stats else None
-        rc = self.lib.cgp_project_step(
-            self.ctx, C.byref(state.c), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
-            _ptr(f, f64, 2 * self.nf, "f"), _ptr(guess, f64, self.nc, "guess"),
-            C.byref(st) if st is not None else None, self._stream())
+        if theta is not None:
+            rc = self.lib.cgp_project_step_net(
+                self.ctx, C.byref(state.c), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
+                _ptr(f, f64, 2 * self.nf, "f"),
+                _ptr(theta, torch.float32, N.CGP_NET_PARAMS, "theta"),
+                C.byref(st) if st is not None else None, self._stream())
+        else:
+            rc = self.lib.cgp_project_step(
+                self.ctx, C.byref(state.c), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
+                _ptr(f, f64, 2 * self.nf, "f"), _ptr(guess, f64, self.nc, "guess"),
+                C.byref(st) if st is not None else None, self._stream())
         N.check(rc)
         state.sync_from_c()
         return st.as_dict() if st is not None else rc
+
+    # -------------------------------------------------------------- learned guess
+    def net_init(self, seed=0):
+        """Device FP32 parameter vector, seeded by the library's initialiser."""
+        import torch
+
+        host = np.empty(N.CGP_NET_PARAMS, np.float32)
+        N.check(self.lib.cgp_net_init(host.ctypes.data_as(C.POINTER(C.c_float)), seed))
+        return torch.as_tensor(host, device=self.device)
+
+    def _hist(self, hist):
+        import torch
+
+        if len(hist) != 4:
+            raise ValueError("hist needs 4 increments, newest first")
+        ptrs = [_ptr(h, torch.float64, self.nc, "hist") for h in hist]
+        return (C.c_void_p * 4)(*[p.value for p in ptrs])
+
+    def net_guess(self, theta, b_c, hist, out=None):
+        import torch
+
+        out = self.zeros(self.nc) if out is None else out
+        N.check(self.lib.cgp_net_guess(
+            self.ctx, _ptr(theta, torch.float32, N.CGP_NET_PARAMS, "theta"),
+            _ptr(b_c, torch.float64, self.nc, "b_c"), self._hist(hist),
+            _ptr(out, torch.float64, self.nc, "guess"), self._stream()))
+        return out
+
+    def net_grad(self, theta, b_c, hist, target):
+        import torch
+
+        grad = torch.empty(N.CGP_NET_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        N.check(self.lib.cgp_net_grad(
+            self.ctx, _ptr(theta, torch.float32, N.CGP_NET_PARAMS, "theta"),
+            _ptr(b_c, torch.float64, self.nc, "b_c"), self._hist(hist),
+            _ptr(target, torch.float64, self.nc, "target"), _ptr(grad), _ptr(loss),
+            self._stream()))
+        return grad, loss
+
+    def net_train_step(self, theta, m, v, step, lr, b_c, hist, target, loss=None):
+        import torch
+
+        f32 = torch.float32
+        loss = torch.empty(1, dtype=f32, device=self.device) if loss is None else loss
+        N.check(self.lib.cgp_net_train_step(
+            self.ctx, _ptr(theta, f32, N.CGP_NET_PARAMS, "theta"),
+            _ptr(m, f32, N.CGP_NET_PARAMS, "m"), _ptr(v, f32, N.CGP_NET_PARAMS, "v"),
+            int(step), float(lr), _ptr(b_c, torch.float64, self.nc, "b_c"), self._hist(hist),
+            _ptr(target, torch.float64, self.nc, "target"), _ptr(loss, f32, 1, "loss"),
+            self._stream()))
+        return loss
+
+    def guess_guard(self, b_c, cand, prev, out=None):
+        import torch
+
+        f64 = torch.float64
+        out = self.zeros(self.nc) if out is None else out
+        chose = torch.zeros(1, dtype=torch.int32, device=self.device)
+        N.check(self.lib.cgp_guess_guard(
+            self.ctx, _ptr(b_c, f64, self.nc, "b_c"), _ptr(cand, f64, self.nc, "cand"),
+            _ptr(prev, f64, self.nc, "prev"), _ptr(out, f64, self.nc, "out"),
+            _ptr(chose, torch.int32, 1, "chose"), self._stream()))
+        return out, chose
 
     def timing_enable(self, kernel_id: int):
         N.check(self.lib.cgp_timing_enable(self.ctx, kernel_id))
