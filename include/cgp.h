@@ -89,7 +89,9 @@ typedef struct cgp_problem {
   double dt;             /* time step                                        */
   double nu;             /* kinematic viscosity 1/Re                         */
   double pcg_tol;        /* coarse solve: ||b - K phi||_2 <= pcg_tol ||b||_2  */
-  double inner_tol;      /* mixed: FP32 inner solve relative tolerance       */
+  double inner_tol;      /* mixed: floor of the FP32 inner relative tolerance
+                            (each inner solve targets max(inner_tol,
+                            0.3 pcg_tol ||b|| / ||r_outer||))                 */
   double mom_tol;        /* momentum BiCGSTAB relative tolerance             */
   double mass_tol;       /* mass-matrix PCG relative tolerance               */
   int32_t max_iter;      /* coarse PCG iteration cap (all inner iterations)  */

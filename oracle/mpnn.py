@@ -10,7 +10,8 @@ central differences and the GPU kernels against this module.
 
 Network (hidden width H = 32, R = 3 rounds), on the coarse node graph (edges
 = off-diagonal slots of the coarse stiffness matrix, both directions):
-  scales   s_b = rms(b) (1 if zero), s = rms(phi^n) (s_b hbar^2 if zero)
+  scales   s_b = rms(b) (1 if zero), s = rms(phi^n) (s_b / hbar^2 if zero: the
+           coarse Poisson solution scales like b / h^2)
   input    x_i = [b_i / s_b, phi^n_i / s, phi^{n-1}_i / s, phi^{n-2}_i / s, phi^{n-3}_i / s]
   edges    e_ij = [(x_j - x_i) / hbar, (y_j - y_i) / hbar, |x_j - x_i| / hbar],
            hbar = mean coarse edge length
@@ -102,7 +103,7 @@ def features(g: Graph, b, hist):
     sb = np.sqrt(np.mean(b * b))
     sb = sb if sb > 0 else 1.0
     s = np.sqrt(np.mean(hist[0] * hist[0]))
-    s = s if s > 0 else sb * g.hbar ** 2
+    s = s if s > 0 else sb / g.hbar ** 2
     X = np.stack([b / sb] + [h / s for h in hist[:4]], axis=1)
     return X, s
 

@@ -325,10 +325,13 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
       cgp::launch_pcg_init<float>(c->C, V, true, c->scal, c->part, c->nb_c, s);
       Scal out[1];
       const int budget = std::max(1, P.max_iter - inner_total);
+      // reduce the residual just enough to reach pcg_tol (with margin), but
+      // not below what FP32 resolves
+      const double eta = std::max(P.inner_tol, 0.3 * P.pcg_tol / std::max(chk.rel, 1e-300));
       int r2 = drive(c, c->scal, 1, budget + 1, 32, true,
                      [&](int it, bool chk2) {
-                       cgp::launch_pcg_iter<float>(c->C, V, c->scal, c->part, c->nb_c, it,
-                                                   P.inner_tol, chk2, s);
+                       cgp::launch_pcg_iter<float>(c->C, V, c->scal, c->part, c->nb_c, it, eta,
+                                                   chk2, s);
                      },
                      s, out);
       if (r2) return r2;

@@ -137,9 +137,19 @@ k_wgrad(int M, int rows_per_block, const float* __restrict__ dY, const float* __
 #pragma unroll
     for (int e = 0; e < 4; ++e) out[(tn * 16 + kg * 4 + e) * K + tk * 16 + lr] = acc[e];
   }
+  // bias gradient: NG row groups of NOUT columns, reduced through LDS
+  constexpr int NG = kB / NOUT;
+  __shared__ float sb[NG][NOUT];
+  {
+    const int col = threadIdx.x % NOUT, grp = threadIdx.x / NOUT;
+    float s = 0.0f;
+    for (int r = rb + grp; r < re; r += NG) s += dY[(int64_t)r * NOUT + col];
+    sb[grp][col] = s;
+  }
+  __syncthreads();
   if (threadIdx.x < NOUT) {
     float s = 0.0f;
-    for (int r = rb; r < re; ++r) s += dY[(int64_t)r * NOUT + threadIdx.x];
+    for (int g = 0; g < NG; ++g) s += sb[g][threadIdx.x];
     out[NOUT * K + threadIdx.x] = s;
   }
 }
@@ -307,7 +317,7 @@ k_net_features(int n, const double* __restrict__ part, int nblk, double hbar,
   double sb = sqrt(sbb / n);
   if (!(sb > 0.0)) sb = 1.0;
   double s = sqrt(spp / n);
-  if (!(s > 0.0)) s = sb * hbar * hbar;
+  if (!(s > 0.0)) s = sb / (hbar * hbar);  // the solution scales like b / h^2
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal[0] = sb;
     scal[1] = s;

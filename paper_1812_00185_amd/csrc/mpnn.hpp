@@ -14,7 +14,7 @@ namespace net {
 constexpr int kHidden = 32;
 constexpr int kRounds = 3;
 constexpr int kFeat = 5;
-constexpr int kRowsPerBlock = 1024;  // rows per block in the weight-gradient products
+constexpr int kRowsPerBlock = 256;  // rows per block in the weight-gradient products
 
 // flat FP32 parameter vector: W_e [32][5], c_e [32], per round
 // A [32][32], B [32][32], C [32][3], d [32], U [32][64], v [32]; w [32], c
