@@ -230,9 +230,15 @@ int cgp_project_step(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const 
 /* ---- Learned initial guess for the coarse solve ------------------------
  * Not part of the paper's method: an accelerator of step 3.  A 3-round
  * message-passing network (hidden width 32) on the coarse node graph maps
- * the coarse right-hand side and the last four increments (newest first) to
- * a predicted increment; its dense layers run on BF16 MFMA with FP32
- * accumulation.  The coarse solve then starts from the prediction only if
+ * the coarse right-hand side b and the last four solutions phi^n ... phi^{n-3}
+ * (newest first) to a predicted solution: it refines the FP64 quadratic
+ * extrapolation q = 3 phi^n - 3 phi^{n-1} + phi^{n-2} in units of
+ * s = rms(e), e = phi^n - 3 phi^{n-1} + 3 phi^{n-2} - phi^{n-3} (the error
+ * that extrapolation made one step earlier; floored at 1e-12 rms(phi^n),
+ * else rms(b) / hbar^2 with hbar the mean coarse edge length).  Node inputs:
+ * b / rms(b), (b - K q) / s, e / s, and the first and second differences of
+ * the history over their own rms; output q + s y.  Its dense layers run on
+ * BF16 MFMA with FP32 accumulation.  The coarse solve then starts from the prediction only if
  * its FP64 residual ||b - K x0|| is not larger than that of the previous
  * increment, and always runs to pcg_tol, so the result never depends on the
  * network beyond the solver tolerance.
@@ -245,13 +251,15 @@ int cgp_project_step(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const 
 /* Seeded fan-in uniform initialisation of a host parameter vector. */
 int cgp_net_init(float* theta_host, uint64_t seed);
 
-/* guess [N_c] (device) = the network's predicted increment. */
+/* guess [N_c] (device) = the network's predicted solution. */
 int cgp_net_guess(cgp_ctx* ctx, const float* theta, const double* b_c,
                   const double* const* hist, double* guess, void* stream);
 
 /* Gradient (device float [CGP_NET_PARAMS], may be NULL) and loss (device
  * float, may be NULL) of the mean squared error between the prediction and
- * target (the solved increment), both normalised by the scale of hist[0]. */
+ * target (the solved phi^{n+1}), as y against t = (target - q) / s, divided
+ * by max(1, mean t^2) so that samples whose history is dominated by solver
+ * noise carry bounded weight. */
 int cgp_net_grad(cgp_ctx* ctx, const float* theta, const double* b_c,
                  const double* const* hist, const double* target, float* grad, float* loss,
                  void* stream);

@@ -10,9 +10,21 @@ central differences and the GPU kernels against this module.
 
 Network (hidden width H = 32, R = 3 rounds), on the coarse node graph (edges
 = off-diagonal slots of the coarse stiffness matrix, both directions):
-  scales   s_b = rms(b) (1 if zero), s = rms(phi^n) (s_b / hbar^2 if zero: the
-           coarse Poisson solution scales like b / h^2)
-  input    x_i = [b_i / s_b, phi^n_i / s, phi^{n-1}_i / s, phi^{n-2}_i / s, phi^{n-3}_i / s]
+  history  q = 3 phi^n - 3 phi^{n-1} + phi^{n-2} (quadratic extrapolation in
+           time), e = phi^n - 3 phi^{n-1} + 3 phi^{n-2} - phi^{n-3} (the error
+           the same extrapolation made for phi^n), d_1 = phi^n - phi^{n-1},
+           d_2 = phi^n - 2 phi^{n-1} + phi^{n-2}
+  residual rho = b - K q, K the solver's coarse operator (Eq. 23 with the
+           phi = 0 rows and columns replaced by identity)
+  scales   s_b = rms(b) (1 if zero); s = max(rms(e), 1e-12 rms(phi^n)) (the
+           floor keeps s above the rounding level of e), or s_b / hbar^2 if
+           that is zero (the coarse Poisson solution scales like b / h^2);
+           s_k = rms(d_k) (1 if zero)
+  input    x_i = [b_i / s_b, rho_i / s, e_i / s, d_1,i / s_1, d_2,i / s_2]
+           The network refines the FP64 extrapolation q in units of its
+           expected error, so a BF16 network never has to resolve the small
+           step-to-step change of phi against phi itself; K t = rho / s holds
+           for the target t below.
   edges    e_ij = [(x_j - x_i) / hbar, (y_j - y_i) / hbar, |x_j - x_i| / hbar],
            hbar = mean coarse edge length
   encoder  h_i = relu(W_e x_i + c_e)
@@ -21,8 +33,11 @@ Network (hidden width H = 32, R = 3 rounds), on the coarse node graph (edges
            a_i = (1 / deg_i) sum_{j in N(i)} m_ij
            h_i <- h_i + relu(U_r [h_i; a_i] + v_r)
   decoder  y_i = w . h_i + c
-  guess    g_i = phi^n_i + s y_i
-  loss     L = (1/N) sum_i (y_i - t_i)^2,  t_i = (phi^{n+1}_i - phi^n_i) / s
+  guess    g_i = q_i + s y_i
+  loss     L = (1/N) sum_i (y_i - t_i)^2 / max(1, (1/N) sum_i t_i^2),
+           t_i = (phi^{n+1}_i - q_i) / s; the per-sample normaliser bounds
+           the weight of steps whose history is dominated by the solver
+           noise of the previous solves (then e is tiny and t large)
 Flat parameter order: W_e (H x 5), c_e (H), then per round A (H x H), B (H x H),
 C (H x 3), d (H), U (H x 2H), v (H), then w (H), c (1); matrices row-major
 (output x input).
@@ -30,6 +45,7 @@ C (H x 3), d (H), U (H x 2H), v (H), then w (H), c (1); matrices row-major
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 H = 32
 ROUNDS = 3
@@ -79,11 +95,18 @@ def init_params(seed=0):
 
 class Graph:
     """Directed edges (i -> j) of the coarse node graph, grouped by i with j
-    ascending, and their features."""
+    ascending, their features, and the solver's coarse operator (K with the
+    rows and columns of `natural` nodes, where phi = 0, replaced by
+    identity)."""
 
-    def __init__(self, xy, adjacency):
-        A = adjacency.tocsr()
+    def __init__(self, xy, K, natural=None):
+        A = K.tocsr()
         A.sort_indices()
+        if natural is not None and np.any(natural):
+            keep = sp.diags((~np.asarray(natural, bool)).astype(np.float64))
+            self.op = (keep @ A @ keep + sp.diags(np.asarray(natural, np.float64))).tocsr()
+        else:
+            self.op = A
         n = A.shape[0]
         rows = np.repeat(np.arange(n), np.diff(A.indptr))
         keep = rows != A.indices
@@ -97,15 +120,26 @@ class Graph:
         self.e = np.stack([d[:, 0], d[:, 1], length], axis=1) / self.hbar
 
 
+def rms(v):
+    return float(np.sqrt(np.mean(v * v)))
+
+
 def features(g: Graph, b, hist):
-    """Node inputs [N, 5] and the scale s (hist: newest first)."""
+    """Node inputs [N, 5], the extrapolation q and the scale s (hist: phi^n,
+    ..., phi^{n-3})."""
     b = np.asarray(b, np.float64)
-    sb = np.sqrt(np.mean(b * b))
-    sb = sb if sb > 0 else 1.0
-    s = np.sqrt(np.mean(hist[0] * hist[0]))
-    s = s if s > 0 else sb / g.hbar ** 2
-    X = np.stack([b / sb] + [h / s for h in hist[:4]], axis=1)
-    return X, s
+    p0, p1, p2, p3 = [np.asarray(h, np.float64) for h in hist[:4]]
+    q = 3.0 * p0 - 3.0 * p1 + p2
+    e = p0 - 3.0 * p1 + 3.0 * p2 - p3
+    d1 = p0 - p1
+    d2 = p0 - 2.0 * p1 + p2
+    sb = rms(b) or 1.0
+    s = max(rms(e), 1e-12 * rms(p0)) or sb / g.hbar ** 2
+    s1 = rms(d1) or 1.0
+    s2 = rms(d2) or 1.0
+    rho = b - g.op @ q
+    X = np.stack([b / sb, rho / s, e / s, d1 / s1, d2 / s2], axis=1)
+    return X, q, s
 
 
 def relu(z):
@@ -137,7 +171,7 @@ def forward(theta, g: Graph, X):
 
 def loss(theta, g, X, t):
     y, _ = forward(theta, g, X)
-    return float(np.mean((y - t) ** 2))
+    return float(np.mean((y - t) ** 2) / max(1.0, np.mean(t * t)))
 
 
 def backward(theta, g: Graph, cache, dy):
@@ -175,11 +209,12 @@ def backward(theta, g: Graph, cache, dy):
 
 
 def loss_grad(theta, g, X, t):
-    """Loss and its gradient (mean squared error on the normalised correction)."""
+    """Loss and its gradient (normalised mean squared error on the correction)."""
     y, cache = forward(theta, g, X)
     n = y.shape[0]
-    L = float(np.mean((y - t) ** 2))
-    return L, backward(theta, g, cache, 2.0 * (y - t) / n)
+    w = 1.0 / max(1.0, float(np.mean(t * t)))
+    L = float(np.mean((y - t) ** 2)) * w
+    return L, backward(theta, g, cache, 2.0 * w * (y - t) / n)
 
 
 def adam_step(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -191,7 +226,12 @@ def adam_step(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     theta[...] = theta - lr * mh / (np.sqrt(vh) + eps)
 
 
+def target(q, s, phi_next):
+    """Normalised training target of a solved phi^{n+1}."""
+    return (np.asarray(phi_next, np.float64) - q) / s
+
+
 def guess(theta, g, b, hist):
-    X, s = features(g, b, hist)
+    X, q, s = features(g, b, hist)
     y, _ = forward(theta, g, X)
-    return hist[0] + s * y
+    return q + s * y

@@ -89,7 +89,7 @@ struct cgp_ctx {
   // learned initial guess
   cgp::net::Buffers net;
   __bf16* net_wb = nullptr;
-  double* net_scal = nullptr;   // (s_b, s)
+  double* net_scal = nullptr;   // (s_b, s, s_1, s_2)
   double* net_dpart = nullptr;  // reduction scratch
   double* net_lpart = nullptr;
   float* net_loss = nullptr;
@@ -156,8 +156,8 @@ size_t carve(cgp_ctx* c, void* base) {
   if (base) c->net.carve(netf, c->nc, (int)nnzc);
   c->net_wb = w.take<__bf16>(cgp::net::kWeightsB);
   c->net_scal = w.take<double>(4);
-  c->net_dpart = w.take<double>(2 * cgp::kNbMax);
-  c->net_lpart = w.take<double>(cgp::kNbMax);
+  c->net_dpart = w.take<double>(5 * cgp::kNbMax);
+  c->net_lpart = w.take<double>(2 * cgp::kNbMax);
   c->net_loss = w.take<float>(4);
   c->chose = w.take<int32_t>(4);
   c->guess_tmp = w.take<double>(nc);
@@ -601,10 +601,10 @@ int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
     // than that of the previous increment
     const double* hist[4] = {S->phi_hist[0], S->phi_hist[1], S->phi_hist[2], S->phi_hist[3]};
     cgp::net::launch_pack(theta, c->net_wb, s);
-    cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, c->bc, hist, c->hbar, c->net_dpart,
-                             c->net_scal, s);
-    cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, S->phi_hist[0], nullptr,
-                            c->guess_tmp, c->nat_c, c->net_lpart, s);
+    cgp::net::launch_forward(c->C, c->Kc, theta, c->net_wb, c->net, c->bc, hist, c->hbar,
+                             c->net_dpart, c->net_scal, s);
+    cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, nullptr, c->guess_tmp, c->nat_c,
+                            c->net_lpart, s);
     cgp::launch_guard(c->C, c->Kc, c->bc, c->guess_tmp, S->phi_hist[0], phi_new, c->chose,
                       c->part, c->nb_c, s);
   } else {
@@ -707,9 +707,9 @@ int cgp_net_guess(cgp_ctx* c, const float* theta, const double* b, const double*
   if (!guess) return fail(CGP_ERR_INVALID, "null guess pointer");
   hipStream_t s = as_stream(stream);
   cgp::net::launch_pack(theta, c->net_wb, s);
-  cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, b, hist, c->hbar, c->net_dpart,
-                           c->net_scal, s);
-  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, hist[0], nullptr, guess, c->nat_c,
+  cgp::net::launch_forward(c->C, c->Kc, theta, c->net_wb, c->net, b, hist, c->hbar,
+                           c->net_dpart, c->net_scal, s);
+  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, nullptr, guess, c->nat_c,
                           c->net_lpart, s);
   HIPCHK(hipGetLastError());
   return CGP_OK;
@@ -721,9 +721,9 @@ int cgp_net_grad(cgp_ctx* c, const float* theta, const double* b, const double* 
   if (!target) return fail(CGP_ERR_INVALID, "null target");
   hipStream_t s = as_stream(stream);
   cgp::net::launch_pack(theta, c->net_wb, s);
-  cgp::net::launch_forward(c->C, theta, c->net_wb, c->net, b, hist, c->hbar, c->net_dpart,
-                           c->net_scal, s);
-  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, hist[0], target, nullptr, nullptr,
+  cgp::net::launch_forward(c->C, c->Kc, theta, c->net_wb, c->net, b, hist, c->hbar,
+                           c->net_dpart, c->net_scal, s);
+  cgp::net::launch_decode(c->C, theta, c->net, c->net_scal, target, nullptr, nullptr,
                           c->net_lpart, s);
   cgp::net::launch_backward(c->C, theta, c->net_wb, c->net, c->net_lpart,
                             loss ? loss : c->net_loss, s);

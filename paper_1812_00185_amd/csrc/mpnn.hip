@@ -3,11 +3,14 @@
 // forward, backward and Adam, for gfx950.
 //
 // Network (per node i, edges = off-diagonal CSR slots of the coarse graph):
-//   x_i = [b_i/s_b, phi^n_i/s, phi^{n-1}_i/s, phi^{n-2}_i/s, phi^{n-3}_i/s]
+//   q = 3 phi^n - 3 phi^{n-1} + phi^{n-2} (quadratic extrapolation in time),
+//   e = phi^n - 3 phi^{n-1} + 3 phi^{n-2} - phi^{n-3} (its last error),
+//   x_i = [b_i/s_b, (b - K q)_i/s, e_i/s, d1_i/s_1, d2_i/s_2], s ~ rms(e),
+//   d1, d2 the first and second differences of the history
 //   h = relu(W_e x + c_e)
 //   round r: p = A_r h, q = B_r h, m_ij = relu(p_i + q_j + C_r e_ij + d_r),
 //            a_i = mean_j m_ij, h <- h + relu(U_r [h; a] + v_r)
-//   y = w . h + c,  guess = phi^n + s y
+//   y = w . h + c,  guess = q + s y
 // Dense layers run on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulate);
 // since the message is linear before its activation, the only dense
 // products are per node (p, q together as one 32 -> 64 layer; the update as
@@ -274,76 +277,129 @@ __global__ void k_edge_grad_reduce(const float* __restrict__ part, int nblk,
 }
 
 // ---------------------------------------------------------------- features, decoder, loss
-// partial sums of b^2 and phi^n^2 (double)
+// Per-block partial sums (double) of b^2, e^2, (phi^n)^2, d1^2, d2^2 with
+// e = phi^n - 3 phi^{n-1} + 3 phi^{n-2} - phi^{n-3}, d1 = phi^n - phi^{n-1},
+// d2 = phi^n - 2 phi^{n-1} + phi^{n-2}.
+constexpr int kStats = 5;
 __global__ void __launch_bounds__(kB)
-k_net_stats(int n, const double* __restrict__ b, const double* __restrict__ phi0,
-            double* __restrict__ part) {
-  __shared__ double sh[2][kB / 64];
-  double sb = 0.0, sp = 0.0;
+k_net_stats(int n, const double* __restrict__ b, const double* __restrict__ h0,
+            const double* __restrict__ h1, const double* __restrict__ h2,
+            const double* __restrict__ h3, double* __restrict__ part) {
+  __shared__ double sh[kStats][kB / 64];
+  double acc[kStats] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    sb += b[i] * b[i];
-    sp += phi0[i] * phi0[i];
+    const double p0 = h0[i], p1 = h1[i], p2 = h2[i], p3 = h3[i];
+    const double e = p0 - 3.0 * p1 + 3.0 * p2 - p3;
+    const double d1 = p0 - p1, d2 = p0 - 2.0 * p1 + p2;
+    acc[0] += b[i] * b[i];
+    acc[1] += e * e;
+    acc[2] += p0 * p0;
+    acc[3] += d1 * d1;
+    acc[4] += d2 * d2;
   }
-  sb = wave_sumd(sb);
-  sp = wave_sumd(sp);
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = sb;
-    sh[1][threadIdx.x >> 6] = sp;
+#pragma unroll
+  for (int k = 0; k < kStats; ++k) {
+    const double v = wave_sumd(acc[k]);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0;
-    for (int w = 0; w < kB / 64; ++w) {
-      a += sh[0][w];
-      c += sh[1][w];
-    }
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = c;
+  if (threadIdx.x < kStats) {
+    double a = 0.0;
+    for (int w = 0; w < kB / 64; ++w) a += sh[threadIdx.x][w];
+    part[kStats * blockIdx.x + threadIdx.x] = a;
   }
 }
 
-// scales (every block sums the partials in order) and the padded inputs
-// Xf[i][0..31]; block 0 stores (s_b, s) in scal[0..1].
+// Scales (every block sums the partials in order), the quadratic
+// extrapolation q = 3 phi^n - 3 phi^{n-1} + phi^{n-2} and the padded inputs
+// Xf[i][0..31] = [b/s_b, (b - K q)/s, e/s, d1/s_1, d2/s_2, 0...] with
+// s = max(rms(e), 1e-12 rms(phi^n)), else s_b / hbar^2 (the coarse solution
+// scales like b / h^2), s_k = rms(d_k) (1 if zero); K is the solver's coarse
+// operator.  Block 0 stores (s_b, s, s_1, s_2) in scal[0..3].
 __global__ void __launch_bounds__(kB)
-k_net_features(int n, const double* __restrict__ part, int nblk, double hbar,
-               const double* __restrict__ b, const double* __restrict__ h0,
-               const double* __restrict__ h1, const double* __restrict__ h2,
-               const double* __restrict__ h3, float* __restrict__ Xf, double* __restrict__ scal) {
-  double sbb = 0.0, spp = 0.0;
-  for (int k = 0; k < nblk; ++k) {
-    sbb += part[2 * k];
-    spp += part[2 * k + 1];
-  }
-  double sb = sqrt(sbb / n);
+k_net_features(DLevel C, const double* __restrict__ K, const double* __restrict__ part,
+               int nblk, double hbar, const double* __restrict__ b,
+               const double* __restrict__ h0, const double* __restrict__ h1,
+               const double* __restrict__ h2, const double* __restrict__ h3,
+               float* __restrict__ Xf, double* __restrict__ qout, double* __restrict__ scal) {
+  const int n = C.n;
+  double t[kStats] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < nblk; ++k)
+#pragma unroll
+    for (int j = 0; j < kStats; ++j) t[j] += part[kStats * k + j];
+  double sb = sqrt(t[0] / n);
   if (!(sb > 0.0)) sb = 1.0;
-  double s = sqrt(spp / n);
-  if (!(s > 0.0)) s = sb / (hbar * hbar);  // the solution scales like b / h^2
+  double s = fmax(sqrt(t[1] / n), 1e-12 * sqrt(t[2] / n));
+  if (!(s > 0.0)) s = sb / (hbar * hbar);
+  double s1 = sqrt(t[3] / n), s2 = sqrt(t[4] / n);
+  if (!(s1 > 0.0)) s1 = 1.0;
+  if (!(s2 > 0.0)) s2 = 1.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal[0] = sb;
     scal[1] = s;
+    scal[2] = s1;
+    scal[3] = s2;
   }
-  const double isb = 1.0 / sb, is = 1.0 / s;
+  const double isb = 1.0 / sb, is = 1.0 / s, is1 = 1.0 / s1, is2 = 1.0 / s2;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double kq = 0.0;
+    for (int r = C.rowptr[i]; r < C.rowptr[i + 1]; ++r) {
+      const int j = C.col[r];
+      kq += K[r] * (3.0 * h0[j] - 3.0 * h1[j] + h2[j]);
+    }
+    const double p0 = h0[i], p1 = h1[i], p2 = h2[i];
+    const double q = 3.0 * p0 - 3.0 * p1 + p2;
+    qout[i] = q;
     float* x = Xf + (int64_t)i * 32;
     x[0] = (float)(b[i] * isb);
-    x[1] = (float)(h0[i] * is);
-    x[2] = (float)(h1[i] * is);
-    x[3] = (float)(h2[i] * is);
-    x[4] = (float)(h3[i] * is);
+    x[1] = (float)((b[i] - kq) * is);
+    x[2] = (float)((p0 - 3.0 * p1 + 3.0 * p2 - h3[i]) * is);
+    x[3] = (float)((p0 - p1) * is1);
+    x[4] = (float)((p0 - 2.0 * p1 + p2) * is2);
 #pragma unroll
     for (int k = 5; k < 32; ++k) x[k] = 0.0f;
   }
 }
 
-// y_i = w . h_i + c; with a target: dy_i = 2 (y_i - t_i) / n, t_i = (phi_t - phi^n)/s,
-// and per-block loss partials; without: guess_i = phi^n_i + s y_i.
+// Per-block partial sums of t_i^2, t_i = (phi_t - q_i)/s, into tpart.
+__global__ void __launch_bounds__(kB)
+k_target_sq(int n, const double* __restrict__ q, const double* __restrict__ scal,
+            const double* __restrict__ target, double* __restrict__ tpart) {
+  __shared__ double sh[kB / 64];
+  const double is = 1.0 / scal[1];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double t = (target[i] - q[i]) * is;
+    acc += t * t;
+  }
+  acc = wave_sumd(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int k = 0; k < kB / 64; ++k) a += sh[k];
+    tpart[blockIdx.x] = a;
+  }
+}
+
+// y_i = w . h_i + c.  With a target: t_i = (phi_t - q_i)/s, the sample weight
+// 1 / max(1, mean t^2) (from the nblk partials in tpart, summed in order by
+// every block), dy_i = 2 wgt (y_i - t_i) / n and per-block partials of
+// wgt (y_i - t_i)^2 in lpart.  Without: guess_i = q_i + s y_i.
 __global__ void __launch_bounds__(kB)
 k_decoder(int n, const float* __restrict__ Hf, const float* __restrict__ w, const float* __restrict__ c,
-          const double* __restrict__ scal, const double* __restrict__ phi0,
-          const double* __restrict__ target, float* __restrict__ dy, double* __restrict__ guess,
-          const uint8_t* __restrict__ nat, double* __restrict__ lpart) {
+          const double* __restrict__ scal, const double* __restrict__ q,
+          const double* __restrict__ target, const double* __restrict__ tpart, int nblk,
+          float* __restrict__ dy, double* __restrict__ guess, const uint8_t* __restrict__ nat,
+          double* __restrict__ lpart) {
   __shared__ double sh[kB / 64];
   const double s = scal[1];
+  double wgt = 1.0;
+  if (target) {
+    double tt = 0.0;
+    for (int k = 0; k < nblk; ++k) tt += tpart[k];
+    wgt = 1.0 / fmax(1.0, tt / n);
+  }
   double lsum = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const float* h = Hf + (int64_t)i * 32;
@@ -351,12 +407,12 @@ k_decoder(int n, const float* __restrict__ Hf, const float* __restrict__ w, cons
 #pragma unroll
     for (int k = 0; k < 32; ++k) y += w[k] * h[k];
     if (target) {
-      const double t = (target[i] - phi0[i]) / s;
+      const double t = (target[i] - q[i]) / s;
       const double r = (double)y - t;
       lsum += r * r;
-      dy[i] = (float)(2.0 * r / n);
+      dy[i] = (float)(2.0 * wgt * r / n);
     } else {
-      guess[i] = (nat && nat[i]) ? 0.0 : phi0[i] + s * (double)y;
+      guess[i] = (nat && nat[i]) ? 0.0 : q[i] + s * (double)y;
     }
   }
   if (!target) return;
@@ -366,7 +422,7 @@ k_decoder(int n, const float* __restrict__ Hf, const float* __restrict__ w, cons
   if (threadIdx.x == 0) {
     double a = 0.0;
     for (int k = 0; k < kB / 64; ++k) a += sh[k];
-    lpart[blockIdx.x] = a;
+    lpart[blockIdx.x] = wgt * a;
   }
 }
 
@@ -493,29 +549,18 @@ inline int nblocks(int64_t work, int per, int cap = 4096) {
 namespace net {
 
 size_t workspace_floats(int n, int nnz) {
-  const size_t N = n;
-  return 32 * N                 // Xf
-         + 32 * N               // Z0
-         + 32 * N * (kRounds + 1)  // H
-         + 64 * N * kRounds     // PQ
-         + 32 * N * kRounds     // A
-         + 32 * N * kRounds     // Z
-         + N                    // dy
-         + 32 * N * 3           // dH, dHb, dZ
-         + 64 * N * 2           // dHA, dPQ
-         + 4 * (size_t)nnz      // edge features
-         + N                    // deg_inv
-         + kParams              // grad
-         + (size_t)nblocks(n, kRowsPerBlock) * (64 * 64 + 64) + 1024  // weight-grad partials
-         + (size_t)nblocks(n, kB / 32) * 128 + 64;                   // edge / decoder partials
+  Buffers B;
+  return B.carve(nullptr, n, nnz);
 }
 
-void Buffers::carve(float* base, int n, int nnz) {
+// Lays the buffers out from base (64-float aligned each) and returns the
+// number of floats used; with base == nullptr only the size is computed.
+size_t Buffers::carve(float* base, int n, int nnz) {
   const size_t N = n;
-  float* p = base;
+  size_t used = 0;
   auto take = [&](size_t k) {
-    float* q = p;
-    p += (k + 63) & ~(size_t)63;
+    float* q = base ? base + used : nullptr;
+    used += (k + 63) & ~(size_t)63;
     return q;
   };
   Xf = take(32 * N);
@@ -533,8 +578,10 @@ void Buffers::carve(float* base, int n, int nnz) {
   ef = reinterpret_cast<float4*>(take(4 * (size_t)nnz));
   deg_inv = take(N);
   grad = take(kParams);
-  wpart = take((size_t)nblocks(n, kRowsPerBlock) * (64 * 64 + 64) + 1024);
-  epart = take((size_t)nblocks(n, kB / 32) * 128 + 64);
+  wpart = take((size_t)nblocks(n, kRowsPerBlock) * (64 * 64 + 64));
+  epart = take((size_t)nblocks(n, kB / 32) * 128);
+  q = reinterpret_cast<double*>(take(2 * N));
+  return used;
 }
 
 void launch_edge_features(const DLevel& C, double hbar, const Buffers& B, hipStream_t s) {
@@ -545,14 +592,14 @@ void launch_pack(const float* theta, __bf16* wb, hipStream_t s) {
   k_pack_weights<<<8, kB, 0, s>>>(theta, wb);
 }
 
-void launch_forward(const DLevel& C, const float* th, const __bf16* wb, const Buffers& B,
-                    const double* b, const double* const hist[4], double hbar, double* dpart,
-                    double* scal, hipStream_t s) {
+void launch_forward(const DLevel& C, const double* Kval, const float* th, const __bf16* wb,
+                    const Buffers& B, const double* b, const double* const hist[4], double hbar,
+                    double* dpart, double* scal, hipStream_t s) {
   const int n = C.n;
   const int nb = nblocks(n, kB, 1024);
-  k_net_stats<<<nb, kB, 0, s>>>(n, b, hist[0], dpart);
-  k_net_features<<<nb, kB, 0, s>>>(n, dpart, nb, hbar, b, hist[0], hist[1], hist[2], hist[3],
-                                   B.Xf, scal);
+  k_net_stats<<<nb, kB, 0, s>>>(n, b, hist[0], hist[1], hist[2], hist[3], dpart);
+  k_net_features<<<nb, kB, 0, s>>>(C, Kval, dpart, nb, hbar, b, hist[0], hist[1], hist[2],
+                                   hist[3], B.Xf, B.q, scal);
   const int gd = nblocks(n, 64);
   k_dense<32, 0, 32, 1><<<gd, kB, 0, s>>>(n, B.Xf, nullptr, wb + kWeB, th + kCe, nullptr, B.Z0,
                                           B.H[0]);
@@ -569,11 +616,12 @@ void launch_forward(const DLevel& C, const float* th, const __bf16* wb, const Bu
 }
 
 void launch_decode(const DLevel& C, const float* th, const Buffers& B, const double* scal,
-                   const double* phi0, const double* target, double* guess, const uint8_t* nat,
-                   double* lpart, hipStream_t s) {
+                   const double* target, double* guess, const uint8_t* nat, double* lpart,
+                   hipStream_t s) {
   const int nb = nblocks(C.n, kB, 1024);
-  k_decoder<<<nb, kB, 0, s>>>(C.n, B.H[kRounds], th + kW, th + kCd, scal, phi0, target, B.dy,
-                              guess, nat, lpart);
+  if (target) k_target_sq<<<nb, kB, 0, s>>>(C.n, B.q, scal, target, lpart + nb);
+  k_decoder<<<nb, kB, 0, s>>>(C.n, B.H[kRounds], th + kW, th + kCd, scal, B.q, target,
+                              lpart + nb, nb, B.dy, guess, nat, lpart);
 }
 
 void launch_backward(const DLevel& C, const float* th, const __bf16* wb, const Buffers& B,

@@ -59,22 +59,25 @@ struct Buffers {
   float* deg_inv = nullptr;
   float* grad = nullptr;
   float *wpart = nullptr, *epart = nullptr;
-  void carve(float* base, int n, int nnz);
+  double* q = nullptr;  // quadratic extrapolation of the history [n]
+  size_t carve(float* base, int n, int nnz);
 };
 
 size_t workspace_floats(int n, int nnz);
 
 void launch_edge_features(const DLevel& C, double hbar, const Buffers& B, hipStream_t s);
 void launch_pack(const float* theta, __bf16* wb, hipStream_t s);
-// scales, inputs, encoder and the three rounds; dpart: >= 2 * 1024 doubles
-// of reduction scratch; scal[0..1] receives (s_b, s)
-void launch_forward(const DLevel& C, const float* theta, const __bf16* wb, const Buffers& B,
-                    const double* b, const double* const hist[4], double hbar, double* dpart,
-                    double* scal, hipStream_t s);
-// decoder: with a target the loss partials and dy, else the guess
+// scales, the extrapolation B.q, inputs, encoder and the three rounds; Kval:
+// the solver's coarse operator (residual feature); dpart: >= 5 * 1024
+// doubles of reduction scratch; scal[0..3] receives (s_b, s, s_1, s_2)
+void launch_forward(const DLevel& C, const double* Kval, const float* theta, const __bf16* wb,
+                    const Buffers& B, const double* b, const double* const hist[4], double hbar,
+                    double* dpart, double* scal, hipStream_t s);
+// decoder: with a target the loss partials and dy, else the guess; lpart:
+// >= 2 * 1024 doubles
 void launch_decode(const DLevel& C, const float* theta, const Buffers& B, const double* scal,
-                   const double* phi0, const double* target, double* guess, const uint8_t* nat,
-                   double* lpart, hipStream_t s);
+                   const double* target, double* guess, const uint8_t* nat, double* lpart,
+                   hipStream_t s);
 void launch_backward(const DLevel& C, const float* theta, const __bf16* wb, const Buffers& B,
                      const double* lpart, float* loss, hipStream_t s);
 void launch_adam(float* theta, const float* grad, float* m, float* v, int step, float lr,

@@ -94,13 +94,14 @@ def train(g: CGP, runs, epochs=8, lr=1e-3, seed=0, log=None, skip=4):
 
 
 def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
-    """Time to tolerance of the coarse solve along a fresh run, three ways on
+    """Time to tolerance of the coarse solve along a fresh run, four ways on
     the same right-hand side and to the same FP64 tolerance: plain FP64 PCG
-    from the previous increment (solver g), the guarded learned guess with
-    FP64 PCG (g), and the guarded learned guess with mixed-precision
-    refinement (solver gm, same mesh).  The run advances with the plain
-    solution.  Returns per-step records and means over the steps after
-    `warm`."""
+    from the previous increment (solver g); the guarded quadratic
+    extrapolation 3 phi^n - 3 phi^{n-1} + phi^{n-2} with FP64 PCG (a
+    network-free point of comparison); the guarded learned guess with FP64
+    PCG (g); and the guarded learned guess with mixed-precision refinement
+    (solver gm, same mesh).  The run advances with the plain solution.
+    Returns per-step records and means over the steps after `warm`."""
     import torch
 
     xyd = g.fine_xy[g.dirichlet_nodes]
@@ -123,6 +124,11 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         st = solver.pcg_solve(b, phi)
         return phi, chose, st
 
+    def extrap_solve():
+        q = 3.0 * hist[0] - 3.0 * hist[1] + hist[2]
+        phi, _ = g.guess_guard(b, q, hist[0])
+        return g.pcg_solve(b, phi)
+
     for n in range(steps):
         uD = g.to_device(workload.dirichlet_values(xyd, (n + 1) * workload.dt))
         Ut, _ = g.momentum(U_prev, U, P, uD)
@@ -130,10 +136,12 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         hist = [phis[-k] if len(phis) >= k else zeros for k in range(1, 5)]
         phi_a = hist[0].clone()
         st_a, ms_a = timed(lambda: g.pcg_solve(b, phi_a))
+        st_q, ms_q = timed(extrap_solve)
         (phi_b, chose, st_b), ms_b = timed(lambda: learned_solve(g))
         (phi_c, _, st_c), ms_c = timed(lambda: learned_solve(gm))
         na = torch.linalg.norm(phi_a)
-        rec.append(dict(iters_plain=st_a["iters"], iters_learned=st_b["iters"],
+        rec.append(dict(iters_plain=st_a["iters"], iters_extrap=st_q["iters"], ms_extrap=ms_q,
+                        iters_learned=st_b["iters"],
                         iters_learned_mixed=st_c["iters"], outer=st_c["outer_iters"],
                         ms_plain=ms_a, ms_learned=ms_b, ms_learned_mixed=ms_c,
                         accepted=int(chose.item() == 0), res_plain=st_a["rel_res"],
@@ -145,8 +153,8 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         U_prev, U = U, U_new
         phis.append(phi_a)
     tail = rec[warm:] if len(rec) > warm else rec
-    keys = ("iters_plain", "iters_learned", "iters_learned_mixed", "ms_plain", "ms_learned",
-            "ms_learned_mixed", "accepted")
+    keys = ("iters_plain", "iters_extrap", "iters_learned", "iters_learned_mixed", "ms_plain",
+            "ms_extrap", "ms_learned", "ms_learned_mixed", "accepted")
     summary = {k: float(np.mean([r[k] for r in tail])) for k in keys}
     summary["steps"] = len(tail)
     for k in ("res_plain", "res_learned", "res_learned_mixed", "diff", "diff_mixed"):

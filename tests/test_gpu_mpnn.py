@@ -46,9 +46,9 @@ def test_forward_matches_fp64_network():
     g, o, graph, theta, b, hist = setup()
     out = g.net_guess(g.to_device(theta).float(), g.to_device(b), [g.to_device(h) for h in hist])
     torch.cuda.synchronize()
-    X, s = mpnn.features(graph, b, np.array(hist))
+    X, q, s = mpnn.features(graph, b, np.array(hist))
     y_o, _ = mpnn.forward(theta.astype(np.float64), graph, X)
-    y_g = (out.cpu().numpy() - hist[0]) / s
+    y_g = (out.cpu().numpy() - q) / s
     err = rel(y_g, y_o)
     print(f"[result] forward relative error {err:.3e} (|y| {np.linalg.norm(y_o):.3e})", flush=True)
     assert err <= 3e-2
@@ -61,8 +61,8 @@ def test_gradient_matches_fp64_network():
     grad, loss = g.net_grad(g.to_device(theta).float(), g.to_device(b),
                             [g.to_device(h) for h in hist], g.to_device(target))
     torch.cuda.synchronize()
-    X, s = mpnn.features(graph, b, np.array(hist))
-    t = (target - hist[0]) / s
+    X, q, s = mpnn.features(graph, b, np.array(hist))
+    t = mpnn.target(q, s, target)
     L_o, G_o = mpnn.loss_grad(theta.astype(np.float64), graph, X, t)
     G_g = grad.cpu().numpy().astype(np.float64)
     print(f"[result] loss gpu {loss.item():.6e} oracle {L_o:.6e}; "
