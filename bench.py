@@ -5,11 +5,23 @@
 A step is one full CGP time step (Eqs. 21-26: momentum, restriction, coarse
 Poisson solve, prolongation, velocity and pressure correction) of the
 2049 x 2049 Taylor-Green workload with 3 coarsening levels (257 x 257 pressure
-mesh), inputs resident on the GPU.  Prints one JSON line with the throughput
-in fine DOF * steps / s (DOF = 3 N_f: u, v, p), the roofline position of the
-dominant kernel (HIP events over the timed region), the CPU oracle timed on a
-bounded sample, the parity of one GPU step against that oracle step, and the
-coarse-solve time to tolerance of the FP64 and mixed-precision forms.
+mesh, rotational form), inputs resident on the GPU.  Three forms of the step
+run over the same trajectory:
+  plain_fp64     FP64 Jacobi-PCG from the previous increment (the paper's step)
+  learned_mixed  guarded learned guess + FP32-inner / FP64-refinement PCG
+  learned_fp64   guarded learned guess + FP64 PCG
+The network is first trained on the GPU, with the library's own kernels, on
+(b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
+trajectories than the timed one).  `value` is the plain_fp64 throughput in
+fine DOF * steps / s (DOF = 3 N_f: u, v, p), the form that matches the FP64
+oracle to 1e-10; the other forms (which agree with it to the solver
+tolerance), the coarse-solve time to tolerance of each guess on this
+workload and on the 257 x 257 lid-driven cavity with a 129 x 129 pressure
+mesh (the learned guess's own workload: trained on lid speeds U[0.5, 1.5],
+evaluated on a fresh U = 1 run), the roofline position of the dominant
+kernel (HIP events over the timed region), the CPU oracle timed on a bounded
+sample and the parity of the first step against that oracle step are
+reported beside it in the same JSON line.
 """
 from __future__ import annotations
 
@@ -46,8 +58,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, g_fine_xy, gpu_first_step):
-    """Oracle (as it stands) on one step of the same workload, single thread."""
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cpu_baseline(w, g_fine_xy, first_steps):
+    """Oracle (as it stands) on one step of the same workload, single thread;
+    returns the baseline record and the parity of each form's first GPU step
+    against the oracle's."""
     from threadpoolctl import threadpool_limits
 
     from oracle.cgp import build as build_oracle
@@ -62,13 +80,9 @@ def cpu_baseline(w, g_fine_xy, gpu_first_step):
         r = ora.step(st, uD)
         t_step = time.perf_counter() - t0
     assert np.array_equal(ora.fine_xy, g_fine_xy)
-    U_g, P_g = gpu_first_step
-
-    def rel(a, b):
-        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-    parity = {"u": rel(U_g, r.state.U), "p": rel(P_g, r.state.P),
-              "pcg_iters_oracle": r.stats["pcg_iters"]}
+    parity = {"pcg_iters_oracle": r.stats["pcg_iters"]}
+    for form, (U_g, P_g) in first_steps.items():
+        parity[form] = {"u": rel(U_g, r.state.U), "p": rel(P_g, r.state.P)}
     dof = 3 * ora.nf
     return {
         "value": dof / t_step, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
@@ -78,14 +92,45 @@ def cpu_baseline(w, g_fine_xy, gpu_first_step):
     }, parity
 
 
+def run_form(torch, g, uD, fields, warmup, steps, theta=None, kid=0):
+    """W untimed steps, then K timed steps (synchronised on both sides, the
+    selected kernel bracketed by HIP events), then one untimed step with
+    statistics.  Returns (elapsed s, kernel ms, launches, stats, state)."""
+    state = g.new_state(*fields)
+    for n in range(warmup):
+        g.step(state, uD[n], theta=theta)
+    torch.cuda.synchronize()
+    if kid:
+        g.timing_enable(kid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(warmup, warmup + steps):
+        g.step(state, uD[n], theta=theta)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, nl = g.timing_read() if kid else (0.0, 0)
+    g.timing_enable(0)
+    st = g.step(state, uD[warmup + steps], theta=theta, stats=True)
+    return elapsed, kms, nl, st, state
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tg2049_k3_fp64")
+    ap.add_argument("--learned-workload", default="cavity257_k1_learned")
+    ap.add_argument("--learned-runs", type=int, default=4)
+    ap.add_argument("--learned-steps", type=int, default=150)
+    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--learned-eval", type=int, default=300)
     ap.add_argument("--timed-kernel", default="mass_spmv", choices=sorted(KERNELS))
+    ap.add_argument("--train-runs", type=int, default=3)
+    ap.add_argument("--train-steps", type=int, default=40)
+    ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain_fp64,learned_mixed,learned_fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -97,103 +142,137 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
-    from paper_1812_00185_amd import CGP
+    from paper_1812_00185_amd import CGP, learned
     from workloads import get_workload
 
     w = get_workload(args.workload)
-    prec = "fp64" if w.precision == 0 else "mixed"
+    forms = args.forms.split(",")
+    kw = dict(chi=w.chi, restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol,
+              mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter)
     t0 = time.perf_counter()
-    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, precision=prec,
-            restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol,
-            mass_tol=w.mass_tol, max_iter=w.max_iter)
+    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64", **kw)
+    gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="mixed", **kw)
     torch.cuda.synchronize()
     log(f"[bench] {w.name}: N_f={g.nf} N_c={g.nc} nnz_f={g.sizes.nnz_fine} "
         f"set-up {time.perf_counter() - t0:.1f} s")
+    solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
+
+    # --- train the learned guess on other trajectories (phase-shifted flows)
+    t0 = time.perf_counter()
+    runs = learned.plain_runs(g, learned.variants(w, args.train_runs, seed=0),
+                              args.train_steps)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    theta, losses = learned.train(g, runs, epochs=args.train_epochs, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_samples = sum(len(r.b) for r in runs)
+    del runs
+    log(f"[bench] trained on {n_samples} pairs in {t_train:.1f} s (collect {t_collect:.1f} s); "
+        f"losses {[round(x, 4) for x in losses]}")
+    thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]
     nsteps = args.warmup + args.steps
     uD = [g.to_device(w.dirichlet_values(xyd, (n + 1) * w.dt)) for n in range(nsteps + 1)]
 
-    # one step from the initial fields for the parity check against the oracle
-    s1 = g.new_state(Um, U0, P0)
-    g.step(s1, uD[0])
-    torch.cuda.synchronize()
-    first = (s1.U.cpu().numpy(), s1.P.cpu().numpy())
-    del s1
-
-    state = g.new_state(Um, U0, P0)
-    for n in range(args.warmup):
-        g.step(state, uD[n])
-    torch.cuda.synchronize()
-    log(f"[bench] warm-up {args.warmup} steps done")
+    # one step of each form from the initial fields for the parity check
+    first = {}
+    for form in forms:
+        s1 = solvers[form].new_state(Um, U0, P0)
+        solvers[form].step(s1, uD[0], theta=thetas[form])
+        torch.cuda.synchronize()
+        first[form] = (s1.U.cpu().numpy(), s1.P.cpu().numpy())
+        del s1
 
     kid, kbytes = KERNELS[args.timed_kernel]
-    g.timing_enable(kid)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for n in range(args.warmup, nsteps):
-        g.step(state, uD[n])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kms, nlaunch = g.timing_read()
-    g.timing_enable(0)
-    st = g.step(state, uD[nsteps], stats=True)
-    log(f"[bench] timed {args.steps} steps: {elapsed:.3f} s; last step stats {st}")
+    main_form = "plain_fp64" if "plain_fp64" in forms else forms[0]
+    results, finals = {}, {}
+    for form in forms:
+        el, kms, nl, st, state = run_form(torch, solvers[form], uD, (Um, U0, P0),
+                                          args.warmup, args.steps, thetas[form],
+                                          kid if form == main_form else 0)
+        results[form] = {"value": 3 * g.nf * args.steps / el,
+                         "ms_per_step": 1e3 * el / args.steps, "last_step": st}
+        finals[form] = (state.U.cpu().numpy(), state.P.cpu().numpy())
+        if form == main_form:
+            kernel = (kms, nl)
+        log(f"[bench] {form}: {args.steps} steps in {el:.3f} s; last step {st}")
+        del state
+    ref = finals.get("plain_fp64")
+    if ref is not None:
+        for form in forms:
+            results[form]["vs_plain_fp64_rel_l2"] = {"u": rel(finals[form][0], ref[0]),
+                                                     "p": rel(finals[form][1], ref[1])}
 
-    dof = 3 * g.nf
-    value = dof * args.steps / elapsed
+    kms, nlaunch = kernel
+    fine_xy = g.fine_xy
+    sizes = {"fine_nodes": g.nf, "coarse_nodes": g.nc, "nnz_fine": int(g.sizes.nnz_fine)}
     n_rows, nnz = (g.nc, int(g.sizes.nnz_coarse)) if kid == 3 else (g.nf, int(g.sizes.nnz_fine))
     bpl = kbytes(n_rows, nnz, 3 if w.chi else 2)
     avg_s = (kms / 1e3) / max(nlaunch, 1)
     achieved = bpl / avg_s / 1e9 if nlaunch else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "kernel": args.timed_kernel, "launches": nlaunch,
+                "kernel": args.timed_kernel, "form": main_form, "launches": nlaunch,
                 "avg_us": avg_s * 1e6, "bytes_per_launch": bpl}
 
-    # coarse-solve time to tolerance: FP64 PCG vs mixed refinement, same rhs and guess
-    ttt = None
-    try:
-        Ut, _ = g.momentum(state.U_prev, state.U, state.P, uD[nsteps])
-        b = g.restrict(Ut)
-        guess = state.phi_hist[0].clone()
-        gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, precision="mixed",
-                 restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol,
-                 mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter)
-        res = {}
-        for name, solver in (("fp64", g), ("mixed", gm)):
-            times = []
-            for _ in range(3):
-                phi = guess.clone()
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                info = solver.pcg_solve(b, phi)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t1)
-            res[name] = {"ms": 1e3 * min(times), "iters": info["iters"],
-                         "outer": info["outer_iters"], "rel_res": info["rel_res"]}
-        ttt = res
-        del gm
-    except Exception as e:  # reported, not fatal
-        ttt = {"error": str(e)}
+    # coarse-solve time to tolerance along the timed trajectory, every guess
+    # solving the same right-hand side to the same FP64 tolerance
+    _, tt5 = learned.evaluate(g, gm, theta, w, steps=nsteps, warm=args.warmup)
+    tt5["training"] = {"pairs": n_samples, "epochs": args.train_epochs, "s": t_train,
+                       "final_loss": losses[-1]}
+    ttt = {w.name: tt5}
+    del g, gm, solvers, finals, uD
+    torch.cuda.empty_cache()
+
+    # the learned guess on its own workload: cavity, trained on other lid speeds
+    if args.learned_workload:
+        wl = get_workload(args.learned_workload)
+        kl = dict(chi=wl.chi, restrict=wl.restrict, pcg_tol=wl.pcg_tol,
+                  inner_tol=wl.inner_tol, mom_tol=wl.mom_tol, mass_tol=wl.mass_tol,
+                  max_iter=wl.max_iter)
+        gl = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="fp64", **kl)
+        glm = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="mixed", **kl)
+        t0 = time.perf_counter()
+        runs = learned.plain_runs(gl, learned.variants(wl, args.learned_runs, seed=0),
+                                  args.learned_steps)
+        t1 = time.perf_counter()
+        theta_l, losses_l = learned.train(gl, runs, epochs=args.learned_epochs, lr=1e-3,
+                                          seed=0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pairs = sum(len(r.b) for r in runs)
+        del runs
+        _, ttl = learned.evaluate(gl, glm, theta_l, wl.with_(lid_speed=1.0),
+                                  steps=args.learned_eval, warm=10)
+        ttl["training"] = {"pairs": pairs, "epochs": args.learned_epochs,
+                           "collect_s": t1 - t0, "s": t2 - t1, "final_loss": losses_l[-1]}
+        ttl["config"] = {"fine_nodes": gl.nf, "coarse_nodes": gl.nc, "levels": wl.levels,
+                         "pcg_tol": wl.pcg_tol}
+        ttt[wl.name] = ttl
+        log(f"[bench] {wl.name}: {json.dumps(ttl)}")
+        del gl, glm
 
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
-        cpu, parity = cpu_baseline(w, g.fine_xy, first)
+        cpu, parity = cpu_baseline(w, fine_xy, first)
 
     out = {
-        "metric": METRIC, "value": value, "unit": "DOF*steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "metric": METRIC, "value": results[main_form]["value"], "unit": "DOF*steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": results[main_form]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32+bf16" if main_form == "learned_mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "fine_nodes": g.nf, "coarse_nodes": g.nc,
-                   "nnz_fine": int(g.sizes.nnz_fine), "levels": w.levels, "dt": w.dt,
-                   "nu": w.nu, "chi": w.chi, "precision": prec, "restrict": w.restrict,
-                   "pcg_tol": w.pcg_tol},
-        "roofline": roofline, "cpu_baseline": cpu, "parity_rel_l2": parity,
-        "time_to_tol": ttt,
+        "config": {"workload": w.name, "form": main_form, **sizes,
+                   "levels": w.levels, "dt": w.dt, "nu": w.nu, "chi": w.chi,
+                   "restrict": w.restrict, "pcg_tol": w.pcg_tol, "mom_tol": w.mom_tol},
+        "forms": results, "roofline": roofline, "cpu_baseline": cpu,
+        "parity_rel_l2": parity, "time_to_tol": ttt,
     }
     print(json.dumps(out), flush=True)
 

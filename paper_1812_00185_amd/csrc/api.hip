@@ -188,19 +188,26 @@ hipEvent_t* timer(cgp_ctx* c, int id) {
   return p;
 }
 
+struct NoStop {
+  bool operator()(const Scal*) const { return false; }
+};
+
 // Queues iterations 1..last of a Krylov solve through `launch(it, check_only)`
 // in chunks, polling the stopping flags of the first `nrhs` scalars one chunk
 // behind.  `last` = max_iter for PCG, max_iter + 1 for BiCGSTAB (whose final
 // test runs at the start of the next iteration).  Copies the final scalars to
-// `out`.
-template <class Launch>
+// `out`.  `stop(polled)` may end an unfinished solve early (the chunk already
+// queued still runs); *launched receives the number of iterations queued.
+template <class Launch, class Stop = NoStop>
 int drive(cgp_ctx* c, Scal* sc, int nrhs, int last, int chunk, bool trailing_check,
-          Launch launch, hipStream_t s, Scal* out) {
+          Launch launch, hipStream_t s, Scal* out, Stop stop = Stop(),
+          int* launched = nullptr) {
   int it = 1, k = 0;
   bool have_prev = false;
   while (true) {
     const int hi = std::min(it + chunk - 1, last);
     for (; it <= hi; ++it) launch(it, trailing_check && it == last);
+    if (launched) *launched = it - 1;
     HIPCHK(hipMemcpyAsync(c->pinned + 8 * k, sc, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(c->ev[k], s));
     auto all_done = [&](int slot) {
@@ -212,6 +219,11 @@ int drive(cgp_ctx* c, Scal* sc, int nrhs, int last, int chunk, bool trailing_che
       HIPCHK(hipEventSynchronize(c->ev[k ^ 1]));
       if (all_done(k ^ 1)) {
         std::memcpy(out, c->pinned + 8 * (k ^ 1), sizeof(Scal) * nrhs);
+        return CGP_OK;
+      }
+      if (stop(c->pinned + 8 * (k ^ 1))) {
+        HIPCHK(hipEventSynchronize(c->ev[k]));
+        std::memcpy(out, c->pinned + 8 * k, sizeof(Scal) * nrhs);
         return CGP_OK;
       }
     }
@@ -301,17 +313,22 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
     if (rc) return rc;
     rc = stats_status(out, 1, P.max_iter, st);
   } else {
-    // FP64 iterative refinement around FP32-inner Jacobi-PCG
+    // FP64 iterative refinement around FP32-inner Jacobi-PCG.  A correction
+    // that does not halve the FP64 residual (the inner solve went below what
+    // FP32 resolves on this operator) is undone and the inner tolerance floor
+    // raised; the iterate is never left worse than the best one seen.
     int inner_total = 0, outer = 0;
     Scal chk{};
-    bool converged = false;
+    bool converged = false, undone = false;
+    double prev_rel = 0.0, eta_floor = P.inner_tol;
+    double* xsave = c->cz;  // FP64 vector unused on this path
     for (;;) {
       cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
       cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, outer, s);
       HIPCHK(hipMemcpyAsync(c->pinned, c->scal + 4, sizeof(Scal), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       chk = c->pinned[0];
-      if (chk.status == 2) {
+      if (chk.status == 2 && outer == 0) {
         rc = fail(CGP_ERR_NAN, "mixed-precision refinement produced NaN/Inf");
         break;
       }
@@ -319,29 +336,59 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
         converged = true;
         break;
       }
+      if (outer > 0 && !undone && !(chk.rel <= 0.5 * prev_rel)) {
+        cgp::launch_copy(xsave, x, c->nc, s);
+        eta_floor *= 100.0;
+        undone = true;
+        if (eta_floor >= 0.1) {
+          chk.rel = prev_rel;
+          break;
+        }
+        continue;  // recompute the residual of the restored iterate
+      }
+      undone = false;
+      prev_rel = chk.rel;
       if (outer >= P.max_outer || inner_total >= P.max_iter) break;
+      cgp::launch_copy(x, xsave, c->nc, s);
       cgp::PcgVecs<float> V{c->cx32, c->cr32, c->cz32, c->cq32, {c->cp32a, c->cp32b},
                             c->cb32, c->invdKc32, c->Kc32};
       cgp::launch_pcg_init<float>(c->C, V, true, c->scal, c->part, c->nb_c, s);
       Scal out[1];
       const int budget = std::max(1, P.max_iter - inner_total);
       // reduce the residual just enough to reach pcg_tol (with margin), but
-      // not below what FP32 resolves
-      const double eta = std::max(P.inner_tol, 0.3 * P.pcg_tol / std::max(chk.rel, 1e-300));
+      // not below the floor
+      const double eta = std::max(eta_floor, 0.3 * P.pcg_tol / std::max(chk.rel, 1e-300));
+      // FP32 stagnation: the recursive residual has not halved in 8 polls
+      double best = 1e300;
+      int since = 0, launched = 0;
+      auto stalled = [&](const Scal* p) {
+        if (p->rel < 0.5 * best) {
+          best = p->rel;
+          since = 0;
+          return false;
+        }
+        return ++since >= 8;
+      };
       int r2 = drive(c, c->scal, 1, budget + 1, 32, true,
                      [&](int it, bool chk2) {
                        cgp::launch_pcg_iter<float>(c->C, V, c->scal, c->part, c->nb_c, it, eta,
                                                    chk2, s);
                      },
-                     s, out);
+                     s, out, stalled, &launched);
       if (r2) return r2;
-      if (out[0].status == 2) {
-        rc = fail(CGP_ERR_NAN, "inner FP32 solve produced NaN/Inf");
-        break;
-      }
-      inner_total += out[0].done_stamp ? out[0].iters : budget;
-      cgp::launch_axpy_f32(c->cx32, x, c->nc, s);
+      inner_total += out[0].done_stamp ? out[0].iters : std::min(launched, budget);
       ++outer;
+      if (out[0].status == 2) {
+        // no correction from a failed inner solve: demand less of FP32
+        eta_floor *= 100.0;
+        undone = true;
+        if (eta_floor >= 0.1) {
+          rc = fail(CGP_ERR_NAN, "inner FP32 solve produced NaN/Inf");
+          break;
+        }
+        continue;
+      }
+      cgp::launch_axpy_f32(c->cx32, x, c->nc, s);
     }
     if (st) {
       st->iters = inner_total;

@@ -41,14 +41,28 @@ def _advance(g: CGP, U_prev, U, P, uD, phi_guess, record=None):
     return U_new, P_new, phi, b, Ut, st
 
 
-def plain_runs(g: CGP, workload, n_runs, steps, seed=0, speed_range=(0.5, 1.5)):
-    """`n_runs` plain runs of `steps` steps from rest, the lid speed drawn
-    uniformly from speed_range (seeded)."""
+def variants(workload, n_runs, seed=0, speed_range=(0.5, 1.5)):
+    """Seeded training variants of a workload: lid speeds drawn uniformly
+    from speed_range for the cavity, phase shifts (x0, y0) ~ U[0, 1)^2 for
+    Taylor-Green (translated exact solutions); other flows repeat as is."""
     rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_runs):
+        if workload.flow == "cavity":
+            out.append(workload.with_(lid_speed=float(rng.uniform(*speed_range))))
+        elif workload.flow == "taylor_green":
+            out.append(workload.with_(phase=tuple(float(v) for v in rng.uniform(0, 1, 2))))
+        else:
+            out.append(workload)
+    return out
+
+
+def plain_runs(g: CGP, workloads, steps):
+    """One plain run of `steps` steps per workload (same mesh as g) from its
+    initial fields, recording (b, phi) of every step."""
     runs = []
     xyd = g.fine_xy[g.dirichlet_nodes]
-    for r in range(n_runs):
-        w = workload.with_(lid_speed=float(rng.uniform(*speed_range)))
+    for w in workloads:
         Um, U0, P0 = w.initial_fields(g.fine_xy)
         U_prev, U, P = g.to_device(Um), g.to_device(U0), g.to_device(P0)
         phi = g.zeros(g.nc)

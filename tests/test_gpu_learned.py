@@ -27,7 +27,7 @@ def test_trained_network_reduces_coarse_iterations():
             pcg_tol=w.pcg_tol)
     gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, precision="mixed",
              pcg_tol=w.pcg_tol)
-    runs = learned.plain_runs(g, w, n_runs=3, steps=120, seed=0)
+    runs = learned.plain_runs(g, learned.variants(w, 3, seed=0), steps=120)
     theta, losses = learned.train(g, runs, epochs=4, lr=1e-3, seed=0)
     print(f"[result] training loss per epoch {[f'{x:.3e}' for x in losses]}", flush=True)
     assert np.isfinite(losses).all() and losses[-1] < losses[0]

@@ -307,6 +307,34 @@ def test_mixed_precision_step(name, wf):
     assert rel(np_(P_g), P_o) <= 1e-6
 
 
+def test_mixed_refinement_survives_unreachable_inner_tolerance():
+    """An inner tolerance below what FP32 resolves on the operator: stalled
+    inner solves end early, corrections that do not pay are undone and the
+    inner floor is raised, and the refinement still reaches the FP64
+    tolerance within a bounded number of inner iterations."""
+    w = cavity(129, 0, chi=0).with_(precision=1, pcg_tol=1e-10, inner_tol=1e-13)
+    g, o = make(w)
+    g64 = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, precision="fp64",
+              pcg_tol=w.pcg_tol)
+    Um, U0, P0 = start(w, o, g, seed=5)
+    uD = g.to_device(w.dirichlet_values(o.fine_xy[o.dir], w.dt))
+    Ut, _ = g.momentum(g.to_device(Um), g.to_device(U0), g.to_device(P0), uD)
+    b = g.restrict(Ut)
+    phi64 = g.zeros(g.nc)
+    st64 = g64.pcg_solve(b, phi64)
+    phi = g.zeros(g.nc)
+    st = g.pcg_solve(b, phi)
+    b_o = np_(b)
+    f = o.phi_free
+    phic = np_(phi)
+    true = np.linalg.norm(b_o[f] - o.Kc_ff @ phic[f]) / np.linalg.norm(b_o[f])
+    print(f"[result] inner iters {st['iters']} outer {st['outer_iters']} (FP64 PCG "
+          f"{st64['iters']}), true rel residual {true:.3e}", flush=True)
+    assert st["converged"] and true <= w.pcg_tol
+    assert st["iters"] <= 6 * st64["iters"]
+    assert rel(phic, np_(phi64)) <= 1e-6
+
+
 @pytest.mark.parametrize("name,wf", MIXED_CASES[:3], ids=[c[0] for c in MIXED_CASES[:3]])
 def test_mixed_precision_trajectory(name, wf):
     """Ten mixed steps: every coarse solve converges to the FP64 tolerance;

@@ -1,0 +1,74 @@
+"""Pins of the synthetic input data: the Taylor-Green fields (shifted or not)
+solve the incompressible Navier-Stokes equations (Eqs. 1-2 with zero
+forcing), checked by central differences; boundary data of the cavity and
+the channel."""
+import numpy as np
+import pytest
+
+from workloads import flows, get_workload
+from workloads.meshes import CHANNEL_H
+
+
+@pytest.mark.parametrize("phase", [(0.0, 0.0), (0.31, 0.77)])
+def test_taylor_green_solves_navier_stokes(phase):
+    w = get_workload("tg2049_k3_fp64").with_(phase=phase)
+    nu = w.nu
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(0, 1, size=(50, 2))
+    t, h = 0.37, 1e-4
+
+    def fields(xy, tt):
+        (u, v), p = w.exact(xy, tt)
+        return u, v, p
+
+    def d(f, k, tt=t):
+        e = np.zeros(2)
+        e[k] = h
+        a, b = fields(pts + e, tt), fields(pts - e, tt)
+        return [(ai - bi) / (2 * h) for ai, bi in zip(a, b)]
+
+    def lap(tt=t):
+        c = fields(pts, tt)
+        out = [np.zeros(len(pts)) for _ in range(3)]
+        for k in range(2):
+            e = np.zeros(2)
+            e[k] = h
+            a, b = fields(pts + e, tt), fields(pts - e, tt)
+            for i in range(3):
+                out[i] += (a[i] - 2 * c[i] + b[i]) / (h * h)
+        return out
+
+    u, v, p = fields(pts, t)
+    ux, vx, px = d(fields, 0)
+    uy, vy, py = d(fields, 1)
+    fp, fm = fields(pts, t + h), fields(pts, t - h)
+    ut, vt = (fp[0] - fm[0]) / (2 * h), (fp[1] - fm[1]) / (2 * h)
+    lu, lv, _ = lap()
+    np.testing.assert_allclose(ux + vy, 0.0, atol=1e-7)
+    np.testing.assert_allclose(ut + u * ux + v * uy + px - nu * lu, 0.0, atol=1e-5)
+    np.testing.assert_allclose(vt + u * vx + v * vy + py - nu * lv, 0.0, atol=1e-5)
+
+
+def test_phase_shift_translates_the_fields():
+    w0 = get_workload("tg33_k1")
+    w1 = w0.with_(phase=(0.25, 0.5))
+    xy = np.random.default_rng(1).uniform(0, 1, size=(20, 2))
+    (U1, P1), (U0, P0) = w1.exact(xy + [0.25, 0.5], 0.1), w0.exact(xy, 0.1)
+    np.testing.assert_allclose(U1, U0, atol=1e-14)
+    np.testing.assert_allclose(P1, P0, atol=1e-14)
+    np.testing.assert_allclose(w1.dirichlet_values(xy + [0.25, 0.5], 0.1), U0, atol=1e-14)
+
+
+def test_boundary_data():
+    x = np.array([0.0, 0.5, 1.0, 0.5])
+    y = np.array([1.0, 1.0, 1.0, 0.0])
+    u, v = flows.cavity_lid(x, y, 1.5)
+    np.testing.assert_array_equal(u, [0.0, 1.5, 0.0, 0.0])
+    np.testing.assert_array_equal(v, 0.0)
+    yy = np.linspace(0, CHANNEL_H, 1001)
+    u, v = flows.channel_inflow(np.zeros(1001), yy, 0.3)
+    assert u[500] == pytest.approx(0.3, rel=1e-12) and u[0] == 0
+    assert u[-1] == pytest.approx(0, abs=1e-15)
+    # mean inflow 2/3 U_m (Simpson's rule is exact for the parabola)
+    mean = (yy[1] - yy[0]) / 3 * (u[0] + u[-1] + 4 * u[1:-1:2].sum() + 2 * u[2:-1:2].sum())
+    assert mean / CHANNEL_H == pytest.approx(0.2, rel=1e-12)

@@ -39,6 +39,7 @@ class Workload:
     lid_speed: float = 1.0
     channel_h: float = 0.0082
     seed: int = 0
+    phase: tuple = (0.0, 0.0)      # Taylor-Green shift (x0, y0): u(x - x0, y - y0, t)
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -56,8 +57,9 @@ class Workload:
         t=0; the impulsively started flows start from rest."""
         n = xy.shape[0]
         if self.flow == "taylor_green":
-            um, vm, _ = flows.taylor_green(xy[:, 0], xy[:, 1], -self.dt, self.nu)
-            u0, v0, p0 = flows.taylor_green(xy[:, 0], xy[:, 1], 0.0, self.nu)
+            x, y = self._shifted(xy)
+            um, vm, _ = flows.taylor_green(x, y, -self.dt, self.nu)
+            u0, v0, p0 = flows.taylor_green(x, y, 0.0, self.nu)
             return np.stack([um, vm]), np.stack([u0, v0]), p0
         z = np.zeros(n)
         return np.stack([z, z]), np.stack([z, z]), z.copy()
@@ -66,7 +68,7 @@ class Workload:
         """[2, n_dir] velocity at the Dirichlet nodes at time t."""
         x, y = xy_dir[:, 0], xy_dir[:, 1]
         if self.flow == "taylor_green":
-            u, v, _ = flows.taylor_green(x, y, t, self.nu)
+            u, v, _ = flows.taylor_green(*self._shifted(xy_dir), t, self.nu)
         elif self.flow == "cavity":
             u, v = flows.cavity_lid(x, y, self.lid_speed)
         elif self.flow == "channel":
@@ -78,8 +80,13 @@ class Workload:
     def exact(self, xy: np.ndarray, t: float):
         if self.flow != "taylor_green":
             return None
-        u, v, p = flows.taylor_green(xy[:, 0], xy[:, 1], t, self.nu)
+        u, v, p = flows.taylor_green(*self._shifted(xy), t, self.nu)
         return np.stack([u, v]), p
+
+    def _shifted(self, xy):
+        """Coordinates shifted by the Taylor-Green phase (a translated exact
+        solution is still one)."""
+        return xy[:, 0] - self.phase[0], xy[:, 1] - self.phase[1]
 
 
 @lru_cache(maxsize=8)
