@@ -208,7 +208,7 @@ int drive(cgp_ctx* c, Scal* sc, int nrhs, int last, int chunk, bool trailing_che
     const int hi = std::min(it + chunk - 1, last);
     for (; it <= hi; ++it) launch(it, trailing_check && it == last);
     if (launched) *launched = it - 1;
-    HIPCHK(hipMemcpyAsync(c->pinned + 8 * k, sc, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, s));
+    cgp::launch_mirror(sc, c->pinned + 8 * k, nrhs, s);
     HIPCHK(hipEventRecord(c->ev[k], s));
     auto all_done = [&](int slot) {
       for (int d = 0; d < nrhs; ++d)
@@ -325,7 +325,7 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
     for (;;) {
       cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
       cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, outer, s);
-      HIPCHK(hipMemcpyAsync(c->pinned, c->scal + 4, sizeof(Scal), hipMemcpyDeviceToHost, s));
+      cgp::launch_mirror(c->scal + 4, c->pinned, 1, s);
       HIPCHK(hipStreamSynchronize(s));
       chk = c->pinned[0];
       if (chk.status == 2 && outer == 0) {

@@ -651,22 +651,14 @@ k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double 
   const T* __restrict__ z = V.z;
   T beta = T(0);
   double pq = 0.0;
-  // every block owns at least one tile (nb <= ntiles); the first tile's loads
-  // are issued before the reduction of the partial sums so that both
-  // latencies overlap
+  // every block owns at least one tile (nb <= ntiles).  On the first tile the
+  // tile is staged and the first kRowBatch gathers of z and p_old are issued
+  // before the reduction of the partial sums (beta is needed only to combine
+  // them), so the three latencies overlap
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
     const int s0 = L.rowptr[r0], cnt = L.rowptr[r1] - s0;
-    T pv[kPer];
-    int32_t pc[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int k = threadIdx.x + q * kBlock;
-      if (k < cnt) {
-        pv[q] = V.val[s0 + k];
-        pc[q] = L.col[s0 + k];
-      }
-    }
+    const bool first = t == (int)blockIdx.x;
     const int row = r0 + threadIdx.x;
     const bool own = row < r1;
     int a = 0, b = 0;
@@ -677,7 +669,29 @@ k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double 
       zr = z[row];
       por = pold[row];
     }
-    if (t == (int)blockIdx.x) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int k = threadIdx.x + q * kBlock;
+      if (k < cnt) {
+        st.val[k] = V.val[s0 + k];
+        st.col[k] = L.col[s0 + k];
+      }
+    }
+    __syncthreads();
+    // first batch of the row's gathers
+    T gz[kRowBatch], gp[kRowBatch], gv[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      gz[u] = gp[u] = gv[u] = T(0);
+      if (own && a + u < b) {
+        const int c = st.col[a + u];
+        gv[u] = st.val[a + u];
+        gz[u] = z[c];
+        gp[u] = pold[c];
+      }
+    }
+    if (first) {
       const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
       double s[3];
       block_sums<3>(part, nb, idx, s);
@@ -704,23 +718,29 @@ k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double 
       if (fin || check_only) return;
       beta = it == 1 ? T(0) : (T)(s[0] / sc[0].rho[(it - 2) & 1]);
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int k = threadIdx.x + q * kBlock;
-      if (k < cnt) {
-        st.val[k] = pv[q];
-        st.col[k] = pc[q];
-      }
-    }
-    __syncthreads();
     if (own) {
-      T acc[1];
-      tile_row_range<T, 1>(st, a, b, [&](int, int c) { return z[c] + beta * pold[c]; }, acc);
+      // same summation order as tile_row_range: batches of kRowBatch in row order
+      T acc = T(0);
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (a + u < b) acc += gv[u] * (gz[u] + beta * gp[u]);
+      for (int s = a + kRowBatch; s < b; s += kRowBatch) {
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (s + u < b) {
+            const int c = st.col[s + u];
+            gv[u] = st.val[s + u];
+            gz[u] = z[c];
+            gp[u] = pold[c];
+          }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (s + u < b) acc += gv[u] * (gz[u] + beta * gp[u]);
+      }
       const T pr = zr + beta * por;
       pnew[row] = pr;
-      V.q[row] = acc[0];
-      pq += (double)pr * (double)acc[0];
+      V.q[row] = acc;
+      pq += (double)pr * (double)acc;
     }
   }
   const double vals[1] = {pq};
@@ -1071,6 +1091,21 @@ k_guard_select(int32_t n, const double* __restrict__ x0, const double* __restric
 }
 
 // ------------------------------------------------------------------ small ops
+// Copies n solver-scalar records into host-mapped pinned memory (the host
+// polls them after an event): one 8-byte word per lane, then a system-scope
+// fence.  Much cheaper on the stream than a DMA/blit copy of 72 bytes.
+__global__ void k_mirror(const Scal* __restrict__ src, Scal* dst, int n) {
+  constexpr int kWords = sizeof(Scal) / 8;
+  static_assert(sizeof(Scal) % 8 == 0, "Scal is a whole number of words");
+  const int i = threadIdx.x;
+  if (i < n * kWords) {
+    const int64_t* s = reinterpret_cast<const int64_t*>(src);
+    int64_t* d = reinterpret_cast<int64_t*>(dst);
+    d[i] = s[i];
+  }
+  __threadfence_system();
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1298,6 +1333,9 @@ void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
 }
 void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s) {
   k_zero_masked<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, nat, n);
+}
+void launch_mirror(const Scal* src, Scal* host_dst, int n, hipStream_t s) {
+  k_mirror<<<1, 64, 0, s>>>(src, host_dst, n);
 }
 void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s) {
   k_axpy_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(d, x, n);
