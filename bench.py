@@ -46,11 +46,12 @@ HBM_PEAK_GBS = 8000.0
 #               index 4 B + two Jacobi diagonals 16 B per row, and per rhs the
 #               gathered iterate, the previous iterate, b and the new iterate
 #  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written
-#  coarse_spmv: PCG direction + product kernel: z, p_old read, p_new, q written
+#  coarse_spmv: one single-reduction PCG iteration: x, p, r, w, s, D^-1 read,
+#               x, p, r, w, s written
 KERNELS = {
     "mass_spmv": (1, lambda n, z, nr: 12 * z + 4 * (n + 1) + 20 * n + 32 * nr * n),
     "mom_spmv": (2, lambda n, z, nr: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
-    "coarse_spmv": (3, lambda n, z, nr: 12 * z + 4 * (n + 1) + 4 * 8 * n),
+    "coarse_spmv": (3, lambda n, z, nr: 12 * z + 4 * (n + 1) + 11 * 8 * n),
 }
 
 
@@ -131,7 +132,15 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="plain_fp64,learned_mixed,learned_fp64")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="plain FP64 form only: no training, no learned forms or legs")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run an FP64 scale-by-one kernel over this many MiB (reads "
+                         "and writes that many bytes): the reference for HBM counter scaling")
     args = ap.parse_args()
+    if args.no_learned:
+        args.forms = "plain_fp64"
+        args.learned_workload = ""
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described but not built", file=sys.stderr)
@@ -145,8 +154,19 @@ def main():
     from paper_1812_00185_amd import CGP, learned
     from workloads import get_workload
 
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {args.copy_calibration_mb} MiB read + written")
+        del src, dst
+
     w = get_workload(args.workload)
     forms = args.forms.split(",")
+    learned_forms = any(f.startswith("learned") for f in forms)
     kw = dict(chi=w.chi, restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol,
               mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter)
     t0 = time.perf_counter()
@@ -158,19 +178,21 @@ def main():
     solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
 
     # --- train the learned guess on other trajectories (phase-shifted flows)
-    t0 = time.perf_counter()
-    runs = learned.plain_runs(g, learned.variants(w, args.train_runs, seed=0),
-                              args.train_steps)
-    torch.cuda.synchronize()
-    t_collect = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    theta, losses = learned.train(g, runs, epochs=args.train_epochs, lr=1e-3, seed=0)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    n_samples = sum(len(r.b) for r in runs)
-    del runs
-    log(f"[bench] trained on {n_samples} pairs in {t_train:.1f} s (collect {t_collect:.1f} s); "
-        f"losses {[round(x, 4) for x in losses]}")
+    theta = None
+    if learned_forms:
+        t0 = time.perf_counter()
+        runs = learned.plain_runs(g, learned.variants(w, args.train_runs, seed=0),
+                                  args.train_steps)
+        torch.cuda.synchronize()
+        t_collect = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        theta, losses = learned.train(g, runs, epochs=args.train_epochs, lr=1e-3, seed=0)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        n_samples = sum(len(r.b) for r in runs)
+        del runs
+        log(f"[bench] trained on {n_samples} pairs in {t_train:.1f} s (collect "
+            f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
@@ -221,10 +243,12 @@ def main():
 
     # coarse-solve time to tolerance along the timed trajectory, every guess
     # solving the same right-hand side to the same FP64 tolerance
-    _, tt5 = learned.evaluate(g, gm, theta, w, steps=nsteps, warm=args.warmup)
-    tt5["training"] = {"pairs": n_samples, "epochs": args.train_epochs, "s": t_train,
-                       "final_loss": losses[-1]}
-    ttt = {w.name: tt5}
+    ttt = {}
+    if learned_forms:
+        _, tt5 = learned.evaluate(g, gm, theta, w, steps=nsteps, warm=args.warmup)
+        tt5["training"] = {"pairs": n_samples, "epochs": args.train_epochs, "s": t_train,
+                           "final_loss": losses[-1]}
+        ttt[w.name] = tt5
     del g, gm, solvers, finals, uD
     torch.cuda.empty_cache()
 

@@ -69,16 +69,23 @@ struct cgp_ctx {
          *invdM_int = nullptr;
   double *Kc = nullptr, *Dxc = nullptr, *Dyc = nullptr, *invdKc = nullptr, *lumped_c = nullptr;
   float *Kc32 = nullptr, *invdKc32 = nullptr;
+  // ELL copy of K_c for the PCG iteration kernel (width = longest row)
+  int ell_w = 0;
+  int32_t* ell_col = nullptr;
+  double* ell_val = nullptr;
+  float* ell_val32 = nullptr;
   double *ut = nullptr, *rhs = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr,
          *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
   double* phi_f = nullptr;
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
   int cheb_iters = 0;
-  double *bc = nullptr, *cr = nullptr, *cz = nullptr, *cp0 = nullptr, *cp1 = nullptr,
-         *cq = nullptr;
-  float *cb32 = nullptr, *cx32 = nullptr, *cr32 = nullptr, *cz32 = nullptr, *cp32a = nullptr,
-        *cp32b = nullptr, *cq32 = nullptr;
+  // coarse vectors: b_c, the PCG direction and alternating r, w, s (FP64 and
+  // FP32), the refinement residual and a saved iterate
+  double *bc = nullptr, *cr = nullptr, *cxsave = nullptr, *cp = nullptr;
+  double *cr2[2] = {}, *cw2[2] = {}, *cs2[2] = {};
+  float *cb32 = nullptr, *cx32 = nullptr, *cp32 = nullptr;
+  float *cr32[2] = {}, *cw32[2] = {}, *cs32[2] = {};
   double* tripart = nullptr;
   double* part = nullptr;
   Scal* scal = nullptr;
@@ -139,15 +146,26 @@ size_t carve(cgp_ctx* c, void* base) {
   c->nat_c = w.take<uint8_t>(nc);
   c->Kc = w.take<double>(nnzc);
   c->Kc32 = w.take<float>(nnzc);
+  {
+    int wmax = 1;
+    const auto& rp = c->h.gc.rowptr;
+    for (size_t i = 0; i + 1 < rp.size(); ++i) wmax = std::max(wmax, rp[i + 1] - rp[i]);
+    c->ell_w = (wmax + cgp::kEllPad - 1) / cgp::kEllPad * cgp::kEllPad;
+  }
+  c->ell_col = w.take<int32_t>((size_t)c->ell_w * nc);
+  c->ell_val = w.take<double>((size_t)c->ell_w * nc);
+  c->ell_val32 = w.take<float>((size_t)c->ell_w * nc);
   c->Dxc = w.take<double>(nnzc);
   c->Dyc = w.take<double>(nnzc);
   c->invdKc = w.take<double>(nc);
   c->invdKc32 = w.take<float>(nc);
   c->lumped_c = w.take<double>(nc);
   int32_t* tile_c = w.take<int32_t>(c->h.gc.tile.size());
-  double** cvec[] = {&c->bc, &c->cr, &c->cz, &c->cp0, &c->cp1, &c->cq};
+  double** cvec[] = {&c->bc,     &c->cr,     &c->cxsave, &c->cp,    &c->cr2[0],
+                     &c->cr2[1], &c->cw2[0], &c->cw2[1], &c->cs2[0], &c->cs2[1]};
   for (double** q : cvec) *q = w.take<double>(nc);
-  float** cvec32[] = {&c->cb32, &c->cx32, &c->cr32, &c->cz32, &c->cp32a, &c->cp32b, &c->cq32};
+  float** cvec32[] = {&c->cb32,     &c->cx32,     &c->cp32,     &c->cr32[0], &c->cr32[1],
+                      &c->cw32[0], &c->cw32[1], &c->cs32[0], &c->cs32[1]};
   for (float** q : cvec32) *q = w.take<float>(nc);
   c->tripart = w.take<double>(3 * (size_t)c->tc);
   c->part = w.take<double>((size_t)cgp::kSlots * 2 * cgp::kNbMax);
@@ -301,7 +319,10 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
   int rc = CGP_OK;
   if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
   if (P.precision == CGP_FP64) {
-    cgp::PcgVecs<double> V{x, c->cr, c->cz, c->cq, {c->cp0, c->cp1}, b, c->invdKc, c->Kc};
+    cgp::PcgVecs<double> V{x,          c->cp,       {c->cr2[0], c->cr2[1]},
+                           {c->cw2[0], c->cw2[1]}, {c->cs2[0], c->cs2[1]},
+                           b,          c->invdKc,   c->Kc,
+                           c->ell_col, c->ell_val,  c->ell_w};
     cgp::launch_pcg_init<double>(c->C, V, false, c->scal, c->part, c->nb_c, s);
     Scal out[1];
     rc = drive(c, c->scal, 1, P.max_iter + 1, 32, true,
@@ -321,7 +342,7 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
     Scal chk{};
     bool converged = false, undone = false;
     double prev_rel = 0.0, eta_floor = P.inner_tol;
-    double* xsave = c->cz;  // FP64 vector unused on this path
+    double* xsave = c->cxsave;
     for (;;) {
       cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
       cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, outer, s);
@@ -350,8 +371,10 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
       prev_rel = chk.rel;
       if (outer >= P.max_outer || inner_total >= P.max_iter) break;
       cgp::launch_copy(x, xsave, c->nc, s);
-      cgp::PcgVecs<float> V{c->cx32, c->cr32, c->cz32, c->cq32, {c->cp32a, c->cp32b},
-                            c->cb32, c->invdKc32, c->Kc32};
+      cgp::PcgVecs<float> V{c->cx32,     c->cp32,       {c->cr32[0], c->cr32[1]},
+                            {c->cw32[0], c->cw32[1]}, {c->cs32[0], c->cs32[1]},
+                            c->cb32,     c->invdKc32,   c->Kc32,
+                            c->ell_col,  c->ell_val32,  c->ell_w};
       cgp::launch_pcg_init<float>(c->C, V, true, c->scal, c->part, c->nb_c, s);
       Scal out[1];
       const int budget = std::max(1, P.max_iter - inner_total);
@@ -481,7 +504,9 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   c->ndir = (int32_t)c->h.dir_nodes.size();
   c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
   // the coarse PCG product kernel requires every block to own a tile
-  c->nb_c = std::min(cgp::kNbMax, std::max(1, c->h.gc.ntiles()));
+  // one row per thread in the PCG iteration kernel; the tiled kernels loop
+  c->nb_c = std::min(cgp::kNbMax, std::max({1, c->h.gc.ntiles(),
+                                            (c->nc + cgp::kBlock - 1) / cgp::kBlock}));
   {  // mean coarse edge length (scale of the learned guess's edge features)
     const cgp::Graph& g = c->h.gc;
     double sum = 0.0;
@@ -569,6 +594,7 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   cgp::launch_mass_assemble(c->F, c->dir_index, c->Mval, c->invdM, c->invdM_int, s);
   cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
                               c->invdKc32, c->lumped_c, s);
+  cgp::launch_make_ell(c->C, c->Kc, c->Kc32, c->ell_w, c->ell_col, c->ell_val, c->ell_val32, s);
   cgp::net::launch_edge_features(c->C, c->hbar, c->net, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -10,6 +10,7 @@ namespace cgp {
 
 constexpr int kBlock = 256;    // threads per block (4 wave64)
 constexpr int kNbMax = 1024;   // blocks per solver launch (partial-sum slots)
+constexpr int kEllPad = 8;     // ELL widths are multiples of this
 constexpr int kSlots = 8;      // reduction slots per right-hand side
 
 // CSR node graph with edge sides (see mesh.hpp), on the device.
@@ -30,12 +31,13 @@ struct DLevel {
 // that takes the decision (every block of it computes the same value) never
 // races with its own write.
 struct Scal {
-  double rho[2];    // PCG: rho of even / odd iterations; BiCGSTAB: rho[0] current
+  double rho[2];    // PCG: gamma of even / odd iterations; BiCGSTAB: rho[0] current
   double rho_old;
   double alpha;
   double omega;
   double bb;        // ||b||^2
   double rel;       // last relative residual seen by the stopping test
+  double pcg_alpha[2];  // PCG: alpha of even / odd iterations
   int32_t done_stamp;
   int32_t iters;
   int32_t status;   // 0 converged, 2 NaN
@@ -73,16 +75,28 @@ void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Sc
 // ---------------------------------------------------------------- PCG (one rhs)
 template <typename T>
 struct PcgVecs {
-  T *x, *r, *z, *q;
-  T* p[2];          // direction, alternating between iterations
+  T* x;             // solution (in: initial guess)
+  T* p;             // direction
+  T* r[2];          // residual, alternating between iterations
+  T* w[2];          // A D^-1 r, alternating
+  T* s[2];          // A p, alternating
   const T* b;
   const T* invd;
-  const T* val;
+  const T* val;       // CSR values (set-up kernels)
+  // fixed-width (ELL) copy of the matrix for the iteration kernel, column
+  // major: entry k of row i at [k * n + i]; width a multiple of kEllPad,
+  // short rows padded with (i, 0)
+  const int32_t* ell_col;
+  const T* ell_val;
+  int32_t ell_w;
 };
 template <typename T>
 void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, bool zero_x0, Scal* sc, double* part,
                      int nb, hipStream_t s);
-// `ev`, when not null, is a pair of events recorded around the product kernel.
+// ELL copy (see PcgVecs) of a CSR matrix's FP64 and FP32 values
+void launch_make_ell(const DLevel& L, const double* val, const float* val32, int w,
+                     int32_t* ell_col, double* ell_val, float* ell_val32, hipStream_t s);
+// `ev`, when not null, is a pair of events recorded around the iteration kernel.
 template <typename T>
 void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* part, int nb, int it,
                      double tol, bool check_only, hipStream_t s, hipEvent_t* ev = nullptr);
@@ -127,7 +141,7 @@ void launch_final_update(int32_t n, const double* ut, const double* du, const do
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
 void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s);
 void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s);
-// n <= 7 scalar records into host-mapped pinned memory
+// n <= 5 scalar records into host-mapped pinned memory
 void launch_mirror(const Scal* src, Scal* host_dst, int n, hipStream_t s);
 void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,
                        double* r, float* r32, double* part, int nb, hipStream_t s);

@@ -73,12 +73,22 @@ template <int NS>
 __device__ void block_sums(const double* part, int nb, const int (&idx)[NS], double (&out)[NS]) {
   __shared__ double sh[NS][kWaves];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // every load of every sum is issued before the first reduction (nb <= kNbMax)
+  double t[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) t[s] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kNbMax / kBlock; ++q) {
+    const int b = threadIdx.x + q * kBlock;
+    if (b < nb) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) t[s] += part[idx[s] + b];
+    }
+  }
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    double t = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) t += part[idx[s] + b];
-    t = wave_sum(t);
-    if (lane == 0) sh[s][wv] = t;
+    const double v = wave_sum(t[s]);
+    if (lane == 0) sh[s][wv] = v;
   }
   __syncthreads();
 #pragma unroll
@@ -130,6 +140,7 @@ __device__ __forceinline__ int stage_tile(TileStage<T>& st, const DLevel& L, con
 }
 
 constexpr int kRowBatch = 8;   // gathers of a row issued together
+static_assert(kRowBatch == kEllPad, "ELL width padding matches the gather batch");
 
 // acc[d] = sum over the staged nonzeros [a, b) of val * g(d, col), the
 // gathers of up to kRowBatch nonzeros in flight at once (in order, so the
@@ -596,22 +607,33 @@ k_bicg_b5(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp)
 }
 
 // ------------------------------------------------------------------ PCG
-// Jacobi-preconditioned CG (vectors of type T, dot products in FP64) in two
-// kernels per iteration; the direction update is folded into the product:
-//   K1(it)  stopping test on r_{it-1} (iters = it - 1), beta = rho_{it-1} / rho_{it-2},
-//           p_it = z + beta p_{it-1} (written to the other p buffer) and
-//           q = A p_it with p_it formed on the fly at the gathered columns,
-//           partial (p_it, q)
-//   K2(it)  alpha = rho_{it-1} / (p, q), x += alpha p, r -= alpha q, z = D^-1 r,
-//           partials (r, z), (r, r)
-// Same arithmetic as the textbook loop (test after the update, then the
-// direction update), one launch fewer per iteration.
+// Jacobi-preconditioned CG (vectors of type T, dot products in FP64) in the
+// single-reduction form of Chronopoulos and Gear (1989).  With z = D^-1 r,
+// w = A z, gamma = (r, z), delta = (z, w):
+//   beta_i  = gamma_i / gamma_{i-1},
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = z_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}  (so s_i = A p_i),
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i.
+// In exact arithmetic these are the textbook iterates (A-conjugacy gives
+// (p_i, A p_i) = delta_i - beta_i gamma_i / alpha_{i-1}); both dot products of
+// an iteration share one reduction, so an iteration is one kernel:
+//   K(it)  sums the partials of iteration it-1 (gamma, delta, (r, r)), tests
+//          ||r_{it-1}|| <= tol ||b|| (iters = it - 1), forms alpha, beta, updates
+//          the row's p, s, x, r and computes w_it = A z_it with z_it formed on
+//          the fly at the gathered columns from r, w, s of iteration it-1,
+//          then the partials of iteration it.
+// r, w and s are read at neighbouring rows, so they alternate between two
+// buffers (K(it) reads [(it-1) & 1], writes [it & 1]); x and p are row-local;
+// z is recomputed where needed.  gamma and alpha alternate in the scalars the
+// same way (written by block 0, read by every block from the other slot), and
+// so do the partial-sum slots (K(it) sums parity (it-1) & 1 while its blocks
+// store parity it & 1).
 
+// r_0 = b - A x_0 (x_0 = 0 when zero_x0)
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_init(DLevel L, PcgVecs<T> V, int zero_x0, Scal* sc, double* part) {
+k_pcg_residual(DLevel L, PcgVecs<T> V, int zero_x0) {
   __shared__ TileStage<T> st;
-  double rz = 0.0, rr = 0.0, bb = 0.0;
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
     int s0 = 0;
@@ -620,175 +642,191 @@ k_pcg_init(DLevel L, PcgVecs<T> V, int zero_x0, Scal* sc, double* part) {
     if (row < r1) {
       T ax[1] = {T(0)};
       if (!zero_x0) tile_row<T, 1>(st, L, s0, row, [&](int, int c) { return V.x[c]; }, ax);
-      const T b = V.b[row];
       if (zero_x0) V.x[row] = T(0);
-      const T r = b - ax[0];
-      const T z = V.invd[row] * r;
-      V.r[row] = r;
-      V.z[row] = z;
-      V.p[0][row] = z;
-      rz += (double)r * (double)z;
-      rr += (double)r * (double)r;
-      bb += (double)b * (double)b;
+      V.r[0][row] = V.b[row] - ax[0];
     }
   }
-  const double vals[3] = {rz, rr, bb};
-  const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
-  block_store<3>(vals, part, idx);
+}
+
+// z_0 = D^-1 r_0, w_0 = A z_0 (z_0 formed at the gathered columns), partials
+// gamma_0, delta_0, (r_0, r_0), (b, b); resets the solver scalars
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_start(DLevel L, PcgVecs<T> V, Scal* sc, double* part) {
+  __shared__ TileStage<T> st;
+  const T* __restrict__ r = V.r[0];
+  const T* __restrict__ dinv = V.invd;
+  double g = 0.0, dl = 0.0, rr = 0.0, bb = 0.0;
+  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+    const int r0 = L.tile[t], r1 = L.tile[t + 1];
+    const int s0 = stage_tile(st, L, V.val, r0, r1);
+    const int row = r0 + threadIdx.x;
+    if (row < r1) {
+      T az[1];
+      tile_row<T, 1>(st, L, s0, row, [&](int, int c) { return dinv[c] * r[c]; }, az);
+      const T rv = r[row], z = dinv[row] * rv, bv = V.b[row];
+      V.w[0][row] = az[0];
+      g += (double)rv * (double)z;
+      dl += (double)z * (double)az[0];
+      rr += (double)rv * (double)rv;
+      bb += (double)bv * (double)bv;
+    }
+  }
+  const double vals[4] = {g, dl, rr, bb};
+  const int idx[4] = {slot(SL_RZ, 0), slot(SL_PQ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
+  block_store<4>(vals, part, idx);
   if (blockIdx.x == 0 && threadIdx.x == 0) reset_scal(sc[0]);
 }
 
+// One thread per row on the ELL copy, so a row's indices and values are one
+// coalesced load away from the thread and the gathers follow directly.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_k1(DLevel L, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double tol,
-         int my_stamp, int check_only) {
-  if (!active(sc, 0, my_stamp)) return;
-  __shared__ TileStage<T> st;
-  constexpr int kPer = kTileNnz / kBlock;
-  const int64_t n = L.n;
-  const T* __restrict__ pold = V.p[(it - 1) & 1];
-  T* __restrict__ pnew = V.p[it & 1];
-  const T* __restrict__ z = V.z;
-  T beta = T(0);
-  double pq = 0.0;
-  // every block owns at least one tile (nb <= ntiles).  On the first tile the
-  // tile is staged and the first kRowBatch gathers of z and p_old are issued
-  // before the reduction of the partial sums (beta is needed only to combine
-  // them), so the three latencies overlap
-  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
-    const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = L.rowptr[r0], cnt = L.rowptr[r1] - s0;
-    const bool first = t == (int)blockIdx.x;
-    const int row = r0 + threadIdx.x;
-    const bool own = row < r1;
-    int a = 0, b = 0;
-    T zr = T(0), por = T(0);
-    if (own) {
-      a = L.rowptr[row] - s0;
-      b = L.rowptr[row + 1] - s0;
-      zr = z[row];
-      por = pold[row];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int k = threadIdx.x + q * kBlock;
-      if (k < cnt) {
-        st.val[k] = V.val[s0 + k];
-        st.col[k] = L.col[s0 + k];
-      }
-    }
-    __syncthreads();
-    // first batch of the row's gathers
-    T gz[kRowBatch], gp[kRowBatch], gv[kRowBatch];
+k_pcg_iter(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, double tol,
+           int my_stamp, int check_only) {
+  const int po = (it - 1) & 1, pn = it & 1;
+  // the solver scalars are read together with the first operands (reading
+  // after the solve has finished is harmless; nothing is written until the
+  // stamp has been tested)
+  const int stamp0 = sc[0].done_stamp;
+  const double bb_prev = sc[0].bb, gam_prev = sc[0].rho[pn], al_prev = sc[0].pcg_alpha[po];
+  const T* __restrict__ ro = V.r[po];
+  const T* __restrict__ wo = V.w[po];
+  const T* __restrict__ so = V.s[po];
+  const T* __restrict__ dinv = V.invd;
+  const int32_t* __restrict__ ecol = V.ell_col;
+  const T* __restrict__ eval = V.ell_val;
+  const int w = V.ell_w;
+  const int64_t ln = n;
+  const bool start = it == 1;  // p_0 = z_0, s_0 = w_0
+  T alpha = T(0), beta = T(0);
+  double g = 0.0, dl = 0.0, rr = 0.0;
+  const int first_row = blockIdx.x * kBlock + threadIdx.x;
+  T xr = T(0), pr = T(0), rv = T(0), wv = T(0), sv = T(0), dv = T(0);
+  T gv[kRowBatch], gr[kRowBatch], gw[kRowBatch], gs[kRowBatch], gd[kRowBatch];
+  // Loads carry no per-entry conditions, so that all of a batch's index loads
+  // are in flight together and then all of its gathers (a condition per entry
+  // splits the batch into blocks that each wait for their own index).  The
+  // ELL width is a multiple of kRowBatch; padding entries are (row, 0).  p and
+  // s are read even at it = 1, where they are not used.
+  auto load_row = [&](int row) {
+    xr = V.x[row];
+    rv = ro[row];
+    wv = wo[row];
+    dv = dinv[row];
+    pr = V.p[row];
+    sv = so[row];
+  };
+  auto load_batch = [&](int row, int k0) {
+    int cix[kRowBatch];
 #pragma unroll
     for (int u = 0; u < kRowBatch; ++u) {
-      gz[u] = gp[u] = gv[u] = T(0);
-      if (own && a + u < b) {
-        const int c = st.col[a + u];
-        gv[u] = st.val[a + u];
-        gz[u] = z[c];
-        gp[u] = pold[c];
-      }
+      const int64_t e = (int64_t)(k0 + u) * ln + row;
+      cix[u] = ecol[e];
+      gv[u] = eval[e];
     }
-    if (first) {
-      const int idx[3] = {slot(SL_RZ, 0), slot(SL_RR, 0), slot(SL_BB, 0)};
-      double s[3];
-      block_sums<3>(part, nb, idx, s);
-      const double bb = it == 1 ? s[2] : sc[0].bb;
-      const double rel = bb > 0.0 ? sqrt(s[1] / bb) : 0.0;
-      const bool nan = !isfinite(bb) || !isfinite(s[1]) || !isfinite(rel);
-      const bool fin = bb == 0.0 || nan || rel <= tol;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (it == 1) sc[0].bb = bb;
-        sc[0].rel = rel;
-        if (fin) {
-          sc[0].done_stamp = my_stamp;
-          sc[0].iters = it - 1;
-          sc[0].status = nan ? 2 : 0;
-        } else {
-          sc[0].rho[(it - 1) & 1] = s[0];
-        }
-      }
-      if (bb == 0.0) {  // zero right-hand side: the solution is zero
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-          V.x[i] = T(0);
-        return;
-      }
-      if (fin || check_only) return;
-      beta = it == 1 ? T(0) : (T)(s[0] / sc[0].rho[(it - 2) & 1]);
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int c = cix[u];
+      gr[u] = ro[c];
+      gw[u] = wo[c];
+      gd[u] = dinv[c];
+      gs[u] = so[c];
     }
-    if (own) {
-      // same summation order as tile_row_range: batches of kRowBatch in row order
-      T acc = T(0);
-#pragma unroll
-      for (int u = 0; u < kRowBatch; ++u)
-        if (a + u < b) acc += gv[u] * (gz[u] + beta * gp[u]);
-      for (int s = a + kRowBatch; s < b; s += kRowBatch) {
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u)
-          if (s + u < b) {
-            const int c = st.col[s + u];
-            gv[u] = st.val[s + u];
-            gz[u] = z[c];
-            gp[u] = pold[c];
-          }
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u)
-          if (s + u < b) acc += gv[u] * (gz[u] + beta * gp[u]);
-      }
-      const T pr = zr + beta * por;
-      pnew[row] = pr;
-      V.q[row] = acc;
-      pq += (double)pr * (double)acc;
-    }
+  };
+  // the first row's operands and gathers are issued before the reduction of
+  // the partial sums (alpha and beta are needed only to combine them)
+  if (first_row < n) {
+    load_row(first_row);
+    load_batch(first_row, 0);
   }
-  const double vals[1] = {pq};
-  const int o[1] = {slot(SL_PQ, 0)};
-  block_store<1>(vals, part, o);
+  if (!(stamp0 == 0 || stamp0 >= my_stamp)) return;  // solve already finished
+  {
+    const int idx[4] = {slot(SL_RZ, po), slot(SL_PQ, po), slot(SL_RR, po), slot(SL_BB, 0)};
+    double sm[4];
+    block_sums<4>(part, nb, idx, sm);
+    const double bb = start ? sm[3] : bb_prev;
+    const double rel = bb > 0.0 ? sqrt(sm[2] / bb) : 0.0;
+    const bool nan = !isfinite(bb) || !isfinite(sm[2]) || !isfinite(rel);
+    const bool fin = bb == 0.0 || nan || rel <= tol;
+    double al = 0.0, be = 0.0;
+    if (!fin) {
+      be = start ? 0.0 : sm[0] / gam_prev;
+      al = start ? sm[0] / sm[1] : sm[0] / (sm[1] - be * sm[0] / al_prev);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (start) sc[0].bb = bb;
+      sc[0].rel = rel;
+      if (fin) {
+        sc[0].done_stamp = my_stamp;
+        sc[0].iters = it - 1;
+        sc[0].status = nan ? 2 : 0;
+      } else {
+        sc[0].rho[po] = sm[0];
+        sc[0].pcg_alpha[pn] = al;
+        sc[0].alpha = al;
+      }
+    }
+    if (bb == 0.0) {  // zero right-hand side: the solution is zero
+      for (int i = first_row; i < n; i += gridDim.x * kBlock) V.x[i] = T(0);
+      return;
+    }
+    if (fin || check_only) return;
+    alpha = (T)al;
+    beta = (T)be;
+  }
+  for (int row = first_row; row < n; row += gridDim.x * kBlock) {
+    if (row != first_row) {
+      load_row(row);
+      load_batch(row, 0);
+    }
+    const T zo = dv * rv;
+    const T pnw = start ? zo : zo + beta * pr;
+    const T sn = start ? wv : wv + beta * sv;
+    const T rn = rv - alpha * sn;
+    const T zn = dv * rn;
+    // w_it at this row: z_it of each neighbour from its r, w, s of it-1, in
+    // row order in batches of kRowBatch
+    T acc = T(0);
+    for (int k0 = 0; k0 < w; k0 += kRowBatch) {
+      if (k0 > 0) load_batch(row, k0);
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const T snc = start ? gw[u] : gw[u] + beta * gs[u];
+        acc += gv[u] * (gd[u] * (gr[u] - alpha * snc));
+      }
+    }
+    V.x[row] = xr + alpha * pnw;
+    V.p[row] = pnw;
+    V.r[pn][row] = rn;
+    V.s[pn][row] = sn;
+    V.w[pn][row] = acc;
+    g += (double)rn * (double)zn;
+    dl += (double)zn * (double)acc;
+    rr += (double)rn * (double)rn;
+  }
+  // this kernel reads the partials of it-1 while other blocks may already be
+  // storing those of it: the two use the slots of opposite parity
+  const double vals[3] = {g, dl, rr};
+  const int o[3] = {slot(SL_RZ, pn), slot(SL_PQ, pn), slot(SL_RR, pn)};
+  block_store<3>(vals, part, o);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_k2(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, int my_stamp) {
-  if (!active(sc, 0, my_stamp)) return;
-  const T* __restrict__ p = V.p[it & 1];
-  // the first row's operands are loaded before the reduction (latency overlap)
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  T xi = T(0), pi = T(0), ri = T(0), qi = T(0), di = T(0);
-  if (i < n) {
-    xi = V.x[i];
-    pi = p[i];
-    ri = V.r[i];
-    qi = V.q[i];
-    di = V.invd[i];
-  }
-  const int idx[1] = {slot(SL_PQ, 0)};
-  double pq[1];
-  block_sums<1>(part, nb, idx, pq);
-  const double a = sc[0].rho[(it - 1) & 1] / pq[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[0].alpha = a;
-  const T alpha = (T)a;
-  double rz = 0.0, rr = 0.0;
-  for (; i < n; i += gridDim.x * blockDim.x) {
-    if (i != (int)(blockIdx.x * blockDim.x + threadIdx.x)) {
-      xi = V.x[i];
-      pi = p[i];
-      ri = V.r[i];
-      qi = V.q[i];
-      di = V.invd[i];
+// ELL copy of a CSR matrix (row order kept: diagonal first, then columns
+// ascending; padding (i, 0))
+__global__ void k_make_ell(DLevel L, const double* __restrict__ val,
+                           const float* __restrict__ val32, int w, int32_t* __restrict__ ecol,
+                           double* __restrict__ ev, float* __restrict__ ev32) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L.n; i += gridDim.x * blockDim.x) {
+    const int beg = L.rowptr[i], len = L.rowptr[i + 1] - beg;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = (int64_t)k * L.n + i;
+      const bool in = k < len;
+      ecol[e] = in ? L.col[beg + k] : i;
+      ev[e] = in ? val[beg + k] : 0.0;
+      ev32[e] = in ? val32[beg + k] : 0.0f;
     }
-    V.x[i] = xi + alpha * pi;
-    const T r = ri - alpha * qi;
-    V.r[i] = r;
-    const T z = di * r;
-    V.z[i] = z;
-    rz += (double)r * (double)z;
-    rr += (double)r * (double)r;
   }
-  const double vals[2] = {rz, rr};
-  const int o[2] = {slot(SL_RZ, 0), slot(SL_RR, 0)};
-  block_store<2>(vals, part, o);
 }
 
 // ------------------------------------------------------------------ Chebyshev
@@ -1220,17 +1258,23 @@ void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Sc
 template <typename T>
 void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, bool zero_x0, Scal* sc, double* part,
                      int nb, hipStream_t s) {
-  k_pcg_init<T><<<nb, kBlock, 0, s>>>(L, V, zero_x0 ? 1 : 0, sc, part);
+  k_pcg_residual<T><<<nb, kBlock, 0, s>>>(L, V, zero_x0 ? 1 : 0);
+  k_pcg_start<T><<<nb, kBlock, 0, s>>>(L, V, sc, part);
 }
 
 template <typename T>
 void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* part, int nb, int it,
                      double tol, bool check_only, hipStream_t s, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
-  k_pcg_k1<T><<<nb, kBlock, 0, s>>>(L, V, sc, part, nb, it, tol, stamp(it, 1), check_only ? 1 : 0);
+  k_pcg_iter<T><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, tol, stamp(it, 1),
+                                      check_only ? 1 : 0);
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (check_only) return;
-  k_pcg_k2<T><<<nb, kBlock, 0, s>>>(L.n, V, sc, part, nb, it, stamp(it, 2));
+}
+
+void launch_make_ell(const DLevel& L, const double* val, const float* val32, int w,
+                     int32_t* ell_col, double* ell_val, float* ell_val32, hipStream_t s) {
+  k_make_ell<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, val, val32, w, ell_col, ell_val,
+                                                       ell_val32);
 }
 
 template void launch_pcg_init<double>(const DLevel&, const PcgVecs<double>&, bool, Scal*, double*,

@@ -307,6 +307,30 @@ def test_mixed_precision_step(name, wf):
     assert rel(np_(P_g), P_o) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_coarse_solve_bitwise_reproducible(prec):
+    """The same coarse solve five times: identical iterates and counts (the
+    reductions are fixed-order and every buffer a kernel reads is disjoint
+    from the ones its blocks write)."""
+    w = cavity(129, 1, chi=0).with_(precision=0 if prec == "fp64" else 1, pcg_tol=1e-8)
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g, seed=9)
+    uD = g.to_device(w.dirichlet_values(o.fine_xy[o.dir], w.dt))
+    Ut, _ = g.momentum(g.to_device(Um), g.to_device(U0), g.to_device(P0), uD)
+    b = g.restrict(Ut)
+    guess = g.to_device(np.random.default_rng(3).standard_normal(g.nc) * 1e-3)
+    outs, its = [], []
+    for _ in range(5):
+        phi = guess.clone()
+        st = g.pcg_solve(b, phi)
+        outs.append(np_(phi))
+        its.append((st["iters"], st["outer_iters"]))
+    print(f"[result] {prec}: iterations {its}", flush=True)
+    assert all(i == its[0] for i in its)
+    for x in outs[1:]:
+        np.testing.assert_array_equal(x, outs[0])
+
+
 def test_mixed_refinement_survives_unreachable_inner_tolerance():
     """An inner tolerance below what FP32 resolves on the operator: stalled
     inner solves end early, corrections that do not pay are undone and the
