@@ -25,12 +25,16 @@
  *    allocates one small pinned host buffer (hipHostMalloc) per context for
  *    convergence flags.
  *  - Node numbering of the fine mesh (the only numbering seen at the ABI):
- *    the coarse nodes keep their numbers 0..N_c-1; each refinement appends the
- *    midpoint of every edge in first-encounter order over (triangle, local
- *    edge (0,1), (1,2), (2,0)); triangle (a,b,c) with midpoints m_ab, m_bc,
- *    m_ca has children (a,m_ab,m_ca), (m_ab,b,m_bc), (m_ca,m_bc,c),
- *    (m_ab,m_bc,m_ca) in that order.  A boundary edge (p,q) splits into
- *    (p,m), (m,q) with the parent's tag.
+ *    refinement level by level appends the midpoint of every edge in
+ *    first-encounter order over (triangle, local edge (0,1), (1,2), (2,0));
+ *    triangle (a,b,c) with midpoints m_ab, m_bc, m_ca has children
+ *    (a,m_ab,m_ca), (m_ab,b,m_bc), (m_ca,m_bc,c), (m_ab,m_bc,m_ca) in that
+ *    order, and a boundary edge (p,q) splits into (p,m), (m,q) with the
+ *    parent's tag.  The finest level is then numbered: the coarse nodes keep
+ *    0..N_c-1, and the new nodes follow, stably sorted by the coarse triangle
+ *    that is the ancestor of the triangle that first created them (the nodes
+ *    of one coarse triangle are contiguous).  Fine triangles keep their
+ *    order: those of coarse triangle T are T*4^k .. (T+1)*4^k - 1.
  *  - Field layout: velocities are structure-of-arrays float64 [2][N_f]
  *    (u then v); scalars float64 [N]; all arrays dense and contiguous.
  */

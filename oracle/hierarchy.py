@@ -6,11 +6,17 @@ Oracle (test infrastructure only).
   midpoints, so a mesh with N elements refined k times has 4^k N elements and
   the spaces are nested, V_1 c V_2 c V_3 c V_4.
 * Node numbering convention (shared with the library's C-ABI as an interface,
-  not as code): the parent level's nodes keep their numbers; new midpoint nodes
-  are appended in first-encounter order over (triangle, local edge (0,1),
-  (1,2), (2,0)).  Children of (a, b, c) with midpoints m_ab, m_bc, m_ca are
-  (a, m_ab, m_ca), (m_ab, b, m_bc), (m_ca, m_bc, c), (m_ab, m_bc, m_ca), in
-  that order.  Boundary edge e = (p, q) becomes (p, m), (m, q) with e's tag.
+  not as code).  Each refinement keeps the parent level's nodes and appends
+  the midpoint of every edge in first-encounter order over (triangle, local
+  edge (0,1), (1,2), (2,0)); children of (a, b, c) with midpoints m_ab, m_bc,
+  m_ca are (a, m_ab, m_ca), (m_ab, b, m_bc), (m_ca, m_bc, c), (m_ab, m_bc,
+  m_ca), in that order; boundary edge e = (p, q) becomes (p, m), (m, q) with
+  e's tag.  The finest mesh is then renumbered: the coarse nodes keep 0..N_c-1
+  and the new nodes follow, stably sorted by their owner, the coarse
+  triangle that is the ancestor of the triangle that first created them, so
+  that the nodes of one coarse triangle are contiguous (the library's
+  neighbour gathers stay local in memory).  Intermediate levels keep the
+  level-by-level numbering.
 * Restriction is pure injection: the coarse value at a coarse node is the fine
   value at the coincident fine node.  With the numbering above that node has
   the same index.
@@ -27,8 +33,10 @@ from workloads.meshes import DIRICHLET, NATURAL
 
 
 def refine_once(xy, tri, bedge, btag):
-    """One level of 4:1 refinement.  Returns (xy, tri, bedge, btag, ends),
-    where ends[m - n_parent] = (a, b) are the parent edge ends of new node m."""
+    """One level of 4:1 refinement.  Returns (xy, tri, bedge, btag, ends,
+    creator), where ends[m - n_parent] = (a, b) are the parent edge ends of
+    new node m and creator[m - n_parent] the parent triangle that first
+    encountered that edge."""
     xy = np.asarray(xy, np.float64)
     tri = np.asarray(tri, np.int64)
     bedge = np.asarray(bedge, np.int64)
@@ -64,7 +72,8 @@ def refine_once(xy, tri, bedge, btag):
     new_bedge = np.stack([np.stack([bedge[:, 0], bm], 1),
                           np.stack([bm, bedge[:, 1]], 1)], axis=1).reshape(-1, 2)
     new_btag = np.repeat(np.asarray(btag), 2)
-    return new_xy, kids, new_bedge, new_btag, ends
+    creator = first[order] // 3
+    return new_xy, kids, new_bedge, new_btag, ends, creator
 
 
 class Hierarchy:
@@ -78,10 +87,30 @@ class Hierarchy:
         bedge, btag = np.asarray(coarse["bedge"], np.int64), np.asarray(coarse["btag"], np.int64)
         self.meshes = [dict(xy=xy, tri=tri, bedge=bedge, btag=btag)]
         self.ends = []          # ends[l]: parent pairs of the nodes added at refinement l+1
-        for _ in range(levels):
-            xy, tri, bedge, btag, ends = refine_once(xy, tri, bedge, btag)
+        owner = np.full(xy.shape[0], -1, np.int64)   # coarse triangle that created a node
+        for l in range(levels):
+            xy, tri, bedge, btag, ends, creator = refine_once(xy, tri, bedge, btag)
+            # level-l triangle t descends from coarse triangle t // 4^l
+            owner = np.concatenate([owner, creator >> (2 * l)])
             self.meshes.append(dict(xy=xy, tri=tri, bedge=bedge, btag=btag))
             self.ends.append(ends)
+        nc = self.meshes[0]["xy"].shape[0]
+        nf = xy.shape[0]
+        # canonical fine numbering: coarse nodes first, then the new nodes
+        # stably sorted by owner; canon[levelwise id] = canonical id
+        self.canon = np.arange(nf)
+        if levels:
+            order = nc + np.argsort(owner[nc:], kind="stable")
+            self.canon[order] = np.arange(nc, nf)
+            self.owner = np.empty(nf, np.int64)
+            self.owner[self.canon] = owner
+            fine = self.meshes[-1]
+            fxy = np.empty_like(fine["xy"])
+            fxy[self.canon] = fine["xy"]
+            self.meshes[-1] = dict(xy=fxy, tri=self.canon[fine["tri"]],
+                                   bedge=self.canon[fine["bedge"]], btag=fine["btag"])
+        else:
+            self.owner = owner
 
     @property
     def coarse(self):
@@ -97,11 +126,14 @@ class Hierarchy:
         return np.asarray(uf)[..., :nc].copy()
 
     def prolong(self, phic):
-        """Linear prolongation P applied k times (Eq. 24)."""
+        """Linear prolongation P applied k times (Eq. 24), level by level in
+        the level-wise numbering, then put in the canonical fine order."""
         phi = np.asarray(phic, np.float64).copy()
         for ends in self.ends:
             phi = np.concatenate([phi, 0.5 * (phi[ends[:, 0]] + phi[ends[:, 1]])])
-        return phi
+        out = np.empty_like(phi)
+        out[self.canon] = phi
+        return out
 
     def prolongation_matrix(self):
         """P = P_k ... P_1 as an explicit N_f x N_c sparse matrix: each level
@@ -115,7 +147,9 @@ class Hierarchy:
             vals = np.concatenate([np.ones(n), np.full(m, 0.5), np.full(m, 0.5)])
             Pl = sp.coo_matrix((vals, (rows, cols)), shape=(n + m, n)).tocsr()
             P = (Pl @ P).tocsr()
-        return P
+        inv = np.empty_like(self.canon)
+        inv[self.canon] = np.arange(self.canon.size)
+        return P[inv].tocsr()
 
 
 def boundary_nodes(mesh: dict, tag: int) -> np.ndarray:

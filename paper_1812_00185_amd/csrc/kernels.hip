@@ -845,12 +845,14 @@ k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_i
        const double* __restrict__ b, double* __restrict__ xk, const double* __restrict__ xkm,
        double* __restrict__ xnew, double ca, double cb, int first) {
   __shared__ TileStage<double> st;
-  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
+  {  // one block per tile, in block order: a mapping that gave each XCD a
+     // contiguous range of tiles was measured slower (227 -> 321 us at 2049^2)
+    const int t = blockIdx.x;
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
     int s0 = 0;
     if (!first) s0 = stage_tile(st, L, M, r0, r1);
     const int row = r0 + threadIdx.x;
-    if (row >= r1) continue;
+    if (row >= r1) return;
     double mx[NR];
     if (!first)
       tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[(int64_t)c * NR + d]; },

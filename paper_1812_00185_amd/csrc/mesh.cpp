@@ -264,6 +264,39 @@ std::string build_hierarchy(const Mesh& coarse, int levels, Hierarchy& h) {
     bary.swap(nb);
     cur = std::move(nxt);
   }
+  if (levels > 0) {
+    // canonical fine numbering: the coarse nodes keep 0..N_c-1, the new nodes
+    // follow stably sorted by the coarse triangle that created them
+    // (code_T), so that the nodes of one coarse triangle are contiguous and
+    // neighbour gathers stay local in memory
+    const int32_t n = cur.n_nodes;
+    std::vector<int32_t> order(n - nc);
+    std::iota(order.begin(), order.end(), nc);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return code_T[a] < code_T[b]; });
+    std::vector<int32_t> canon(n);
+    for (int32_t i = 0; i < nc; ++i) canon[i] = i;
+    for (int32_t k = 0; k < n - nc; ++k) canon[order[k]] = nc + k;
+    Mesh f;
+    f.n_nodes = n;
+    f.n_tris = cur.n_tris;
+    f.xy.resize(cur.xy.size());
+    std::vector<int32_t> cT(n), cN(n);
+    for (int32_t i = 0; i < n; ++i) {
+      f.xy[2 * (size_t)canon[i]] = cur.xy[2 * (size_t)i];
+      f.xy[2 * (size_t)canon[i] + 1] = cur.xy[2 * (size_t)i + 1];
+      cT[canon[i]] = code_T[i];
+      cN[canon[i]] = code_n[i];
+    }
+    f.tri.resize(cur.tri.size());
+    for (size_t k = 0; k < cur.tri.size(); ++k) f.tri[k] = canon[cur.tri[k]];
+    f.bedge.resize(cur.bedge.size());
+    for (size_t k = 0; k < cur.bedge.size(); ++k) f.bedge[k] = canon[cur.bedge[k]];
+    f.btag = cur.btag;
+    cur = std::move(f);
+    code_T.swap(cT);
+    code_n.swap(cN);
+  }
   h.fine = std::move(cur);
   const int32_t nf = h.fine.n_nodes;
   for (int32_t i = 0; i < nf; ++i)

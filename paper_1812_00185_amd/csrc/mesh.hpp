@@ -65,7 +65,8 @@ struct Hierarchy {
 // boundary edge tagged exactly once with a known tag).  Returns "" when valid.
 std::string validate(const Mesh& m);
 
-// One level of uniform refinement with the library's node numbering.
+// One level of uniform refinement, new nodes appended in first-encounter
+// order (build_hierarchy renumbers the finest level).
 Mesh refine(const Mesh& m);
 
 Graph build_graph(const Mesh& m);

@@ -109,3 +109,31 @@ def test_channel_boundary_tags_inherited():
     nat = natural_nodes(f)
     assert np.all(np.isclose(f["xy"][nat, 0], 2.2))
     assert f["bedge"].shape[0] == 4 * h.coarse["bedge"].shape[0]
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_fine_numbering_groups_nodes_by_owner_coarse_triangle(levels):
+    """Canonical fine order: coarse nodes first, then the new nodes grouped by
+    the coarse triangle that created them; every new node lies in that
+    triangle (closed), and the fine mesh is the same point and triangle set as
+    the level-by-level refinement."""
+    m = disc(20, 30, seed=6)
+    h = Hierarchy(m, levels)
+    nc = h.coarse["xy"].shape[0]
+    own = h.owner[nc:]
+    assert np.all(np.diff(own) >= 0) and own.min() >= 0
+    xy = h.fine["xy"][nc:]
+    t = h.coarse["tri"][own]
+    A, B, C = (h.coarse["xy"][t[:, k]] for k in range(3))
+    det = (B[:, 0] - A[:, 0]) * (C[:, 1] - A[:, 1]) - (C[:, 0] - A[:, 0]) * (B[:, 1] - A[:, 1])
+    l1 = ((xy[:, 0] - A[:, 0]) * (C[:, 1] - A[:, 1]) - (C[:, 0] - A[:, 0]) * (xy[:, 1] - A[:, 1])) / det
+    l2 = ((B[:, 0] - A[:, 0]) * (xy[:, 1] - A[:, 1]) - (xy[:, 0] - A[:, 0]) * (B[:, 1] - A[:, 1])) / det
+    tol = 1e-12
+    assert np.all(l1 >= -tol) and np.all(l2 >= -tol) and np.all(l1 + l2 <= 1 + tol)
+    # distinct points; triangles keep their order (those of coarse triangle T
+    # are T*4^k ... (T+1)*4^k - 1) and orientation
+    key = np.round(h.fine["xy"] * 2 ** 30).astype(np.int64)
+    assert len({tuple(k) for k in key}) == h.fine["xy"].shape[0]
+    F, c = fem.Operators(h.fine), fem.Operators(h.coarse)
+    assert np.all(F.area > 0)
+    np.testing.assert_allclose(F.area.reshape(-1, 4 ** levels).sum(1), c.area, rtol=1e-13)
