@@ -43,13 +43,14 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per launch of each timed kernel (int32 indices, FP64 values):
 # CSR matrix 12 B/nnz + 4 B/row pointer; every vector once.
 #  mass_spmv:   one fused Chebyshev step over nr right-hand sides: Dirichlet
-#               index 4 B + two Jacobi diagonals 16 B per row, and per rhs the
-#               gathered iterate, the previous iterate, b and the new iterate
+#               index 4 B per row (the Jacobi diagonal is the row's first
+#               matrix entry), and per rhs the gathered iterate, the previous
+#               iterate, b and the new iterate
 #  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written
 #  coarse_spmv: one single-reduction PCG iteration: x, p, r, w, s, D^-1 read,
 #               x, p, r, w, s written
 KERNELS = {
-    "mass_spmv": (1, lambda n, z, nr: 12 * z + 4 * (n + 1) + 20 * n + 32 * nr * n),
+    "mass_spmv": (1, lambda n, z, nr: 12 * z + 4 * (n + 1) + 4 * n + 32 * nr * n),
     "mom_spmv": (2, lambda n, z, nr: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
     "coarse_spmv": (3, lambda n, z, nr: 12 * z + 4 * (n + 1) + 11 * 8 * n),
 }

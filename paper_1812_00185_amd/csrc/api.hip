@@ -65,8 +65,7 @@ struct cgp_ctx {
   int32_t *tri_f = nullptr, *tri_c = nullptr, *pcode = nullptr, *cn_ptr = nullptr,
           *cn_tri = nullptr, *dir_index = nullptr;
   uint8_t* nat_c = nullptr;
-  double *Mval = nullptr, *Aval = nullptr, *invdA = nullptr, *invdM = nullptr,
-         *invdM_int = nullptr;
+  double *Mval = nullptr, *Aval = nullptr, *invdA = nullptr;
   double *Kc = nullptr, *Dxc = nullptr, *Dyc = nullptr, *invdKc = nullptr, *lumped_c = nullptr;
   float *Kc32 = nullptr, *invdKc32 = nullptr;
   // ELL copy of K_c for the PCG iteration kernel (width = longest row)
@@ -127,8 +126,6 @@ size_t carve(cgp_ctx* c, void* base) {
   c->Mval = w.take<double>(nnzf);
   c->Aval = w.take<double>(nnzf);
   c->invdA = w.take<double>(nf);
-  c->invdM = w.take<double>(nf);
-  c->invdM_int = w.take<double>(nf);
   int32_t* tile_f = w.take<int32_t>(c->h.gf.tile.size());
   double** vec2[] = {&c->ut, &c->rhs, &c->r, &c->rhat, &c->p, &c->v, &c->phat, &c->shat, &c->t};
   for (double** q : vec2) *q = w.take<double>(2 * nf);
@@ -437,8 +434,8 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   // velocity: M dU = -(2/3) dt G phi_f on the non-Dirichlet nodes; rotational
   // form: M dp = -nu D U~ on all nodes -- one fused Chebyshev solve
   cgp::launch_correct_rhs(c->F, c->dir_index, P.dt, P.nu, chi, phi_f, ut, c->mrhs, s);
-  const double* du = cgp::launch_cheb(c->F, c->Mval, c->invdM_int, c->invdM, c->dir_index,
-                                      c->mrhs, chi ? 3 : 2, c->mx, c->cheb_iters, s,
+  const double* du = cgp::launch_cheb(c->F, c->Mval, c->dir_index, c->mrhs, chi ? 3 : 2, c->mx,
+                                      c->cheb_iters, s,
                                       c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
   if (st) {
     // a-priori bound of the Chebyshev iteration on [1/2, 2]
@@ -591,7 +588,7 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   for (int k = 0; k < 2; ++k)
     if (!c->ev[k]) HIPCHK(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c->scal, 0, sizeof(Scal) * 8, s));
-  cgp::launch_mass_assemble(c->F, c->dir_index, c->Mval, c->invdM, c->invdM_int, s);
+  cgp::launch_mass_assemble(c->F, c->Mval, s);
   cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
                               c->invdKc32, c->lumped_c, s);
   cgp::launch_make_ell(c->C, c->Kc, c->Kc32, c->ell_w, c->ell_col, c->ell_val, c->ell_val32, s);

@@ -47,8 +47,7 @@ struct Scal {
 inline int stamp(int it, int phase) { return it * 8 + phase; }
 
 // ---------------------------------------------------------------- assembly
-void launch_mass_assemble(const DLevel& L, const int32_t* dir_index, double* Mval,
-                          double* invd_full, double* invd_int, hipStream_t s);
+void launch_mass_assemble(const DLevel& L, double* Mval, hipStream_t s);
 void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
                             double* Dxval, double* Dyval, double* invd, float* invd32,
                             double* lumped, hipStream_t s);
@@ -106,8 +105,8 @@ int cheb_iterations(double tol);
 // Solves M x = b for nr (2 or 3) right-hand sides interleaved [n][nr]; returns the
 // buffer (one of x[0..2]) holding the result.  `timer(tctx)`, when given,
 // supplies an event pair per product launch.
-double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
-                    const double* invd_full, const int32_t* dir_index, const double* b, int nr,
+double* launch_cheb(const DLevel& L, const double* Mval, const int32_t* dir_index,
+                    const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx);
 

@@ -205,8 +205,7 @@ __device__ __forceinline__ void group_sum(double (&v)[NS]) {
 // ------------------------------------------------------------------ assembly
 
 __global__ void __launch_bounds__(kBlock)
-k_mass_assemble(DLevel L, const int32_t* __restrict__ dir_index, double* __restrict__ Mval,
-                double* __restrict__ invd_full, double* __restrict__ invd_int) {
+k_mass_assemble(DLevel L, double* __restrict__ Mval) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L.n; i += gridDim.x * blockDim.x) {
     const int beg = L.rowptr[i], end = L.rowptr[i + 1];
     const double2 pi = L.xy[i];
@@ -224,8 +223,6 @@ k_mass_assemble(DLevel L, const int32_t* __restrict__ dir_index, double* __restr
       dm += m;
     }
     Mval[beg] = dm;
-    invd_full[i] = 1.0 / dm;
-    invd_int[i] = (dir_index && dir_index[i] >= 0) ? 0.0 : 1.0 / dm;
   }
 }
 
@@ -840,8 +837,7 @@ __global__ void k_make_ell(DLevel L, const double* __restrict__ val,
 // gathered neighbour costs one contiguous access.
 template <int NR>
 __global__ void __launch_bounds__(kBlock)
-k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_int,
-       const double* __restrict__ invd_full, const int32_t* __restrict__ dir_index,
+k_cheb(DLevel L, const double* __restrict__ M, const int32_t* __restrict__ dir_index,
        const double* __restrict__ b, double* __restrict__ xk, const double* __restrict__ xkm,
        double* __restrict__ xnew, double ca, double cb, int first) {
   __shared__ TileStage<double> st;
@@ -857,13 +853,15 @@ k_cheb(DLevel L, const double* __restrict__ M, const double* __restrict__ invd_i
     if (!first)
       tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[(int64_t)c * NR + d]; },
                            mx);
+    // Jacobi scaling by the diagonal (the first entry of the row), which is
+    // in LDS already; the first step reads it from memory
+    const double mii = first ? M[L.rowptr[row]] : st.val[L.rowptr[row] - s0];
+    const double di = 1.0 / mii;
     const bool masked = dir_index[row] >= 0;
-    const double di_int = invd_int[row], di_full = NR > 2 ? invd_full[row] : 0.0;
     const int64_t base = (int64_t)row * NR;
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
       const int64_t k = base + d;
-      const double di = d < 2 ? di_int : di_full;
       double v;
       if (d < 2 && masked)
         v = 0.0;
@@ -1216,9 +1214,8 @@ inline int row_group_grid(int64_t rows) { return grid_for(rows, kBlock / kRowLan
 
 // ------------------------------------------------------------------ launchers
 
-void launch_mass_assemble(const DLevel& L, const int32_t* dir_index, double* Mval,
-                          double* invd_full, double* invd_int, hipStream_t s) {
-  k_mass_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, dir_index, Mval, invd_full, invd_int);
+void launch_mass_assemble(const DLevel& L, double* Mval, hipStream_t s) {
+  k_mass_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, Mval);
 }
 
 void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
@@ -1296,8 +1293,8 @@ int cheb_iterations(double tol) {
   return m < 1 ? 1 : m;
 }
 
-double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
-                    const double* invd_full, const int32_t* dir_index, const double* b, int nr,
+double* launch_cheb(const DLevel& L, const double* Mval, const int32_t* dir_index,
+                    const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx) {
   const double lo = 0.5, hi = 2.0;
@@ -1318,11 +1315,9 @@ double* launch_cheb(const DLevel& L, const double* Mval, const double* invd_int,
     hipEvent_t* ev = (timer && k > 0) ? timer(tctx) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (nr == 3)
-      k_cheb<3><<<g, kBlock, 0, s>>>(L, Mval, invd_int, invd_full, dir_index, b, xk, xkm, xn, ca,
-                                     cb, k == 0);
+      k_cheb<3><<<g, kBlock, 0, s>>>(L, Mval, dir_index, b, xk, xkm, xn, ca, cb, k == 0);
     else
-      k_cheb<2><<<g, kBlock, 0, s>>>(L, Mval, invd_int, invd_full, dir_index, b, xk, xkm, xn, ca,
-                                     cb, k == 0);
+      k_cheb<2><<<g, kBlock, 0, s>>>(L, Mval, dir_index, b, xk, xkm, xn, ca, cb, k == 0);
     if (ev) (void)hipEventRecord(ev[1], s);
   }
   return x[iters % 3];
