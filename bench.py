@@ -26,6 +26,7 @@ reported beside it in the same JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -58,6 +59,34 @@ KERNELS = {
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# committed rocprofv3 counter summaries of the timed kernel, per workload
+TRAFFIC_RECORDS = {("tg2049_k3_fp64", "mass_spmv"): "k_cheb3_tg2049_k3_fp64_traffic.md"}
+
+
+def stored_traffic(workload, kernel):
+    """Measured HBM bytes per launch (FETCH_SIZE and WRITE_SIZE passes scaled
+    by a calibration kernel) from the committed counter summary, or None when
+    there is none or the kernels' source has changed since it was taken."""
+    name = TRAFFIC_RECORDS.get((workload, kernel))
+    if not name:
+        return None, "no counter summary for this workload and kernel"
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_1812_00185_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError as e:
+        return None, str(e)
+    rec = {}
+    for line in text.splitlines():
+        if line.startswith("    ") and ": " in line:
+            k, v = line.strip().split(": ", 1)
+            rec[k] = v
+    if rec.get("kernels_hip_sha256") != digest:
+        return None, "kernels changed since the counters were taken"
+    return int(rec["traffic_bytes_per_launch"]), f"profiles/{name}"
 
 
 def rel(a, b):
@@ -237,10 +266,12 @@ def main():
     bpl = kbytes(n_rows, nnz, 3 if w.chi else 2)
     avg_s = (kms / 1e3) / max(nlaunch, 1)
     achieved = bpl / avg_s / 1e9 if nlaunch else None
+    traffic, traffic_src = stored_traffic(w.name, args.timed_kernel)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "kernel": args.timed_kernel, "form": main_form, "launches": nlaunch,
-                "avg_us": avg_s * 1e6, "bytes_per_launch": bpl}
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_source": traffic_src, "kernel": args.timed_kernel, "form": main_form,
+                "launches": nlaunch, "avg_us": avg_s * 1e6, "bytes_per_launch": bpl,
+                "measured_gbs": (traffic / avg_s / 1e9) if (traffic and nlaunch) else None}
 
     # coarse-solve time to tolerance along the timed trajectory, every guess
     # solving the same right-hand side to the same FP64 tolerance
