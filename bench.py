@@ -10,6 +10,9 @@ run over the same trajectory:
   plain_fp64     FP64 Jacobi-PCG from the previous increment (the paper's step)
   learned_mixed  guarded learned guess + FP32-inner / FP64-refinement PCG
   learned_fp64   guarded learned guess + FP64 PCG
+  lumped_p_fp64  plain FP64 with the lumped-mass pressure update (Eq. 27)
+  lumped_fp64    plain FP64 with lumped mass in Eqs. 25 and 27 (no mass solves)
+and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
 trajectories than the timed one).  `value` is the plain_fp64 throughput in
@@ -161,7 +164,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain_fp64,learned_mixed,learned_fp64")
+    ap.add_argument("--forms",
+                    default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain FP64 form only: no training, no learned forms or legs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -202,10 +206,14 @@ def main():
     t0 = time.perf_counter()
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64", **kw)
     gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="mixed", **kw)
+    solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
+    for form, mass in (("lumped_p_fp64", "lumped_p"), ("lumped_fp64", "lumped")):
+        if form in forms:
+            solvers[form] = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64",
+                                mass=mass, **kw)
     torch.cuda.synchronize()
     log(f"[bench] {w.name}: N_f={g.nf} N_c={g.nc} nnz_f={g.sizes.nnz_fine} "
         f"set-up {time.perf_counter() - t0:.1f} s")
-    solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
 
     # --- train the learned guess on other trajectories (phase-shifted flows)
     theta = None
@@ -223,7 +231,8 @@ def main():
         del runs
         log(f"[bench] trained on {n_samples} pairs in {t_train:.1f} s (collect "
             f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
-    thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta}
+    thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
+              "lumped_p_fp64": None, "lumped_fp64": None}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]
@@ -249,6 +258,13 @@ def main():
         results[form] = {"value": 3 * g.nf * args.steps / el,
                          "ms_per_step": 1e3 * el / args.steps, "last_step": st}
         finals[form] = (state.U.cpu().numpy(), state.P.cpu().numpy())
+        ex = w.exact(g.fine_xy, (args.warmup + args.steps + 1) * w.dt)
+        if ex is not None:
+            Ue, Pe = ex
+            Pf = finals[form][1]
+            results[form]["err_vs_exact"] = {
+                "u": rel(finals[form][0], Ue),
+                "p": rel(Pf - Pf.mean(), Pe - Pe.mean())}
         if form == main_form:
             kernel = (kms, nl)
         log(f"[bench] {form}: {args.steps} steps in {el:.3f} s; last step {st}")

@@ -84,6 +84,10 @@ typedef struct cgp_mesh {
 
 /* The problem statement of Sect. 2.1 (dimensionless; nu = 1/Re) plus the
  * coarsening level k of Sect. 2.2 and the solver settings. */
+#define CGP_MASS_CONSISTENT 0
+#define CGP_MASS_LUMPED_P 1
+#define CGP_MASS_LUMPED 2
+
 typedef struct cgp_problem {
   cgp_mesh coarse;
   int32_t levels;        /* k in 0..3                                        */
@@ -97,11 +101,17 @@ typedef struct cgp_problem {
                             (each inner solve targets max(inner_tol,
                             0.3 pcg_tol ||b|| / ||r_outer||))                 */
   double mom_tol;        /* momentum BiCGSTAB relative tolerance             */
-  double mass_tol;       /* mass-matrix PCG relative tolerance               */
+  double mass_tol;       /* consistent mass solves: target of the Chebyshev
+                            iteration (sets its fixed step count)            */
   int32_t max_iter;      /* coarse PCG iteration cap (all inner iterations)  */
   int32_t mom_max_iter;  /* momentum iteration cap                           */
   int32_t mass_max_iter; /* mass-solve iteration cap                         */
   int32_t max_outer;     /* mixed: refinement-step cap                       */
+  int32_t mass_mode;     /* CGP_MASS_CONSISTENT (Eqs. 25, 26), CGP_MASS_LUMPED_P
+                            (rotational pressure update with the lumped mass
+                            matrix, Eq. 27) or CGP_MASS_LUMPED (Eq. 27 and the
+                            velocity correction with the lumped mass matrix;
+                            no mass solves)                                  */
 } cgp_problem;
 
 typedef struct cgp_sizes {

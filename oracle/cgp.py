@@ -83,12 +83,23 @@ def _rows_to_identity(A, rows):
     return (sp.diags(keep) @ A + sp.diags(put)).tocsr()
 
 
+MASS_MODES = ("consistent", "lumped_p", "lumped")
+
+
 class OracleCGP:
     def __init__(self, coarse_mesh, levels, dt, nu, chi, pcg_tol=1e-8,
-                 mom_tol=1e-12, mass_tol=1e-12, max_iter=20000, restrict="galerkin"):
+                 mom_tol=1e-12, mass_tol=1e-12, max_iter=20000, restrict="galerkin",
+                 mass="consistent"):
         if restrict not in ("galerkin", "inject"):
             raise ValueError("restrict must be 'galerkin' or 'inject'")
+        if mass not in MASS_MODES:
+            raise ValueError(f"mass must be one of {MASS_MODES}")
         self.restrict_mode = restrict
+        # 'consistent': Eqs. 25 and 26 with the consistent M (the paper's
+        # choice); 'lumped_p': the rotational pressure update with the lumped
+        # mass matrix, Eq. 27; 'lumped': Eq. 27 and the velocity correction of
+        # Eq. 25 with the lumped mass matrix as well
+        self.mass_mode = mass
         self.hier = Hierarchy(coarse_mesh, levels)
         self.dt, self.nu, self.chi = float(dt), float(nu), int(chi)
         self.pcg_tol, self.mom_tol, self.mass_tol = pcg_tol, mom_tol, mass_tol
@@ -171,20 +182,32 @@ class OracleCGP:
         return phi, info
 
     def velocity_correction(self, Ut, phi_f):
+        """Eq. 25: M dU = -(2/3) dt G phi_f on the non-Dirichlet rows (dU = 0
+        on the Dirichlet set); M consistent, or lumped (diagonal of row sums)
+        in mass mode 'lumped'."""
         rhs = -(2.0 / 3.0) * self.dt * self.F.grad(phi_f)
         U = Ut.copy()
         its = []
+        f = self.vel_free
         for d in range(2):
-            du, info = pcg_jacobi(self.M_ff, rhs[d][self.vel_free], tol=self.mass_tol,
-                                  maxit=self.max_iter)
-            U[d][self.vel_free] += du
+            if self.mass_mode == "lumped":
+                U[d][f] += rhs[d][f] / self.F.lumped[f]
+                its.append(0)
+                continue
+            du, info = pcg_jacobi(self.M_ff, rhs[d][f], tol=self.mass_tol, maxit=self.max_iter)
+            U[d][f] += du
             its.append(info.iters)
         return U, its
 
     def pressure_update(self, P, phi_f, Ut):
+        """chi = 0: P + phi_f (Eq. 16, algebraic form).  chi = 1: P + phi_f + dp
+        with M dp = -nu D U~ (Eq. 26 / 20, consistent M) or dp = M_L^-1 (-nu D U~)
+        with the lumped M_L (Eq. 27)."""
         if self.chi == 0:
             return P + phi_f, 0
         rhs = -self.nu * self.F.div(Ut)
+        if self.mass_mode in ("lumped_p", "lumped"):
+            return P + phi_f + rhs / self.F.lumped, 0
         dp, info = pcg_jacobi(self.F.M, rhs, tol=self.mass_tol, maxit=self.max_iter)
         return P + phi_f + dp, info.iters
 
@@ -217,7 +240,7 @@ class OracleCGP:
 def build(workload):
     return OracleCGP(workload.coarse_mesh(), workload.levels, workload.dt, workload.nu,
                      workload.chi, workload.pcg_tol, workload.mom_tol, workload.mass_tol,
-                     workload.max_iter, workload.restrict)
+                     workload.max_iter, workload.restrict, workload.mass)
 
 
 def run(workload, steps=None, record=None, F=None):

@@ -26,6 +26,7 @@ CGP_K_MOM_ASSEMBLE = 4
 CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
+CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -42,7 +43,8 @@ class Problem(C.Structure):
                 ("dt", C.c_double), ("nu", C.c_double), ("pcg_tol", C.c_double),
                 ("inner_tol", C.c_double), ("mom_tol", C.c_double), ("mass_tol", C.c_double),
                 ("max_iter", C.c_int32), ("mom_max_iter", C.c_int32),
-                ("mass_max_iter", C.c_int32), ("max_outer", C.c_int32)]
+                ("mass_max_iter", C.c_int32), ("max_outer", C.c_int32),
+                ("mass_mode", C.c_int32)]
 
 
 class Sizes(C.Structure):

@@ -431,20 +431,30 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
                 double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   const int chi = P.chi;
+  const int mode = P.mass_mode;
   // velocity: M dU = -(2/3) dt G phi_f on the non-Dirichlet nodes; rotational
-  // form: M dp = -nu D U~ on all nodes -- one fused Chebyshev solve
-  cgp::launch_correct_rhs(c->F, c->dir_index, P.dt, P.nu, chi, phi_f, ut, c->mrhs, s);
-  const double* du = cgp::launch_cheb(c->F, c->Mval, c->dir_index, c->mrhs, chi ? 3 : 2, c->mx,
+  // form: M dp = -nu D U~ on all nodes.  Consistent M: one fused Chebyshev
+  // solve; lumped M (Eq. 27 for p, and for U in mode LUMPED): a division by
+  // the row sum 2 M_ii, fused into the right-hand-side kernel
+  const bool cheb_u = mode != CGP_MASS_LUMPED;
+  const bool cheb_p = chi && mode == CGP_MASS_CONSISTENT;
+  const int nr = cheb_u ? (cheb_p ? 3 : 2) : 0;
+  cgp::launch_correct_rhs(c->F, c->dir_index, c->Mval, P.dt, P.nu, chi, mode, phi_f, ut, p_in,
+                          c->mrhs, u_out, p_out, s);
+  if (st) {
+    // a-priori bound of the Chebyshev iteration on [1/2, 2]; lumped: exact
+    const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
+    for (int d = 0; d < 3; ++d) {
+      const bool solved = d < 2 ? cheb_u : cheb_p;
+      st[d] = cgp_solve_stats{solved ? c->cheb_iters : 0, 0, 1, 0, solved ? bound : 0.0};
+    }
+  }
+  if (nr == 0) return CGP_OK;  // the kernel wrote U and P
+  const double* du = cgp::launch_cheb(c->F, c->Mval, c->dir_index, c->mrhs, nr, c->mx,
                                       c->cheb_iters, s,
                                       c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
-  if (st) {
-    // a-priori bound of the Chebyshev iteration on [1/2, 2]
-    const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
-    for (int d = 0; d < 3; ++d)
-      st[d] = cgp_solve_stats{(d < 2 || chi) ? c->cheb_iters : 0, 0, 1, 0,
-                              (d < 2 || chi) ? bound : 0.0};
-  }
-  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, chi, u_out, p_out, s);
+  // with the lumped pressure update the kernel above wrote P already
+  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, nr, cheb_p || !chi, u_out, p_out, s);
   return CGP_OK;
 }
 
@@ -471,6 +481,8 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
       !(prob->mass_tol > 0) || !(prob->inner_tol > 0) || prob->max_iter < 1 ||
       prob->mom_max_iter < 1 || prob->mass_max_iter < 1 || prob->max_outer < 1)
     return fail(CGP_ERR_INVALID, "dt, nu, tolerances and iteration caps must be positive");
+  if (prob->mass_mode < CGP_MASS_CONSISTENT || prob->mass_mode > CGP_MASS_LUMPED)
+    return fail(CGP_ERR_INVALID, "unknown mass_mode");
   cgp::Mesh cm;
   cm.n_nodes = m.n_nodes;
   cm.n_tris = m.n_tris;

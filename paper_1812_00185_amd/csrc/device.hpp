@@ -129,12 +129,17 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
 
 // ---------------------------------------------------------------- correction
 // rhs [n][2 + chi]: velocity right-hand sides, then (chi = 1) the rotational one
-void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
-                        int chi, const double* phi_f, const double* ut, double* rhs,
-                        hipStream_t s);
+// right-hand sides of the mass solves (interleaved [n][nr]) or, for the
+// lumped modes, the lumped updates written to u_out / p_out directly
+void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double* Mval,
+                        double dt, double nu, int chi, int mass_mode, const double* phi_f,
+                        const double* ut, const double* p_in, double* rhs, double* u_out,
+                        double* p_out, hipStream_t s);
+// U = U~ + dU from the solved increments du [n][nr]; P = P + phi (+ du[2]
+// when nr = 3) unless write_p is false
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
-                         const double* phi_f, int chi, double* u_out, double* p_out,
-                         hipStream_t s);
+                         const double* phi_f, int nr, bool write_p, double* u_out,
+                         double* p_out, hipStream_t s);
 
 // ---------------------------------------------------------------- small vector ops
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);

@@ -22,6 +22,7 @@
 // gathers the vector; this keeps many full cache lines in flight per CU.
 #include <cmath>
 
+#include "cgp.h"
 #include "device.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
@@ -1028,13 +1029,20 @@ k_prolong(int32_t nf, const int32_t* __restrict__ pcode, const int32_t* __restri
 
 
 // ------------------------------------------------------------------ correction
-// Mass-solve right-hand sides, interleaved per node ([n][2] or, for the
-// rotational form, [n][3]): -(2/3) dt G phi_f on non-Dirichlet rows (0 on
-// Dirichlet rows), then -nu D U~; one lane group per row.
+// Right-hand sides of Eqs. 25-26: -(2/3) dt G phi_f on non-Dirichlet rows (0
+// on Dirichlet rows) and -nu D U~; one lane group per row.
+// MODE CGP_MASS_CONSISTENT: the right-hand sides of the velocity correction
+// (2, Dirichlet rows 0) and, for chi = 1, of the rotational pressure update
+// (3rd), interleaved per node for the fused Chebyshev solve.
+// MODE CGP_MASS_LUMPED_P (chi = 1): the velocity right-hand sides as above,
+// and the pressure update of Eq. 27 written directly, p_out = p_in + phi +
+// (-nu D U~)_i / m_i with the lumped mass m_i = 2 M_ii (the P1 row sum).
+// MODE CGP_MASS_LUMPED: U and P written directly, dU = rhs / m_i.
 __global__ void __launch_bounds__(kBlock)
-k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double nu, int chi,
-              const double* __restrict__ phi, const double* __restrict__ ut,
-              double* __restrict__ rhs) {
+k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __restrict__ M,
+              double dt, double nu, int chi, int mode, const double* __restrict__ phi,
+              const double* __restrict__ ut, const double* __restrict__ p_in,
+              double* __restrict__ rhs, double* __restrict__ u_out, double* __restrict__ p_out) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
   for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
@@ -1065,28 +1073,44 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, double dt, double
     group_sum<3>(acc);
     if (lane == 0) {
       const bool dir = dir_index[i] >= 0;
-      const int nr = chi ? 3 : 2;
-      rhs[(int64_t)i * nr] = dir ? 0.0 : (dt / 9.0) * acc[0];
-      rhs[(int64_t)i * nr + 1] = dir ? 0.0 : (dt / 9.0) * acc[1];
-      if (chi) rhs[(int64_t)i * nr + 2] = -nu * acc[2];
+      const double rx = dir ? 0.0 : (dt / 9.0) * acc[0];
+      const double ry = dir ? 0.0 : (dt / 9.0) * acc[1];
+      const double rp = -nu * acc[2];
+      if (mode == CGP_MASS_CONSISTENT) {
+        const int nr = chi ? 3 : 2;
+        rhs[(int64_t)i * nr] = rx;
+        rhs[(int64_t)i * nr + 1] = ry;
+        if (chi) rhs[(int64_t)i * nr + 2] = rp;
+      } else {
+        const double ml = 2.0 * M[beg];  // lumped mass: row sum of M
+        if (mode == CGP_MASS_LUMPED_P) {
+          rhs[(int64_t)i * 2] = rx;
+          rhs[(int64_t)i * 2 + 1] = ry;
+        } else {
+          u_out[i] = ui + rx / ml;
+          u_out[n + i] = vi + ry / ml;
+        }
+        p_out[i] = chi ? p_in[i] + phii + rp / ml : p_in[i] + phii;
+      }
     }
   }
 }
 
-// u_out = U~ + dU, p_out = p_in + phi_f (+ dp); du holds (dU_x, dU_y[, dp])
-// interleaved per node
+// u_out = U~ + dU, p_out = p_in + phi_f (+ dp) unless write_p is 0; du holds
+// (dU_x, dU_y[, dp]) interleaved per node
 __global__ void __launch_bounds__(kBlock)
 k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restrict__ du,
-               const double* p_in, const double* __restrict__ phi, int chi,
+               const double* p_in, const double* __restrict__ phi, int nr, int write_p,
                double* __restrict__ u_out, double* p_out) {
   const int64_t n = n32;
-  const int nr = chi ? 3 : 2;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int64_t k = (int64_t)i * nr;
     u_out[i] = ut[i] + du[k];
     u_out[n + i] = ut[n + i] + du[k + 1];
-    const double pv = p_in[i] + phi[i];
-    p_out[i] = chi ? pv + du[k + 2] : pv;
+    if (write_p) {
+      const double pv = p_in[i] + phi[i];
+      p_out[i] = nr == 3 ? pv + du[k + 2] : pv;
+    }
   }
 }
 
@@ -1357,16 +1381,19 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
   k_prolong<<<grid_for(n_f, kBlock), kBlock, 0, s>>>(n_f, pcode, tri_c, levels, phic, phif);
 }
 
-void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, double dt, double nu,
-                        int chi, const double* phi_f, const double* ut, double* rhs,
-                        hipStream_t s) {
-  k_correct_rhs<<<row_group_grid(L.n), kBlock, 0, s>>>(L, dir_index, dt, nu, chi, phi_f, ut, rhs);
+void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double* Mval,
+                        double dt, double nu, int chi, int mass_mode, const double* phi_f,
+                        const double* ut, const double* p_in, double* rhs, double* u_out,
+                        double* p_out, hipStream_t s) {
+  k_correct_rhs<<<row_group_grid(L.n), kBlock, 0, s>>>(L, dir_index, Mval, dt, nu, chi, mass_mode,
+                                                       phi_f, ut, p_in, rhs, u_out, p_out);
 }
 
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
-                         const double* phi_f, int chi, double* u_out, double* p_out,
-                         hipStream_t s) {
-  k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, chi, u_out, p_out);
+                         const double* phi_f, int nr, bool write_p, double* u_out,
+                         double* p_out, hipStream_t s) {
+  k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, nr,
+                                                        write_p ? 1 : 0, u_out, p_out);
 }
 
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {

@@ -37,7 +37,7 @@ class CGP:
                  precision: str = "fp64", restrict: str = "galerkin", pcg_tol: float = 1e-8,
                  inner_tol: float = 1e-5, mom_tol: float = 1e-12, mass_tol: float = 1e-12,
                  max_iter: int = 20000, mom_max_iter: int = 1000, mass_max_iter: int = 1000,
-                 max_outer: int = 20, device="cuda:0"):
+                 max_outer: int = 20, mass: str = "consistent", device="cuda:0"):
         import torch
 
         self.lib = N.load()
@@ -54,9 +54,11 @@ class CGP:
                       btag.ctypes.data_as(C.POINTER(C.c_int32)))
         prec = {"fp64": N.CGP_FP64, "mixed": N.CGP_MIXED}[precision]
         rmode = {"galerkin": N.CGP_RESTRICT_GALERKIN, "inject": N.CGP_RESTRICT_INJECT}[restrict]
+        mmode = {"consistent": N.CGP_MASS_CONSISTENT, "lumped_p": N.CGP_MASS_LUMPED_P,
+                 "lumped": N.CGP_MASS_LUMPED}[mass]
         self.problem = N.Problem(mesh, levels, chi, prec, rmode, dt, nu, pcg_tol, inner_tol,
                                  mom_tol, mass_tol, max_iter, mom_max_iter, mass_max_iter,
-                                 max_outer)
+                                 max_outer, mmode)
         ctx = C.c_void_p()
         N.check(self.lib.cgp_create(C.byref(self.problem), C.byref(ctx)))
         self.ctx = ctx

@@ -38,7 +38,7 @@ def make(w, **kw):
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
             precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
             pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol,
-            max_iter=w.max_iter, **kw)
+            max_iter=w.max_iter, mass=w.mass, **kw)
     o = build_oracle(w)
     return g, o
 
@@ -258,6 +258,41 @@ def test_step_matches_composed_calls():
     torch.cuda.synchronize()
     assert torch.equal(s.U, U1) and torch.equal(s.P, P1)
     assert torch.equal(s.phi_hist[0], phi)
+
+
+# ----------------------------------------------------------------- lumped mass modes
+LUMPED_CASES = [
+    ("tg_k1_chi1_lumped_p", lambda: tg(9, 1, chi=1, mass="lumped_p")),
+    ("tg_k1_chi1_lumped", lambda: tg(9, 1, chi=1, mass="lumped")),
+    ("cavity_k2_chi0_lumped", lambda: cavity(9, 2, chi=0, mass="lumped")),
+    ("channel_k1_chi1_lumped", lambda: channel(1, 0.05, chi=1, mass="lumped")),
+]
+
+
+@pytest.mark.parametrize("name,wf", LUMPED_CASES, ids=[c[0] for c in LUMPED_CASES])
+def test_lumped_mass_correction(name, wf, monkeypatch):
+    """Eq. 27 (and the lumped velocity correction): the correction of a
+    perturbed state against the oracle to 1e-10, and a 20-step trajectory to
+    1e-10 or, where the trajectory is ill-conditioned, to 10x the oracle's
+    own rounding sensitivity."""
+    w = wf()
+    g, o = make(w)
+    Um, U0, P0 = start(w, o, g, seed=13)
+    rng = np.random.default_rng(4)
+    Ut = U0 + 0.01 * rng.standard_normal(U0.shape)
+    Ut[:, o.dir] = U0[:, o.dir]
+    phif = o.hier.prolong(rng.standard_normal(o.nc))
+    U_g, P_g, st = g.correct(g.to_device(Ut), g.to_device(phif), g.to_device(P0))
+    U_o, _ = o.velocity_correction(Ut, phif)
+    P_o, _ = o.pressure_update(P0, phif, Ut)
+    assert rel(np_(U_g), U_o) <= TOL64 and rel(np_(P_g), P_o) <= TOL64
+    del g
+    _, _, _, _, worst = run_both(w, 20)
+    sens = oracle_sensitivity(w, 20, monkeypatch)
+    bound = max(TOL64, 10 * sens)
+    print(f"[result] {name}: 20 steps GPU vs oracle {worst:.3e}, oracle self-sensitivity "
+          f"{sens:.3e}", flush=True)
+    assert worst <= bound, (worst, sens)
 
 
 # ----------------------------------------------------------------- mixed precision

@@ -168,3 +168,58 @@ def test_impulsive_start_converges():
     top = np.isclose(ora.fine_xy[:, 1], 1.0) & (ora.fine_xy[:, 0] > 0) & (ora.fine_xy[:, 0] < 1)
     np.testing.assert_array_equal(st.U[0][top], 1.0)
     assert np.abs(st.U).max() <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("mass", ["consistent", "lumped_p", "lumped"])
+def test_rotational_pressure_correction_of_linear_velocity(mass):
+    """A linear U~ with divergence c: D U~ = c * lumped, so the rotational
+    correction -nu M^-1 D U~ is -nu c at every node with the consistent M
+    (M 1 = lumped, Eq. 20) and with the lumped M (Eq. 27) alike."""
+    w = get_workload("tg33_k1").with_(coarse_n=9, levels=1, chi=1, mass=mass)
+    ora = build(w)
+    x, y = ora.fine_xy[:, 0], ora.fine_xy[:, 1]
+    Ut = np.stack([0.3 + 1.7 * x - 0.4 * y, -0.2 + 0.9 * x + 0.6 * y])   # div = 2.3
+    P = np.zeros(ora.nf)
+    phi = np.zeros(ora.nf)
+    Pn, _ = ora.pressure_update(P, phi, Ut)
+    np.testing.assert_allclose(Pn, -ora.nu * 2.3, rtol=1e-11)
+
+
+def test_lumped_velocity_correction_of_linear_increment():
+    """phi_f = a x + b y: at an interior node (G phi)_i = grad(phi) * lumped_i,
+    so the lumped velocity correction is exactly -(2/3) dt grad(phi) there;
+    Dirichlet nodes are untouched."""
+    w = get_workload("tg33_k1").with_(coarse_n=9, levels=1, mass="lumped")
+    ora = build(w)
+    x, y = ora.fine_xy[:, 0], ora.fine_xy[:, 1]
+    a, b = 0.8, -1.9
+    phi = a * x + b * y
+    Ut = np.random.default_rng(0).standard_normal((2, ora.nf))
+    U, its = ora.velocity_correction(Ut, phi)
+    f = ora.vel_free
+    np.testing.assert_allclose(U[0][f] - Ut[0][f], -(2.0 / 3.0) * ora.dt * a, rtol=1e-12)
+    np.testing.assert_allclose(U[1][f] - Ut[1][f], -(2.0 / 3.0) * ora.dt * b, rtol=1e-12)
+    np.testing.assert_array_equal(U[:, ora.dir], Ut[:, ora.dir])
+    # the consistent correction differs near the boundary (M_ff 1 != lumped)
+    ora_c = build(w.with_(mass="consistent"))
+    Uc, _ = ora_c.velocity_correction(Ut, phi)
+    assert np.abs(Uc - U).max() > 1e-3 * ora.dt
+
+
+def test_lumped_modes_stay_accurate_on_taylor_green():
+    """Taylor-Green 33^2 / 17^2, 40 steps: the lumped variants stay within a
+    small factor of the consistent form's velocity error (the paper notes the
+    consistent pressure mass matrix is the more accurate choice)."""
+    errs = {}
+    for mass in ("consistent", "lumped_p", "lumped"):
+        w = get_workload("tg33_k1").with_(chi=1, mass=mass, steps=40)
+        ora = build(w)
+        Um, U0, P0 = w.initial_fields(ora.fine_xy)
+        st = ora.initial_state(Um, U0, P0)
+        xyd = ora.fine_xy[ora.dir]
+        for n in range(w.steps):
+            st = ora.step(st, w.dirichlet_values(xyd, (n + 1) * w.dt)).state
+        Ue, _ = w.exact(ora.fine_xy, w.steps * w.dt)
+        errs[mass] = ora.l2(st.U - Ue) / ora.l2(Ue)
+    assert errs["lumped_p"] <= 1.5 * errs["consistent"]
+    assert errs["lumped"] <= 3.0 * errs["consistent"]

@@ -36,6 +36,7 @@ class Workload:
     mass_tol: float = 1e-12
     max_iter: int = 20000
     restrict: str = "galerkin"     # 'galerkin' | 'inject'
+    mass: str = "consistent"       # 'consistent' | 'lumped_p' (Eq. 27) | 'lumped'
     lid_speed: float = 1.0
     channel_h: float = 0.0082
     seed: int = 0
