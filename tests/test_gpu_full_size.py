@@ -1,0 +1,78 @@
+"""Parity at the full sizes of the benchmark workloads, in the configuration
+the bench times (FP64 bar 1e-10 per field; mixed bar: the FP64 true residual
+of every coarse solve <= tol and the fields within 1e-6 of the oracle).
+
+* lid-driven cavity 257 x 257, k = 1, rotational, 3 steps from rest;
+* channel minus cylinder (h = 0.0082 seeded Delaunay, about 31k coarse
+  triangles refined twice), rotational, mixed precision, 2 steps;
+* Taylor-Green 2049 x 2049, k = 3, rotational, one step from the exact
+  fields (4.2 M fine nodes; the oracle needs about 10 s for it).
+"""
+import numpy as np
+import pytest
+
+from oracle.cgp import build as build_oracle
+from workloads import get_workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1812_00185_amd import CGP  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def solver(w):
+    return CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
+               precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
+               pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol,
+               mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass)
+
+
+def run(w, steps):
+    print(f"\n[case] {w.name} full size, {steps} steps", flush=True)
+    g = solver(w)
+    o = build_oracle(w)
+    print(f"[case] N_f={g.nf} N_c={g.nc}", flush=True)
+    assert np.array_equal(g.fine_xy, o.fine_xy)
+    Um, U0, P0 = w.initial_fields(o.fine_xy)
+    so, sg = o.initial_state(Um, U0, P0), g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    out = []
+    for n in range(steps):
+        uD = w.dirichlet_values(xyd, (n + 1) * w.dt)
+        so = o.step(so, uD).state
+        st = g.step(sg, g.to_device(uD), stats=True)
+        torch.cuda.synchronize()
+        du = rel(sg.U.cpu().numpy(), so.U)
+        dp = rel(sg.P.cpu().numpy(), so.P)
+        print(f"[result] step {n + 1}: u {du:.3e} p {dp:.3e} poisson {st['poisson']}", flush=True)
+        out.append((du, dp, st))
+    return out
+
+
+def test_cavity_257_k1_rotational():
+    w = get_workload("cavity257_k1_chi1_fp64")
+    for du, dp, st in run(w, 3):
+        assert st["poisson"]["converged"]
+        assert du <= 1e-10 and dp <= 1e-10
+
+
+def test_channel_full_mesh_mixed():
+    w = get_workload("channel_k2")
+    assert w.precision == 1
+    for du, dp, st in run(w, 2):
+        assert st["poisson"]["converged"] and st["poisson"]["rel_res"] <= w.pcg_tol
+        assert du <= 1e-6 and dp <= 1e-6
+
+
+def test_taylor_green_2049_k3_one_step():
+    w = get_workload("tg2049_k3_fp64")
+    ((du, dp, st),) = run(w, 1)
+    assert st["poisson"]["converged"]
+    assert du <= 1e-10 and dp <= 1e-10
