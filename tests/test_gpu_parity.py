@@ -211,7 +211,8 @@ def oracle_sensitivity(w, steps, monkeypatch):
         o = build_oracle(w)
         st = o.initial_state(*w.initial_fields(o.fine_xy))
         for n in range(steps):
-            st = o.step(st, w.dirichlet_values(o.fine_xy[o.dir], (n + 1) * w.dt)).state
+            t = (n + 1) * w.dt
+            st = o.step(st, w.dirichlet_values(o.fine_xy[o.dir], t), w.forcing(o.fine_xy, t)).state
             yield st.U.copy(), st.P.copy()
 
     clean = list(traj())
@@ -258,6 +259,38 @@ def test_step_matches_composed_calls():
     torch.cuda.synchronize()
     assert torch.equal(s.U, U1) and torch.equal(s.P, P1)
     assert torch.equal(s.phi_hist[0], phi)
+
+
+# ----------------------------------------------------------------- forcing
+@pytest.mark.parametrize("chi", [0, 1])
+def test_jobelin_disc_with_forcing(chi, monkeypatch):
+    """The paper's Jobelin vortex in the circle on the Fig. 1 mesh (1201
+    coarse nodes, k = 2, 36,864 fine triangles) with its body force passed
+    every step: the first step against the oracle at 1e-10, then 20 steps
+    at 1e-10 or 10x the oracle's own rounding sensitivity."""
+    w = get_workload(f"jobelin_disc_chi{chi}")
+    g, o = make(w)
+    Um, U0, P0 = w.initial_fields(o.fine_xy)
+    so, sg = o.initial_state(Um, U0, P0), g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    worst = 0.0
+    for n in range(20):
+        t = (n + 1) * w.dt
+        uD, F = w.dirichlet_values(xyd, t), w.forcing(o.fine_xy, t)
+        so = o.step(so, uD, F).state
+        st = g.step(sg, g.to_device(uD), f=g.to_device(F), stats=True)
+        assert st["poisson"]["converged"]
+        du, dp = rel(np_(sg.U), so.U), rel(np_(sg.P), so.P)
+        if n == 0:
+            print(f"[result] jobelin chi={chi} step 1: u {du:.3e} p {dp:.3e}", flush=True)
+            assert du <= TOL64 and dp <= TOL64
+        worst = max(worst, du, dp)
+    Ue, _ = w.exact(o.fine_xy, 20 * w.dt)
+    sens = oracle_sensitivity(w, 20, monkeypatch)
+    print(f"[result] jobelin chi={chi}: GPU vs oracle {worst:.3e} (last u {du:.3e} p {dp:.3e}), "
+          f"oracle self-sensitivity {sens:.3e}, velocity error vs exact "
+          f"{rel(np_(sg.U), Ue):.3e}", flush=True)
+    assert worst <= max(TOL64, 10 * sens)
 
 
 # ----------------------------------------------------------------- lumped mass modes

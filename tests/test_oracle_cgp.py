@@ -223,3 +223,35 @@ def test_lumped_modes_stay_accurate_on_taylor_green():
         errs[mass] = ora.l2(st.U - Ue) / ora.l2(Ue)
     assert errs["lumped_p"] <= 1.5 * errs["consistent"]
     assert errs["lumped"] <= 3.0 * errs["consistent"]
+
+
+@pytest.mark.parametrize("chi", [0, 1])
+def test_jobelin_disc_velocity_error_independent_of_coarsening(chi):
+    """The paper's Jobelin vortex in the circle (forcing balancing the exact
+    solution, Dirichlet velocity): with the fine mesh fixed, coarsening the
+    pressure mesh by k = 0, 1, 2 levels keeps the velocity error (Sect. 3,
+    circle case); the pressure error stays of the same order.  Small seeded
+    disc (240 coarse nodes), 20 steps of dt = 0.01."""
+    from oracle.hierarchy import Hierarchy
+    from workloads import disc
+
+    w = get_workload(f"jobelin_disc_chi{chi}")
+    base = disc(40, 200, 0.5, 0)
+    eu, ep = {}, {}
+    for k in (0, 1, 2):
+        coarse = Hierarchy(base, 2 - k).fine if k < 2 else base
+        o = OracleCGP(coarse, k, w.dt, w.nu, chi, pcg_tol=1e-10)
+        Um, U0, P0 = w.initial_fields(o.fine_xy)
+        st = o.initial_state(Um, U0, P0)
+        xyd = o.fine_xy[o.dir]
+        for n in range(20):
+            t = (n + 1) * w.dt
+            st = o.step(st, w.dirichlet_values(xyd, t), w.forcing(o.fine_xy, t)).state
+        Ue, Pe = w.exact(o.fine_xy, 20 * w.dt)
+        m = o.F.lumped
+        mean_free = lambda q: q - (m @ q) / m.sum()  # noqa: E731
+        eu[k] = o.l2(st.U - Ue) / o.l2(Ue)
+        ep[k] = o.l2(mean_free(st.P) - mean_free(Pe)) / o.l2(mean_free(Pe))
+    assert eu[0] < 1e-4
+    assert max(eu.values()) <= 1.05 * eu[0]
+    assert max(ep.values()) <= 1.5 * ep[0]

@@ -72,3 +72,32 @@ def test_boundary_data():
     # mean inflow 2/3 U_m (Simpson's rule is exact for the parabola)
     mean = (yy[1] - yy[0]) / 3 * (u[0] + u[-1] + 4 * u[1:-1:2].sum() + 2 * u[2:-1:2].sum())
     assert mean / CHANNEL_H == pytest.approx(0.2, rel=1e-12)
+
+
+def test_jobelin_disc_forcing_balances_navier_stokes():
+    """The hand-derived forcing of the Jobelin vortex: u_t + (u . grad) u +
+    grad p - nu lap u - f = 0 and div u = 0 by central differences."""
+    w = get_workload("jobelin_disc_chi0")
+    nu, t, h = w.nu, 0.43, 1e-4
+    ang = np.random.default_rng(3).uniform(0, 2 * np.pi, 40)
+    rad = 0.45 * np.sqrt(np.random.default_rng(4).uniform(0, 1, 40))
+    pts = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+
+    def F(xy, tt):
+        (u, v), p = w.exact(xy, tt)
+        return u, v, p
+
+    ex, ey = np.array([h, 0.0]), np.array([0.0, h])
+    c = F(pts, t)
+    px, mx, py, my = F(pts + ex, t), F(pts - ex, t), F(pts + ey, t), F(pts - ey, t)
+    tp, tm = F(pts, t + h), F(pts, t - h)
+    d = lambda a, b: [(ai - bi) / (2 * h) for ai, bi in zip(a, b)]  # noqa: E731
+    ux, vx, pxx = d(px, mx)
+    uy, vy, pyy = d(py, my)
+    ut, vt, _ = d(tp, tm)
+    lap = [(px[i] + mx[i] + py[i] + my[i] - 4 * c[i]) / h ** 2 for i in range(2)]
+    fx, fy = w.forcing(pts, t)
+    u, v = c[0], c[1]
+    np.testing.assert_allclose(ux + vy, 0.0, atol=1e-7)
+    np.testing.assert_allclose(ut + u * ux + v * uy + pxx - nu * lap[0] - fx, 0.0, atol=1e-5)
+    np.testing.assert_allclose(vt + u * vx + v * vy + pyy - nu * lap[1] - fy, 0.0, atol=1e-5)

@@ -46,3 +46,28 @@ def channel_inflow(x, y, u_max=0.3):
     inflow = x == 0.0
     u = np.where(inflow, 4.0 * u_max * y * (H - y) / (H * H), 0.0)
     return u, np.zeros_like(x)
+
+
+def jobelin_disc(x, y, t):
+    """The Jobelin vortex of the paper's circle test (Sect. 3, Dirichlet
+    boundary conditions on x^2 + y^2 < 1/4):
+      u = sin(x + t) sin(y + t),  v = cos(x + t) cos(y + t),  p = cos(x - y + t),
+    divergence free."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    a, b = x + t, y + t
+    return np.sin(a) * np.sin(b), np.cos(a) * np.cos(b), np.cos(x - y + t)
+
+
+def jobelin_disc_forcing(x, y, t, nu):
+    """f = u_t + (u . grad) u + grad p - nu lap u for jobelin_disc (derived by
+    hand: u_t = sin(a + b), v_t = -sin(a + b), (u . grad) u = sin a cos a,
+    (u . grad) v = -sin b cos b, lap u = -2 u, lap v = -2 v with a = x + t,
+    b = y + t)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    a, b = x + t, y + t
+    s = np.sin(x - y + t)
+    fx = np.sin(a + b) + np.sin(a) * np.cos(a) - s + 2.0 * nu * np.sin(a) * np.sin(b)
+    fy = -np.sin(a + b) - np.sin(b) * np.cos(b) + s + 2.0 * nu * np.cos(a) * np.cos(b)
+    return fx, fy
