@@ -12,6 +12,9 @@ run over the same trajectory:
   learned_fp64   guarded learned guess + FP64 PCG
   lumped_p_fp64  plain FP64 with the lumped-mass pressure update (Eq. 27)
   lumped_fp64    plain FP64 with lumped mass in Eqs. 25 and 27 (no mass solves)
+  ndchol_fp64    FP64 PCG preconditioned by the nested-dissection Cholesky
+                 factor of K_c (one iteration to rounding level)
+  ndchol_lumped_fp64  ndchol_fp64 with lumped mass in Eqs. 25 and 27
 and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
@@ -165,7 +168,8 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
-                    default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64")
+                    default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
+                            "ndchol_fp64,ndchol_lumped_fp64")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain FP64 form only: no training, no learned forms or legs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -207,10 +211,13 @@ def main():
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64", **kw)
     gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="mixed", **kw)
     solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
-    for form, mass in (("lumped_p_fp64", "lumped_p"), ("lumped_fp64", "lumped")):
+    for form, mass, pre in (("lumped_p_fp64", "lumped_p", "jacobi"),
+                            ("lumped_fp64", "lumped", "jacobi"),
+                            ("ndchol_fp64", "consistent", "ndchol"),
+                            ("ndchol_lumped_fp64", "lumped", "ndchol")):
         if form in forms:
             solvers[form] = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64",
-                                mass=mass, **kw)
+                                mass=mass, precond=pre, **kw)
     torch.cuda.synchronize()
     log(f"[bench] {w.name}: N_f={g.nf} N_c={g.nc} nnz_f={g.sizes.nnz_fine} "
         f"set-up {time.perf_counter() - t0:.1f} s")
@@ -232,7 +239,8 @@ def main():
         log(f"[bench] trained on {n_samples} pairs in {t_train:.1f} s (collect "
             f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
-              "lumped_p_fp64": None, "lumped_fp64": None}
+              "lumped_p_fp64": None, "lumped_fp64": None, "ndchol_fp64": None,
+              "ndchol_lumped_fp64": None}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]

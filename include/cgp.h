@@ -65,6 +65,11 @@ extern "C" {
 #define CGP_FP64 0  /* Jacobi-PCG in FP64 throughout */
 #define CGP_MIXED 1 /* FP64 iterative refinement around FP32-inner Jacobi-PCG */
 
+/* coarse-solve preconditioner (the paper preconditions its Krylov solves
+ * with ILU(0), Sect. 2.3; the choice of coarse solver is open) */
+#define CGP_PRECOND_JACOBI 0 /* diagonal: single-reduction PCG, FP64 or mixed   */
+#define CGP_PRECOND_NDCHOL 1 /* nested-dissection Cholesky factor of K_c (FP64) */
+
 /* reading of the coarse divergence in Eq. 23 (Sect. 2.2) */
 #define CGP_RESTRICT_GALERKIN 0 /* coarse shape functions against the fine velocity */
 #define CGP_RESTRICT_INJECT 1   /* inject U~ at the coarse nodes (Eq. 22), then D_c */
@@ -112,6 +117,12 @@ typedef struct cgp_problem {
                             matrix, Eq. 27) or CGP_MASS_LUMPED (Eq. 27 and the
                             velocity correction with the lumped mass matrix;
                             no mass solves)                                  */
+  int32_t coarse_precond; /* CGP_PRECOND_JACOBI, or CGP_PRECOND_NDCHOL: PCG in
+                            FP64 preconditioned by the exact Cholesky factor
+                            of K_c (phi = 0 nodes removed; without natural
+                            nodes the last coarse node N_c - 1 is pinned, as
+                            K_c is singular), computed once on the host in
+                            cgp_assemble; requires precision = CGP_FP64      */
 } cgp_problem;
 
 typedef struct cgp_sizes {
@@ -207,7 +218,9 @@ int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream)
  * phi = 0 rows/columns removed) from the guess held in phi_c, stopping when
  * ||b - K phi|| <= pcg_tol ||b||; CGP_FP64 runs Jacobi-PCG in FP64,
  * CGP_MIXED runs FP64 refinement steps around FP32 Jacobi-PCG (FP64 dot
- * products and norms).  For the pure Neumann problem the lumped-mass mean of
+ * products and norms); CGP_PRECOND_NDCHOL runs FP64 PCG whose
+ * preconditioner is the factor (one iteration reaches rounding level; the
+ * FP64 residual is tested before the first and after every iteration).  For the pure Neumann problem the lumped-mass mean of
  * the result is removed.  b_c, phi_c device [N_c].  stats may be NULL (then
  * no synchronisation beyond the convergence polling). */
 int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stats* stats,
@@ -317,6 +330,35 @@ int cgp_intermediates(cgp_ctx* ctx, const double** u_tilde, const double** b_c,
 #define CGP_K_MOM_ASSEMBLE 4
 int cgp_timing_enable(cgp_ctx* ctx, int kernel_id);
 int cgp_timing_read(cgp_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* ---- Nested-dissection factor of the coarse matrix ---------------------
+ * Structure of the factor used by CGP_PRECOND_NDCHOL: unknowns factored,
+ * supernodes (leaves of at most 32 nodes and separators), tree levels (one
+ * forward and one backward launch each), the widest front, and the stored
+ * factor entries (G = [L11^-1 ; L21 L11^-1] per supernode; the workspace
+ * holds it twice, as G and G^T). */
+typedef struct cgp_ndchol_info {
+  int32_t n_factored;
+  int32_t n_supernodes;
+  int32_t height;
+  int32_t max_front;
+  int64_t g_entries;
+} cgp_ndchol_info;
+
+/* Factor structure of a context created with CGP_PRECOND_NDCHOL (zeros
+ * otherwise). */
+int cgp_query_ndchol(const cgp_ctx* ctx, cgp_ndchol_info* out);
+
+/* Host-only: orders, factors and applies the nested-dissection factor of a
+ * symmetric positive definite CSR matrix restricted to the rows/columns with
+ * skip[i] == 0: z = K^-1 r there, z = 0 at skipped rows, by the level
+ * algorithm of the device solves.  rowptr [n+1], col, val [rowptr[n]]
+ * (columns in range, both triangles present), xy [2n] node coordinates
+ * (the ordering), skip [n], r and z [n]; all host.  info may be NULL.
+ * Errors: CGP_ERR_INVALID (arguments, or a non-positive pivot). */
+int cgp_ndchol_solve_host(int32_t n, const int32_t* rowptr, const int32_t* col,
+                          const double* val, const double* xy, const uint8_t* skip,
+                          const double* r, double* z, cgp_ndchol_info* info);
 
 /* Releases host memory and the pinned buffer; the workspace stays the
  * caller's.  Safe on NULL. */

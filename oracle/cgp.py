@@ -35,6 +35,8 @@ Readings where the paper is silent:
     the Dirichlet values of Eq. 10 imposed (so the Dirichlet rows' residual is
     zero throughout and the shadow residual lives on the free rows), the
     Poisson solve from the previous step's Phi_c (zero at the first step);
+    with coarse='exact' the coarse system is solved directly instead (the
+    limit of a PCG whose preconditioner is an exact factorisation of K_c);
   * when no boundary is natural the coarse Poisson problem is pure Neumann:
     the right-hand side is projected onto mean zero (Euclidean mean) before the
     solve, and the lumped-mass-weighted mean of Phi_c is removed after it;
@@ -48,10 +50,11 @@ from dataclasses import dataclass, field
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .fem import Operators
 from .hierarchy import Hierarchy, dirichlet_nodes, natural_nodes
-from .krylov import bicgstab_jacobi, pcg_jacobi
+from .krylov import SolveInfo, bicgstab_jacobi, pcg_jacobi
 
 
 @dataclass
@@ -89,9 +92,15 @@ MASS_MODES = ("consistent", "lumped_p", "lumped")
 class OracleCGP:
     def __init__(self, coarse_mesh, levels, dt, nu, chi, pcg_tol=1e-8,
                  mom_tol=1e-12, mass_tol=1e-12, max_iter=20000, restrict="galerkin",
-                 mass="consistent"):
+                 mass="consistent", coarse="pcg"):
         if restrict not in ("galerkin", "inject"):
             raise ValueError("restrict must be 'galerkin' or 'inject'")
+        if coarse not in ("pcg", "exact"):
+            raise ValueError("coarse must be 'pcg' or 'exact'")
+        # 'pcg': Jacobi-PCG to pcg_tol from the guess; 'exact': the exact
+        # solution of the coarse system (what PCG preconditioned by an exact
+        # factorisation of K_c returns, to rounding)
+        self.coarse_solver = coarse
         if mass not in MASS_MODES:
             raise ValueError(f"mass must be one of {MASS_MODES}")
         self.restrict_mode = restrict
@@ -171,15 +180,37 @@ class OracleCGP:
             b = b - b.mean()
         return b
 
-    def poisson(self, b, guess):
+    def poisson(self, b, guess, pin=None):
         phi = np.zeros(self.nc)
-        x, info = pcg_jacobi(self.Kc_ff, b[self.phi_free], x0=guess[self.phi_free],
-                             tol=self.pcg_tol, maxit=self.max_iter)
+        if self.coarse_solver == "exact":
+            x, info = self.exact_coarse(b[self.phi_free], pin)
+        else:
+            x, info = pcg_jacobi(self.Kc_ff, b[self.phi_free], x0=guess[self.phi_free],
+                                 tol=self.pcg_tol, maxit=self.max_iter)
         phi[self.phi_free] = x
         if self.pure_neumann:
             m = self.C.lumped
             phi = phi - (m @ phi) / m.sum()
         return phi, info
+
+    def exact_coarse(self, b, pin=None):
+        """Direct solve of K_c x = b on the phi-free unknowns.  K_c is
+        singular in the pure Neumann case (constants are its null space and b
+        has zero sum): one unknown (`pin`, default the last) is then fixed to
+        0, which selects one solution; the mean removal in poisson() makes the
+        result independent of that choice."""
+        K = self.Kc_ff
+        n = K.shape[0]
+        x = np.zeros(n)
+        if self.pure_neumann:
+            pin = n - 1 if pin is None else pin
+            keep = np.setdiff1d(np.arange(n), [pin])
+            x[keep] = spla.spsolve(K[keep][:, keep].tocsc(), b[keep])
+        else:
+            x = spla.spsolve(K.tocsc(), b)
+        nb = np.linalg.norm(b)
+        res = np.linalg.norm(b - K @ x) / nb if nb > 0 else 0.0
+        return x, SolveInfo(1, True, res)
 
     def velocity_correction(self, Ut, phi_f):
         """Eq. 25: M dU = -(2/3) dt G phi_f on the non-Dirichlet rows (dU = 0
@@ -240,7 +271,8 @@ class OracleCGP:
 def build(workload):
     return OracleCGP(workload.coarse_mesh(), workload.levels, workload.dt, workload.nu,
                      workload.chi, workload.pcg_tol, workload.mom_tol, workload.mass_tol,
-                     workload.max_iter, workload.restrict, workload.mass)
+                     workload.max_iter, workload.restrict, workload.mass,
+                     "exact" if workload.precond == "ndchol" else "pcg")
 
 
 def run(workload, steps=None, record=None, F=None):

@@ -27,6 +27,7 @@ CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
 CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED = 0, 1, 2
+CGP_PRECOND_JACOBI, CGP_PRECOND_NDCHOL = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -44,7 +45,16 @@ class Problem(C.Structure):
                 ("inner_tol", C.c_double), ("mom_tol", C.c_double), ("mass_tol", C.c_double),
                 ("max_iter", C.c_int32), ("mom_max_iter", C.c_int32),
                 ("mass_max_iter", C.c_int32), ("max_outer", C.c_int32),
-                ("mass_mode", C.c_int32)]
+                ("mass_mode", C.c_int32), ("coarse_precond", C.c_int32)]
+
+
+class NdcholInfo(C.Structure):
+    _fields_ = [("n_factored", C.c_int32), ("n_supernodes", C.c_int32), ("height", C.c_int32),
+                ("max_front", C.c_int32), ("g_entries", C.c_int64)]
+
+    def as_dict(self):
+        return dict(n_factored=self.n_factored, n_supernodes=self.n_supernodes,
+                    height=self.height, max_front=self.max_front, g_entries=self.g_entries)
 
 
 class Sizes(C.Structure):
@@ -111,6 +121,9 @@ SIGNATURES = [
                                   C.c_void_p, C.c_void_p]),
     ("cgp_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("cgp_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("cgp_query_ndchol", C.c_int, [C.c_void_p, C.POINTER(NdcholInfo)]),
+    ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,
+                                        C.POINTER(C.c_uint8), _dp, _dp, C.POINTER(NdcholInfo)]),
     ("cgp_destroy", None, [C.c_void_p]),
     ("cgp_last_error", C.c_char_p, []),
 ]
@@ -146,3 +159,24 @@ def check(code: int, allow_not_converged: bool = True) -> int:
     if code == CGP_OK or (code == CGP_NOT_CONVERGED and allow_not_converged):
         return code
     raise CGPError(code, load().cgp_last_error().decode())
+
+
+def ndchol_solve_host(rowptr, col, val, xy, skip, r):
+    """z = K^-1 r on the rows with skip == 0 (0 elsewhere) through the
+    library's host factor routine; returns (z, info dict)."""
+    import numpy as np
+
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    xy = np.ascontiguousarray(xy, np.float64)
+    skip = np.ascontiguousarray(skip, np.uint8)
+    r = np.ascontiguousarray(r, np.float64)
+    n = rowptr.size - 1
+    z = np.empty(n)
+    info = NdcholInfo()
+    check(load().cgp_ndchol_solve_host(
+        n, rowptr.ctypes.data_as(_ip), col.ctypes.data_as(_ip), val.ctypes.data_as(_dp),
+        xy.ctypes.data_as(_dp), skip.ctypes.data_as(C.POINTER(C.c_uint8)),
+        r.ctypes.data_as(_dp), z.ctypes.data_as(_dp), C.byref(info)), allow_not_converged=False)
+    return z, info.as_dict()

@@ -17,6 +17,7 @@
 #include "device.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
+#include "ndchol.hpp"
 
 using cgp::DLevel;
 using cgp::Scal;
@@ -103,6 +104,14 @@ struct cgp_ctx {
   double* guess_tmp = nullptr;  // [N_c]
   double hbar = 1.0;
 
+  // nested-dissection factor preconditioner (CGP_PRECOND_NDCHOL): host
+  // structure, device view, and the PCG vectors z, p (alternating) and q
+  cgp::NdFactor nd;
+  cgp::NdDev ndd{};
+  double* nd_z = nullptr;
+  double* nd_p[2] = {nullptr, nullptr};
+  double* nd_q = nullptr;
+
   // measurement hook (cgp_timing_enable)
   int timed_id = 0;
   std::vector<hipEvent_t> tev;
@@ -176,6 +185,27 @@ size_t carve(cgp_ctx* c, void* base) {
   c->net_loss = w.take<float>(4);
   c->chose = w.take<int32_t>(4);
   c->guess_tmp = w.take<double>(nc);
+  if (c->prob.coarse_precond == CGP_PRECOND_NDCHOL) {
+    const cgp::NdFactor& f = c->nd;
+    cgp::NdDev& d = c->ndd;
+    d.nfac = f.nfac;
+    d.perm = w.take<int32_t>(f.perm.size());
+    d.sn = w.take<cgp::NdSuper>(f.sn.size());
+    d.rows = w.take<int32_t>(f.rows.size());
+    d.gptr = w.take<int32_t>(f.gptr.size());
+    d.gidx = w.take<int32_t>(f.gidx.size());
+    d.fwd = w.take<cgp::NdItem>(f.fwd.size());
+    d.bwd = w.take<cgp::NdItem>(f.bwd.size());
+    d.G = w.take<double>((size_t)f.g_entries);
+    d.GT = w.take<double>((size_t)f.g_entries);
+    d.Y = w.take<double>(f.nfac);
+    d.X = w.take<double>(f.nfac);
+    d.U = w.take<double>(f.n_upd);
+    c->nd_z = w.take<double>(nc);
+    c->nd_p[0] = w.take<double>(nc);
+    c->nd_p[1] = w.take<double>(nc);
+    c->nd_q = w.take<double>(nc);
+  }
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
   c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
@@ -311,11 +341,54 @@ int run_restrict(cgp_ctx* c, const double* ut, double* b, hipStream_t s) {
   return CGP_OK;
 }
 
+// PCG preconditioned by the nested-dissection factor: the FP64 residual is
+// tested before the first iteration and after each one (host polls; with the
+// exact factor one iteration reaches rounding level).
+int run_pcg_nd(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
+  double* const pbuf[2] = {c->nd_p[0], c->nd_p[1]};
+  int it = 0, rc = CGP_OK;
+  Scal chk{};
+  for (;;) {
+    cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, it, s);
+    cgp::launch_mirror(c->scal + 4, c->pinned, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    chk = c->pinned[0];
+    if (chk.status == 2) {
+      rc = fail(CGP_ERR_NAN, "coarse PCG produced NaN/Inf");
+      break;
+    }
+    if (chk.bb == 0.0) {  // zero right-hand side: the solution is zero
+      cgp::launch_fill(x, 0.0, c->nc, s);
+      break;
+    }
+    if (chk.done_stamp) break;
+    if (it >= P.max_iter) {
+      rc = fail(CGP_NOT_CONVERGED, "iteration limit reached");
+      break;
+    }
+    ++it;
+    cgp::launch_nd_solve(c->ndd, c->nd, c->cr, c->nd_z, s);
+    cgp::launch_fpcg_iter(c->nc, c->ell_col, c->ell_val, c->ell_w, c->nd_z, pbuf, c->nd_q, x,
+                          c->cr, c->scal + 5, c->part, c->nb_c, it, s);
+  }
+  if (st) {
+    st->iters = it;
+    st->outer_iters = 0;
+    st->converged = rc == CGP_OK;
+    st->rel_res = chk.rel;
+  }
+  return rc;
+}
+
 int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   int rc = CGP_OK;
   if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
-  if (P.precision == CGP_FP64) {
+  if (P.coarse_precond == CGP_PRECOND_NDCHOL) {
+    rc = run_pcg_nd(c, b, x, st, s);
+  } else if (P.precision == CGP_FP64) {
     cgp::PcgVecs<double> V{x,          c->cp,       {c->cr2[0], c->cr2[1]},
                            {c->cw2[0], c->cw2[1]}, {c->cs2[0], c->cs2[1]},
                            b,          c->invdKc,   c->Kc,
@@ -487,6 +560,10 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     return fail(CGP_ERR_INVALID, "dt, nu, tolerances and iteration caps must be positive");
   if (prob->mass_mode < CGP_MASS_CONSISTENT || prob->mass_mode > CGP_MASS_LUMPED)
     return fail(CGP_ERR_INVALID, "unknown mass_mode");
+  if (prob->coarse_precond != CGP_PRECOND_JACOBI && prob->coarse_precond != CGP_PRECOND_NDCHOL)
+    return fail(CGP_ERR_INVALID, "unknown coarse_precond");
+  if (prob->coarse_precond == CGP_PRECOND_NDCHOL && prob->precision != CGP_FP64)
+    return fail(CGP_ERR_INVALID, "CGP_PRECOND_NDCHOL requires precision CGP_FP64");
   cgp::Mesh cm;
   cm.n_nodes = m.n_nodes;
   cm.n_tris = m.n_tris;
@@ -537,6 +614,22 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   if (c->cheb_iters > prob->mass_max_iter) {
     delete c;
     return fail(CGP_ERR_INVALID, "mass_max_iter is below the Chebyshev count for mass_tol");
+  }
+  if (prob->coarse_precond == CGP_PRECOND_NDCHOL) {
+    // phi = 0 nodes are not unknowns; without any, K_c is singular (constant
+    // null space) and the last coarse node is pinned
+    std::vector<uint8_t> skip(c->h.nat_c.begin(), c->h.nat_c.end());
+    if (c->h.n_nat_c == 0) skip[c->nc - 1] = 1;
+    try {
+      err = cgp::nd_symbolic(c->nc, c->h.gc.rowptr, c->h.gc.col, c->h.coarse.xy.data(), skip,
+                             c->nd);
+    } catch (const std::exception& e) {
+      err = std::string("coarse factor set-up failed: ") + e.what();
+    }
+    if (!err.empty()) {
+      delete c;
+      return fail(CGP_ERR_INVALID, err);
+    }
   }
   c->ws_bytes = carve(c, nullptr);
   *out = c;
@@ -611,6 +704,36 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   cgp::net::launch_edge_features(c->C, c->hbar, c->net, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  if (c->prob.coarse_precond == CGP_PRECOND_NDCHOL) {
+    // factor the K_c just assembled (its own rounding), upload the factor
+    cgp::NdFactor& f = c->nd;
+    std::vector<double> kc(h.gc.nnz());
+    HIPCHK(hipMemcpyAsync(kc.data(), c->Kc, sizeof(double) * kc.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::string err;
+    try {
+      err = cgp::nd_numeric(h.gc.rowptr, h.gc.col, kc.data(), f);
+    } catch (const std::exception& e) {
+      err = std::string("coarse factorisation failed: ") + e.what();
+    }
+    if (!err.empty()) return fail(CGP_ERR_INVALID, err);
+    const cgp::NdDev& d = c->ndd;
+    HIPCHK(up((void*)d.perm, f.perm.data(), sizeof(int32_t) * f.perm.size()));
+    HIPCHK(up((void*)d.sn, f.sn.data(), sizeof(cgp::NdSuper) * f.sn.size()));
+    HIPCHK(up((void*)d.rows, f.rows.data(), sizeof(int32_t) * f.rows.size()));
+    HIPCHK(up((void*)d.gptr, f.gptr.data(), sizeof(int32_t) * f.gptr.size()));
+    HIPCHK(up((void*)d.gidx, f.gidx.data(), sizeof(int32_t) * f.gidx.size()));
+    HIPCHK(up((void*)d.fwd, f.fwd.data(), sizeof(cgp::NdItem) * f.fwd.size()));
+    HIPCHK(up((void*)d.bwd, f.bwd.data(), sizeof(cgp::NdItem) * f.bwd.size()));
+    HIPCHK(up((void*)d.G, f.G.data(), sizeof(double) * f.G.size()));
+    HIPCHK(up((void*)d.GT, f.GT.data(), sizeof(double) * f.GT.size()));
+    // z is written at the factored unknowns only: zero once
+    cgp::launch_fill(c->nd_z, 0.0, c->nc, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double>().swap(f.G);
+    std::vector<double>().swap(f.GT);
+  }
   c->assembled = true;
   return CGP_OK;
 }
@@ -661,6 +784,49 @@ int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   int rc = run_correct(c, ut, phi_f, p_in, u_out, p_out, st, as_stream(stream));
   HIPCHK(hipGetLastError());
   return rc;
+}
+
+int cgp_query_ndchol(const cgp_ctx* c, cgp_ndchol_info* out) {
+  if (!c || !out) return fail(CGP_ERR_INVALID, "null argument");
+  const cgp::NdFactor& f = c->nd;
+  out->n_factored = f.nfac;
+  out->n_supernodes = (int32_t)f.sn.size();
+  out->height = f.height;
+  out->max_front = f.max_front;
+  out->g_entries = f.g_entries;
+  return CGP_OK;
+}
+
+int cgp_ndchol_solve_host(int32_t n, const int32_t* rowptr, const int32_t* col,
+                          const double* val, const double* xy, const uint8_t* skip,
+                          const double* r, double* z, cgp_ndchol_info* info) {
+  if (n < 1 || !rowptr || !col || !val || !xy || !skip || !r || !z)
+    return fail(CGP_ERR_INVALID, "null argument or n < 1");
+  if (rowptr[0] != 0) return fail(CGP_ERR_INVALID, "rowptr[0] must be 0");
+  for (int32_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(CGP_ERR_INVALID, "rowptr not monotone");
+  for (int32_t e = 0; e < rowptr[n]; ++e)
+    if (col[e] < 0 || col[e] >= n) return fail(CGP_ERR_INVALID, "column index out of range");
+  std::vector<int32_t> rp(rowptr, rowptr + n + 1), cl(col, col + rowptr[n]);
+  std::vector<uint8_t> sk(skip, skip + n);
+  cgp::NdFactor f;
+  std::string err;
+  try {
+    err = cgp::nd_symbolic(n, rp, cl, xy, sk, f);
+    if (err.empty()) err = cgp::nd_numeric(rp, cl, val, f);
+  } catch (const std::exception& e) {
+    err = std::string("factorisation failed: ") + e.what();
+  }
+  if (!err.empty()) return fail(CGP_ERR_INVALID, err);
+  cgp::nd_solve_host(f, r, z);
+  if (info) {
+    info->n_factored = f.nfac;
+    info->n_supernodes = (int32_t)f.sn.size();
+    info->height = f.height;
+    info->max_front = f.max_front;
+    info->g_entries = f.g_entries;
+  }
+  return CGP_OK;
 }
 
 }  // extern "C"

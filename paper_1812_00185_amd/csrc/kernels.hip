@@ -1225,6 +1225,91 @@ __global__ void k_reduce_check(const double* part, int nb, double tol, Scal* sc,
   }
 }
 
+// ------------------------------------------------ PCG with a factor preconditioner
+// Textbook PCG (two reductions per iteration) around z = M^-1 r from the
+// nested-dissection factor: partials of (r, z); the new direction with
+// q = K p (p formed on the fly at the gathered columns, so p alternates
+// between two buffers); the update of x and r.  rho of even / odd
+// iterations alternates in the scalars as in the single-reduction PCG.
+
+__global__ void __launch_bounds__(kBlock)
+k_fpcg_rz(int32_t n, const double* __restrict__ r, const double* __restrict__ z, double* part) {
+  double t = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) t += r[i] * z[i];
+  const double vals[1] = {t};
+  const int o[1] = {slot(SL_RZ, 0)};
+  block_store<1>(vals, part, o);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fpcg_dir(int32_t n, const int32_t* __restrict__ ecol, const double* __restrict__ eval, int ew,
+           const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
+           double* __restrict__ q, Scal* sc, double* part, int nb, int it) {
+  const int idx[1] = {slot(SL_RZ, 0)};
+  double rz[1];
+  block_sums<1>(part, nb, idx, rz);
+  const double rho_prev = sc[0].rho[(it - 1) & 1];
+  const bool first = it == 1;
+  const double beta = first || rho_prev == 0.0 ? 0.0 : rz[0] / rho_prev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[0].rho[it & 1] = rz[0];
+  const int64_t ln = n;
+  double pq = 0.0;
+  for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
+    const double pr = first ? z[row] : z[row] + beta * pold[row];
+    double acc = 0.0;
+    for (int k0 = 0; k0 < ew; k0 += kRowBatch) {
+      int cix[kRowBatch];
+      double gv[kRowBatch], gz[kRowBatch], gp[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int64_t e = (int64_t)(k0 + u) * ln + row;
+        cix[u] = ecol[e];
+        gv[u] = eval[e];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        gz[u] = z[cix[u]];
+        gp[u] = first ? 0.0 : pold[cix[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) acc += gv[u] * (gz[u] + beta * gp[u]);
+    }
+    pnew[row] = pr;
+    q[row] = acc;
+    pq += pr * acc;
+  }
+  const double vals[1] = {pq};
+  const int o[1] = {slot(SL_PQ, 0)};
+  block_store<1>(vals, part, o);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fpcg_update(int32_t n, const double* __restrict__ p, const double* __restrict__ q,
+              double* __restrict__ x, double* __restrict__ r, const Scal* sc, double* part, int nb,
+              int it) {
+  const int idx[1] = {slot(SL_PQ, 0)};
+  double pq[1];
+  block_sums<1>(part, nb, idx, pq);
+  const double rho = sc[0].rho[it & 1];
+  const double alpha = pq[0] != 0.0 ? rho / pq[0] : 0.0;
+  double rr = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    rr += rn * rn;
+  }
+  const double vals[1] = {rr};
+  const int o[1] = {slot(SL_RR, 0)};
+  block_store<1>(vals, part, o);
+}
+
+__global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
 inline int grid_for(int64_t units, int per_block, int cap = 4096) {
   int64_t g = (units + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1422,6 +1507,20 @@ void launch_guard(const DLevel& C, const double* Kval, const double* b, const do
                   hipStream_t s) {
   k_guard_residuals<<<nb, kBlock, 0, s>>>(C, Kval, b, cand, prev, part);
   k_guard_select<<<nb, kBlock, 0, s>>>(C.n, cand, prev, out, chose, part, nb);
+}
+
+
+void launch_fpcg_iter(int32_t n, const int32_t* ell_col, const double* ell_val, int ell_w,
+                      const double* z, double* const p[2], double* q, double* x, double* r,
+                      Scal* sc, double* part, int nb, int it, hipStream_t s) {
+  k_fpcg_rz<<<nb, kBlock, 0, s>>>(n, r, z, part);
+  k_fpcg_dir<<<nb, kBlock, 0, s>>>(n, ell_col, ell_val, ell_w, z, p[(it - 1) & 1], p[it & 1], q,
+                                   sc, part, nb, it);
+  k_fpcg_update<<<nb, kBlock, 0, s>>>(n, p[it & 1], q, x, r, sc, part, nb, it);
+}
+
+void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
+  k_fill<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, v, n);
 }
 
 }  // namespace cgp

@@ -37,7 +37,8 @@ class CGP:
                  precision: str = "fp64", restrict: str = "galerkin", pcg_tol: float = 1e-8,
                  inner_tol: float = 1e-5, mom_tol: float = 1e-12, mass_tol: float = 1e-12,
                  max_iter: int = 20000, mom_max_iter: int = 1000, mass_max_iter: int = 1000,
-                 max_outer: int = 20, mass: str = "consistent", device="cuda:0"):
+                 max_outer: int = 20, mass: str = "consistent", precond: str = "jacobi",
+                 device="cuda:0"):
         import torch
 
         self.lib = N.load()
@@ -56,15 +57,19 @@ class CGP:
         rmode = {"galerkin": N.CGP_RESTRICT_GALERKIN, "inject": N.CGP_RESTRICT_INJECT}[restrict]
         mmode = {"consistent": N.CGP_MASS_CONSISTENT, "lumped_p": N.CGP_MASS_LUMPED_P,
                  "lumped": N.CGP_MASS_LUMPED}[mass]
+        pmode = {"jacobi": N.CGP_PRECOND_JACOBI, "ndchol": N.CGP_PRECOND_NDCHOL}[precond]
         self.problem = N.Problem(mesh, levels, chi, prec, rmode, dt, nu, pcg_tol, inner_tol,
                                  mom_tol, mass_tol, max_iter, mom_max_iter, mass_max_iter,
-                                 max_outer, mmode)
+                                 max_outer, mmode, pmode)
         ctx = C.c_void_p()
         N.check(self.lib.cgp_create(C.byref(self.problem), C.byref(ctx)))
         self.ctx = ctx
         sz = N.Sizes()
         N.check(self.lib.cgp_query(self.ctx, C.byref(sz)))
         self.sizes = sz
+        nd = N.NdcholInfo()
+        N.check(self.lib.cgp_query_ndchol(self.ctx, C.byref(nd)))
+        self.ndchol = nd.as_dict()
         self.nf, self.nc = int(sz.n_fine), int(sz.n_coarse)
         self.ndir = int(sz.n_dirichlet)
         xyf = np.empty(2 * self.nf)

@@ -31,7 +31,7 @@ def solver(w):
     return CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
                precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
                pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol,
-               mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass)
+               mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass, precond=w.precond)
 
 
 def run(w, steps):
@@ -76,3 +76,13 @@ def test_taylor_green_2049_k3_one_step():
     ((du, dp, st),) = run(w, 1)
     assert st["poisson"]["converged"]
     assert du <= 1e-10 and dp <= 1e-10
+
+
+def test_taylor_green_2049_k3_ndchol_two_steps():
+    """The same workload with the coarse PCG preconditioned by the
+    nested-dissection factor (257 x 257 coarse unknowns), against the oracle
+    with an exact coarse solve."""
+    w = get_workload("tg2049_k3_fp64").with_(precond="ndchol")
+    for du, dp, st in run(w, 2):
+        assert st["poisson"]["converged"] and st["poisson"]["iters"] <= 2
+        assert du <= 1e-10 and dp <= 1e-10

@@ -38,7 +38,7 @@ def make(w, **kw):
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
             precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
             pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol,
-            max_iter=w.max_iter, mass=w.mass, **kw)
+            max_iter=w.max_iter, mass=w.mass, precond=w.precond, **kw)
     o = build_oracle(w)
     return g, o
 

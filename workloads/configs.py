@@ -37,6 +37,7 @@ class Workload:
     max_iter: int = 20000
     restrict: str = "galerkin"     # 'galerkin' | 'inject'
     mass: str = "consistent"       # 'consistent' | 'lumped_p' (Eq. 27) | 'lumped'
+    precond: str = "jacobi"        # coarse PCG preconditioner: 'jacobi' | 'ndchol' (exact factor)
     lid_speed: float = 1.0
     channel_h: float = 0.0082
     seed: int = 0
