@@ -71,6 +71,7 @@ struct cgp_ctx {
   float *Kc32 = nullptr, *invdKc32 = nullptr;
   // ELL copy of K_c for the PCG iteration kernel (width = longest row)
   int ell_w = 0;
+  int mom_expect = 0;  // iterations of the last momentum solve (0: unknown)
   int32_t* ell_col = nullptr;
   double* ell_val = nullptr;
   float* ell_val32 = nullptr;
@@ -246,20 +247,34 @@ struct NoStop {
 template <class Launch, class Stop = NoStop>
 int drive(cgp_ctx* c, Scal* sc, int nrhs, int last, int chunk, bool trailing_check,
           Launch launch, hipStream_t s, Scal* out, Stop stop = Stop(),
-          int* launched = nullptr) {
+          int* launched = nullptr, int first = 0) {
   int it = 1, k = 0;
   bool have_prev = false;
+  auto all_done = [&](int slot) {
+    for (int d = 0; d < nrhs; ++d)
+      if (c->pinned[8 * slot + d].done_stamp == 0) return false;
+    return true;
+  };
+  if (first > 0) {
+    // a first chunk of the expected length, polled before anything else is
+    // queued (no speculative iterations when the expectation holds)
+    const int hi = std::min(first, last);
+    for (; it <= hi; ++it) launch(it, trailing_check && it == last);
+    if (launched) *launched = it - 1;
+    cgp::launch_mirror(sc, c->pinned, nrhs, s);
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    HIPCHK(hipEventSynchronize(c->ev[0]));
+    if (all_done(0) || it > last || stop(c->pinned)) {
+      std::memcpy(out, c->pinned, sizeof(Scal) * nrhs);
+      return CGP_OK;
+    }
+  }
   while (true) {
     const int hi = std::min(it + chunk - 1, last);
     for (; it <= hi; ++it) launch(it, trailing_check && it == last);
     if (launched) *launched = it - 1;
     cgp::launch_mirror(sc, c->pinned + 8 * k, nrhs, s);
     HIPCHK(hipEventRecord(c->ev[k], s));
-    auto all_done = [&](int slot) {
-      for (int d = 0; d < nrhs; ++d)
-        if (c->pinned[8 * slot + d].done_stamp == 0) return false;
-      return true;
-    };
     if (have_prev) {
       HIPCHK(hipEventSynchronize(c->ev[k ^ 1]));
       if (all_done(k ^ 1)) {
@@ -315,13 +330,17 @@ int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
   cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
   Scal out[2];
   const int last = P.mom_max_iter + 1;
+  // the first chunk covers the previous solve's iterations plus the launch
+  // that runs the final test
+  const int first = c->mom_expect > 0 ? c->mom_expect + 1 : 0;
   int rc = drive(c, c->scal, 2, last, 4, true,
                  [&](int it, bool chk) {
                    cgp::launch_bicg_iter(c->F, c->Aval, V, c->scal, c->part, c->nb_f, it,
                                          P.mom_tol, chk, s, chk ? nullptr : timer(c, CGP_K_MOM_SPMV));
                  },
-                 s, out);
+                 s, out, NoStop(), nullptr, first);
   if (rc) return rc;
+  c->mom_expect = (out[0].done_stamp && out[1].done_stamp) ? std::max(out[0].iters, out[1].iters) : 0;
   return stats_status(out, 2, P.mom_max_iter, st);
 }
 
@@ -341,20 +360,31 @@ int run_restrict(cgp_ctx* c, const double* ut, double* b, hipStream_t s) {
   return CGP_OK;
 }
 
-// PCG preconditioned by the nested-dissection factor: the FP64 residual is
-// tested before the first iteration and after each one (host polls; with the
-// exact factor one iteration reaches rounding level).
+// PCG preconditioned by the nested-dissection factor.  The FP64 residual is
+// tested before the first iteration and after each one.  The first test and
+// the first iteration are queued together (the iteration's kernels return at
+// once if the test found the guess converged), so a solve that one iteration
+// finishes, the usual case with the exact factor, costs one host poll.
 int run_pcg_nd(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
-  cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
   double* const pbuf[2] = {c->nd_p[0], c->nd_p[1]};
+  Scal* const first = c->scal + 4;  // test of the guess
+  Scal* const later = c->scal + 6;  // test after each iteration
+  cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
+  cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, first, 0, s);
+  cgp::launch_nd_solve(c->ndd, c->nd, c->cr, c->nd_z, s, first);
+  cgp::launch_fpcg_iter(c->nc, c->ell_col, c->ell_val, c->ell_w, c->nd_z, pbuf, c->nd_q, x,
+                        c->cr, c->scal + 5, c->part, c->nb_c, 1, s, first);
+  cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, later, 1, s);
+  cgp::launch_mirror(first, c->pinned, 3, s);
+  HIPCHK(hipStreamSynchronize(s));
   int it = 0, rc = CGP_OK;
-  Scal chk{};
+  Scal chk = c->pinned[0];
+  if (chk.status != 2 && chk.bb != 0.0 && !chk.done_stamp) {
+    it = 1;
+    chk = c->pinned[2];
+  }
   for (;;) {
-    cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, c->scal + 4, it, s);
-    cgp::launch_mirror(c->scal + 4, c->pinned, 1, s);
-    HIPCHK(hipStreamSynchronize(s));
-    chk = c->pinned[0];
     if (chk.status == 2) {
       rc = fail(CGP_ERR_NAN, "coarse PCG produced NaN/Inf");
       break;
@@ -372,6 +402,10 @@ int run_pcg_nd(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipS
     cgp::launch_nd_solve(c->ndd, c->nd, c->cr, c->nd_z, s);
     cgp::launch_fpcg_iter(c->nc, c->ell_col, c->ell_val, c->ell_w, c->nd_z, pbuf, c->nd_q, x,
                           c->cr, c->scal + 5, c->part, c->nb_c, it, s);
+    cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, later, it, s);
+    cgp::launch_mirror(later, c->pinned, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    chk = c->pinned[0];
   }
   if (st) {
     st->iters = it;

@@ -154,10 +154,12 @@ void launch_reduce_check(const double* part, int nb, double tol, Scal* sc, int o
 
 // one iteration of PCG with the factor preconditioner, after z = M^-1 r:
 // p_it = z + beta p_{it-1} (p alternates between p[0] and p[1]), q = K p_it,
-// x += alpha p_it, r -= alpha q; leaves the partials of (r, r) in the RR slot
+// x += alpha p_it, r -= alpha q; leaves the partials of (r, r) in the RR slot.
+// With skip != nullptr the kernels return at once when skip->done_stamp is set.
 void launch_fpcg_iter(int32_t n, const int32_t* ell_col, const double* ell_val, int ell_w,
                       const double* z, double* const p[2], double* q, double* x, double* r,
-                      Scal* sc, double* part, int nb, int it, hipStream_t s);
+                      Scal* sc, double* part, int nb, int it, hipStream_t s,
+                      const Scal* skip = nullptr);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 
 }  // namespace cgp

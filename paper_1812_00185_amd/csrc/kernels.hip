@@ -1233,7 +1233,9 @@ __global__ void k_reduce_check(const double* part, int nb, double tol, Scal* sc,
 // iterations alternates in the scalars as in the single-reduction PCG.
 
 __global__ void __launch_bounds__(kBlock)
-k_fpcg_rz(int32_t n, const double* __restrict__ r, const double* __restrict__ z, double* part) {
+k_fpcg_rz(int32_t n, const double* __restrict__ r, const double* __restrict__ z, double* part,
+          const Scal* skip) {
+  if (skip && skip->done_stamp) return;
   double t = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) t += r[i] * z[i];
   const double vals[1] = {t};
@@ -1244,7 +1246,8 @@ k_fpcg_rz(int32_t n, const double* __restrict__ r, const double* __restrict__ z,
 __global__ void __launch_bounds__(kBlock)
 k_fpcg_dir(int32_t n, const int32_t* __restrict__ ecol, const double* __restrict__ eval, int ew,
            const double* __restrict__ z, const double* __restrict__ pold, double* __restrict__ pnew,
-           double* __restrict__ q, Scal* sc, double* part, int nb, int it) {
+           double* __restrict__ q, Scal* sc, double* part, int nb, int it, const Scal* skip) {
+  if (skip && skip->done_stamp) return;
   const int idx[1] = {slot(SL_RZ, 0)};
   double rz[1];
   block_sums<1>(part, nb, idx, rz);
@@ -1286,7 +1289,8 @@ k_fpcg_dir(int32_t n, const int32_t* __restrict__ ecol, const double* __restrict
 __global__ void __launch_bounds__(kBlock)
 k_fpcg_update(int32_t n, const double* __restrict__ p, const double* __restrict__ q,
               double* __restrict__ x, double* __restrict__ r, const Scal* sc, double* part, int nb,
-              int it) {
+              int it, const Scal* skip) {
+  if (skip && skip->done_stamp) return;
   const int idx[1] = {slot(SL_PQ, 0)};
   double pq[1];
   block_sums<1>(part, nb, idx, pq);
@@ -1512,11 +1516,11 @@ void launch_guard(const DLevel& C, const double* Kval, const double* b, const do
 
 void launch_fpcg_iter(int32_t n, const int32_t* ell_col, const double* ell_val, int ell_w,
                       const double* z, double* const p[2], double* q, double* x, double* r,
-                      Scal* sc, double* part, int nb, int it, hipStream_t s) {
-  k_fpcg_rz<<<nb, kBlock, 0, s>>>(n, r, z, part);
+                      Scal* sc, double* part, int nb, int it, hipStream_t s, const Scal* skip) {
+  k_fpcg_rz<<<nb, kBlock, 0, s>>>(n, r, z, part, skip);
   k_fpcg_dir<<<nb, kBlock, 0, s>>>(n, ell_col, ell_val, ell_w, z, p[(it - 1) & 1], p[it & 1], q,
-                                   sc, part, nb, it);
-  k_fpcg_update<<<nb, kBlock, 0, s>>>(n, p[it & 1], q, x, r, sc, part, nb, it);
+                                   sc, part, nb, it, skip);
+  k_fpcg_update<<<nb, kBlock, 0, s>>>(n, p[it & 1], q, x, r, sc, part, nb, it, skip);
 }
 
 void launch_fill(double* x, double v, int64_t n, hipStream_t s) {

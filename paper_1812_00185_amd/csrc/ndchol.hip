@@ -7,42 +7,72 @@
 
 #include <algorithm>
 
+#include "device.hpp"
 #include "ndchol.hpp"
 
 namespace cgp {
 namespace {
 
 constexpr int kNdWave = 64;
+constexpr int kNdWaves = 4;  // waves per item, each over a quarter of the reduction
+constexpr int kNdBlock = kNdWave * kNdWaves;
 static_assert(kNdItemRows == kNdWave, "one output row (column) per lane");
 
+// sum over [a, b) of g[k * ld] * x[k], 8 loads in flight
+__device__ __forceinline__ double dot_strided(const double* __restrict__ g, int64_t ld,
+                                              const double* x, int a, int b) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int k = a;
+  for (; k + 8 <= b; k += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += g[(int64_t)(k + u) * ld] * x[k + u];
+  }
+  for (; k < b; ++k) acc[0] += g[(int64_t)k * ld] * x[k];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// the kNdWaves partial sums of each lane, added in wave order by wave 0
+__device__ __forceinline__ double combine(double part, double (&sh)[kNdWaves][kNdWave]) {
+  const int lane = threadIdx.x % kNdWave, wv = threadIdx.x / kNdWave;
+  sh[wv][lane] = part;
+  __syncthreads();
+  double t = 0.0;
+  if (wv == 0) {
+#pragma unroll
+    for (int q = 0; q < kNdWaves; ++q) t += sh[q][lane];
+  }
+  return t;
+}
+
+__device__ __forceinline__ bool nd_skip(const Scal* flag) {
+  return flag != nullptr && flag->done_stamp != 0;
+}
+
 // forward: y_C and u of one item; f_C = r on C plus the children's updates
-__global__ void __launch_bounds__(kNdWave)
-k_nd_forward(NdDev d, const NdItem* __restrict__ items, const double* __restrict__ r) {
+__global__ void __launch_bounds__(kNdBlock)
+k_nd_forward(NdDev d, const NdItem* __restrict__ items, const double* __restrict__ r,
+             const Scal* flag) {
   extern __shared__ double fc[];
+  __shared__ double part[kNdWaves][kNdWave];
+  if (nd_skip(flag)) return;
   const NdItem it = items[blockIdx.x];
   const NdSuper S = d.sn[it.sn];
   const int fs = S.w + S.m;
-  for (int j = threadIdx.x; j < S.w; j += kNdWave) {
+  for (int j = threadIdx.x; j < S.w; j += kNdBlock) {
     double v = r[d.perm[S.c0 + j]];
     for (int q = d.gptr[S.gpos + j]; q < d.gptr[S.gpos + j + 1]; ++q) v += d.U[d.gidx[q]];
     fc[j] = v;
   }
   __syncthreads();
-  const int o = it.lo + threadIdx.x;
-  if (o >= it.hi) return;
+  const int lane = threadIdx.x % kNdWave, wv = threadIdx.x / kNdWave;
+  const int o = it.lo + lane;
+  const int oc = o < it.hi ? o : it.lo;  // idle lanes read a valid row
   // rows of L11^-1 are zero right of the diagonal
   const int jmax = it.hi <= S.w ? it.hi : S.w;
-  const double* __restrict__ g = d.G + S.goff + o;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int j = 0;
-  for (; j + 4 <= jmax; j += 4) {
-    a0 += g[(int64_t)j * fs] * fc[j];
-    a1 += g[(int64_t)(j + 1) * fs] * fc[j + 1];
-    a2 += g[(int64_t)(j + 2) * fs] * fc[j + 2];
-    a3 += g[(int64_t)(j + 3) * fs] * fc[j + 3];
-  }
-  for (; j < jmax; ++j) a0 += g[(int64_t)j * fs] * fc[j];
-  const double acc = (a0 + a1) + (a2 + a3);
+  const int chunk = (jmax + kNdWaves - 1) / kNdWaves;
+  const int a = min(jmax, wv * chunk), b = min(jmax, a + chunk);
+  const double acc = combine(dot_strided(d.G + S.goff + oc, fs, fc, a, b), part);
+  if (wv != 0 || o >= it.hi) return;
   if (o < S.w) {
     d.Y[S.c0 + o] = acc;
   } else {
@@ -53,29 +83,27 @@ k_nd_forward(NdDev d, const NdItem* __restrict__ items, const double* __restrict
 }
 
 // backward: x_C = G^T [y_C ; -x_R] for one item's columns
-__global__ void __launch_bounds__(kNdWave)
-k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z) {
+__global__ void __launch_bounds__(kNdBlock)
+k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z,
+              const Scal* flag) {
   extern __shared__ double v[];
+  __shared__ double part[kNdWaves][kNdWave];
+  if (nd_skip(flag)) return;
   const NdItem it = items[blockIdx.x];
   const NdSuper S = d.sn[it.sn];
   const int fs = S.w + S.m;
   // rows of the column range start at it.lo (L11^-T is upper triangular)
-  for (int o = it.lo + threadIdx.x; o < fs; o += kNdWave)
+  for (int o = it.lo + threadIdx.x; o < fs; o += kNdBlock)
     v[o] = o < S.w ? d.Y[S.c0 + o] : -d.X[d.rows[S.roff + o - S.w]];
   __syncthreads();
-  const int i = it.lo + threadIdx.x;
-  if (i >= it.hi) return;
-  const double* __restrict__ g = d.GT + S.goff + i;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int o = it.lo;
-  for (; o + 4 <= fs; o += 4) {
-    a0 += g[(int64_t)o * S.w] * v[o];
-    a1 += g[(int64_t)(o + 1) * S.w] * v[o + 1];
-    a2 += g[(int64_t)(o + 2) * S.w] * v[o + 2];
-    a3 += g[(int64_t)(o + 3) * S.w] * v[o + 3];
-  }
-  for (; o < fs; ++o) a0 += g[(int64_t)o * S.w] * v[o];
-  const double acc = (a0 + a1) + (a2 + a3);
+  const int lane = threadIdx.x % kNdWave, wv = threadIdx.x / kNdWave;
+  const int i = it.lo + lane;
+  const int ic = i < it.hi ? i : it.lo;
+  const int len = fs - it.lo;
+  const int chunk = (len + kNdWaves - 1) / kNdWaves;
+  const int a = it.lo + min(len, wv * chunk), b = it.lo + min(len, (wv + 1) * chunk);
+  const double acc = combine(dot_strided(d.GT + S.goff + ic, S.w, v, a, b), part);
+  if (wv != 0 || i >= it.hi) return;
   d.X[S.c0 + i] = acc;
   z[d.perm[S.c0 + i]] = acc;
 }
@@ -83,18 +111,18 @@ k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z)
 }  // namespace
 
 void launch_nd_solve(const NdDev& d, const NdFactor& f, const double* r, double* z,
-                     hipStream_t s) {
+                     hipStream_t s, const Scal* skip_if_done) {
   for (int L = 0; L < f.height; ++L) {
     const int a = f.fwd_lvl[L], b = f.fwd_lvl[L + 1];
     int lds = 1;
     for (int k = a; k < b; ++k) lds = std::max(lds, f.sn[f.fwd[k].sn].w);
-    k_nd_forward<<<b - a, kNdWave, sizeof(double) * lds, s>>>(d, d.fwd + a, r);
+    k_nd_forward<<<b - a, kNdBlock, sizeof(double) * lds, s>>>(d, d.fwd + a, r, skip_if_done);
   }
   for (int q = 0; q < f.height; ++q) {
     const int a = f.bwd_lvl[q], b = f.bwd_lvl[q + 1];
     int lds = 1;
     for (int k = a; k < b; ++k) lds = std::max(lds, f.sn[f.bwd[k].sn].w + f.sn[f.bwd[k].sn].m);
-    k_nd_backward<<<b - a, kNdWave, sizeof(double) * lds, s>>>(d, d.bwd + a, z);
+    k_nd_backward<<<b - a, kNdBlock, sizeof(double) * lds, s>>>(d, d.bwd + a, z, skip_if_done);
   }
 }
 

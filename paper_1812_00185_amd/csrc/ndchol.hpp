@@ -108,10 +108,13 @@ struct NdDev {
   double* U;  // [n_upd] update vectors
 };
 
+struct Scal;
+
 // z = K^-1 r on the factored unknowns: one forward launch per tree level
 // (leaves first), then one backward launch per level (root first).  Entries
-// of z at skipped nodes are not written.
+// of z at skipped nodes are not written.  With skip_if_done != nullptr every
+// launch returns at once when that record's done_stamp is set.
 void launch_nd_solve(const NdDev& d, const NdFactor& f, const double* r, double* z,
-                     hipStream_t s);
+                     hipStream_t s, const Scal* skip_if_done = nullptr);
 
 }  // namespace cgp
