@@ -49,17 +49,21 @@ HBM_PEAK_GBS = 8000.0
 
 # algorithmic bytes per launch of each timed kernel (int32 indices, FP64 values):
 # CSR matrix 12 B/nnz + 4 B/row pointer; every vector once.
-#  mass_spmv:   one fused Chebyshev step over nr right-hand sides: Dirichlet
-#               index 4 B per row (the Jacobi diagonal is the row's first
-#               matrix entry), and per rhs the gathered iterate, the previous
-#               iterate, b and the new iterate
+#  mass_spmv:   one fused Chebyshev step over nr right-hand sides on the
+#               lattice layout: per fine node and rhs the gathered iterate, the
+#               previous iterate, b and the new iterate (32 B), a Dirichlet
+#               flag byte; per coarse triangle its area, vertices and edges
+#               (32 B); per coarse edge its ends and triangles (16 B); the CSR
+#               rows of the coarse vertices (2E + V entries of 16 B: value,
+#               column, its lattice index) and their row pointers
 #  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written
 #  coarse_spmv: one single-reduction PCG iteration: x, p, r, w, s, D^-1 read,
 #               x, p, r, w, s written
 KERNELS = {
-    "mass_spmv": (1, lambda n, z, nr: 12 * z + 4 * (n + 1) + 4 * n + 32 * nr * n),
-    "mom_spmv": (2, lambda n, z, nr: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
-    "coarse_spmv": (3, lambda n, z, nr: 12 * z + 4 * (n + 1) + 11 * 8 * n),
+    "mass_spmv": (1, lambda n, z, nr, t, e, v: 32 * nr * n + n + 32 * t + 16 * e
+                  + 16 * (2 * e + v) + 4 * v),
+    "mom_spmv": (2, lambda n, z, nr, t, e, v: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
+    "coarse_spmv": (3, lambda n, z, nr, t, e, v: 12 * z + 4 * (n + 1) + 11 * 8 * n),
 }
 
 
@@ -287,7 +291,9 @@ def main():
     fine_xy = g.fine_xy
     sizes = {"fine_nodes": g.nf, "coarse_nodes": g.nc, "nnz_fine": int(g.sizes.nnz_fine)}
     n_rows, nnz = (g.nc, int(g.sizes.nnz_coarse)) if kid == 3 else (g.nf, int(g.sizes.nnz_fine))
-    bpl = kbytes(n_rows, nnz, 3 if w.chi else 2)
+    tc, vc = int(g.sizes.n_coarse_tris), g.nc
+    ec = (int(g.sizes.nnz_coarse) - vc) // 2   # the coarse graph holds N + 2E entries
+    bpl = kbytes(n_rows, nnz, 3 if w.chi else 2, tc, ec, vc)
     avg_s = (kms / 1e3) / max(nlaunch, 1)
     achieved = bpl / avg_s / 1e9 if nlaunch else None
     traffic, traffic_src = stored_traffic(w.name, args.timed_kernel)

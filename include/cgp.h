@@ -349,6 +349,18 @@ typedef struct cgp_ndchol_info {
  * otherwise). */
 int cgp_query_ndchol(const cgp_ctx* ctx, cgp_ndchol_info* out);
 
+/* ---- Lattice mass operator -----------------------------------------------
+ * The consistent mass solves (Eqs. 25, 26) run on a lattice layout of the
+ * fine nodes: inside a coarse triangle every fine triangle has area
+ * |T| / 4^k and edges parallel to T's, so M is applied from the coarse
+ * areas and lattice offsets (stored matrix rows only at coarse vertices).
+ * Host-only check of that operator on a context: y = M x and diag = M_ii
+ * for x (host [N_f], fine numbering), with the rows of the coarse vertices
+ * taken from the given CSR matrix (rowptr [N_c + 1] at least, col, mval; fine
+ * numbering, columns in range).  Errors: CGP_ERR_INVALID. */
+int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
+                                const double* mval, const double* x, double* y, double* diag);
+
 /* Host-only: orders, factors and applies the nested-dissection factor of a
  * symmetric positive definite CSR matrix restricted to the rows/columns with
  * skip[i] == 0: z = K^-1 r there, z = 0 at skipped rows, by the level

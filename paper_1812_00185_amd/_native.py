@@ -122,6 +122,7 @@ SIGNATURES = [
     ("cgp_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("cgp_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("cgp_query_ndchol", C.c_int, [C.c_void_p, C.POINTER(NdcholInfo)]),
+    ("cgp_lattice_mass_apply_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, _dp, _dp, _dp]),
     ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,
                                         C.POINTER(C.c_uint8), _dp, _dp, C.POINTER(NdcholInfo)]),
     ("cgp_destroy", None, [C.c_void_p]),

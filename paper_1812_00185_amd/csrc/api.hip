@@ -81,6 +81,9 @@ struct cgp_ctx {
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
   int cheb_iters = 0;
+  // lattice layout of the mass solves (host structure and device view)
+  cgp::Lattice lat;
+  cgp::LatDev latd{};
   // coarse vectors: b_c, the PCG direction and alternating r, w, s (FP64 and
   // FP32), the refinement residual and a saved iterate
   double *bc = nullptr, *cr = nullptr, *cxsave = nullptr, *cp = nullptr;
@@ -140,6 +143,23 @@ size_t carve(cgp_ctx* c, void* base) {
   double** vec2[] = {&c->ut, &c->rhs, &c->r, &c->rhat, &c->p, &c->v, &c->phat, &c->shat, &c->t};
   for (double** q : vec2) *q = w.take<double>(2 * nf);
   c->phi_f = w.take<double>(nf);
+  {
+    const cgp::Lattice& L = c->lat;
+    cgp::LatDev& d = c->latd;
+    d.m = L.m;
+    d.nI = L.nI;
+    d.nT = L.nT;
+    d.nE = L.nE;
+    d.nV = L.nV;
+    d.EB = L.EB;
+    d.VB = L.VB;
+    d.tri_e = w.take<int32_t>(L.tri_e.size());
+    d.edge_v = w.take<int32_t>(L.edge_v.size());
+    d.edge_t = w.take<int32_t>(L.edge_t.size());
+    d.af = w.take<double>(L.af.size());
+    d.ldir = w.take<uint8_t>(L.ldir.size());
+    d.lat_of = w.take<int32_t>(L.lat_of.size());
+  }
   c->mrhs = w.take<double>(3 * nf);
   for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
 
@@ -209,6 +229,10 @@ size_t carve(cgp_ctx* c, void* base) {
   }
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
+  c->latd.tri_v = c->tri_c;
+  c->latd.rowptr = rp_f;
+  c->latd.col = col_f;
+  c->latd.M = c->Mval;
   c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
   return w.off + 256;
 }
@@ -551,7 +575,7 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   const bool cheb_p = chi && mode == CGP_MASS_CONSISTENT;
   const int nr = cheb_u ? (cheb_p ? 3 : 2) : 0;
   cgp::launch_correct_rhs(c->F, c->dir_index, c->Mval, P.dt, P.nu, chi, mode, phi_f, ut, p_in,
-                          c->mrhs, u_out, p_out, s);
+                          c->mrhs, u_out, p_out, c->latd.lat_of, s);
   if (st) {
     // a-priori bound of the Chebyshev iteration on [1/2, 2]; lumped: exact
     const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
@@ -561,11 +585,11 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
     }
   }
   if (nr == 0) return CGP_OK;  // the kernel wrote U and P
-  const double* du = cgp::launch_cheb(c->F, c->Mval, c->dir_index, c->mrhs, nr, c->mx,
-                                      c->cheb_iters, s,
+  const double* du = cgp::launch_cheb(c->latd, c->nf, c->mrhs, nr, c->mx, c->cheb_iters, s,
                                       c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
   // with the lumped pressure update the kernel above wrote P already
-  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, nr, cheb_p || !chi, u_out, p_out, s);
+  cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, nr, cheb_p || !chi, u_out, p_out,
+                           c->latd.lat_of, s);
   return CGP_OK;
 }
 
@@ -616,6 +640,15 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     err = cgp::build_hierarchy(cm, prob->levels, c->h);
   } catch (const std::exception& e) {
     err = std::string("host set-up failed: ") + e.what();
+  }
+  if (!err.empty()) {
+    delete c;
+    return fail(CGP_ERR_MESH, err);
+  }
+  try {
+    err = cgp::build_lattice(c->h, c->lat);
+  } catch (const std::exception& e) {
+    err = std::string("lattice set-up failed: ") + e.what();
   }
   if (!err.empty()) {
     delete c;
@@ -724,6 +757,16 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   HIPCHK(up(c->cn_ptr, h.cn_ptr.data(), 4 * h.cn_ptr.size()));
   HIPCHK(up(c->cn_tri, h.cn_tri.data(), 4 * h.cn_tri.size()));
   HIPCHK(up(c->nat_c, h.nat_c.data(), h.nat_c.size()));
+  {
+    const cgp::Lattice& L = c->lat;
+    const cgp::LatDev& d = c->latd;
+    HIPCHK(up((void*)d.tri_e, L.tri_e.data(), 4 * L.tri_e.size()));
+    HIPCHK(up((void*)d.edge_v, L.edge_v.data(), 4 * L.edge_v.size()));
+    HIPCHK(up((void*)d.edge_t, L.edge_t.data(), 4 * L.edge_t.size()));
+    HIPCHK(up((void*)d.af, L.af.data(), 8 * L.af.size()));
+    HIPCHK(up((void*)d.ldir, L.ldir.data(), L.ldir.size()));
+    HIPCHK(up((void*)d.lat_of, L.lat_of.data(), 4 * L.lat_of.size()));
+  }
   if (!c->pinned) {
     HIPCHK(hipHostMalloc((void**)&c->pinned, sizeof(Scal) * 16, hipHostMallocDefault));
     std::memset(c->pinned, 0, sizeof(Scal) * 16);
@@ -818,6 +861,43 @@ int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   int rc = run_correct(c, ut, phi_f, p_in, u_out, p_out, st, as_stream(stream));
   HIPCHK(hipGetLastError());
   return rc;
+}
+
+int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
+                                const double* mval, const double* x, double* y, double* diag) {
+  if (!c || !rowptr || !col || !mval || !x || !y || !diag) return fail(CGP_ERR_INVALID, "null argument");
+  const cgp::Lattice& L = c->lat;
+  cgp::LatDev v = L.host_view();
+  v.rowptr = rowptr;
+  v.col = col;
+  v.M = mval;
+  const int32_t n = c->nf;
+  for (int32_t e = 0; e < rowptr[c->nc]; ++e)
+    if (col[e] < 0 || col[e] >= n) return fail(CGP_ERR_INVALID, "column index out of range");
+  std::vector<double> xl(n);
+  std::vector<int32_t> node(n);
+  for (int32_t i = 0; i < n; ++i) {
+    xl[L.lat_of[i]] = x[i];
+    node[L.lat_of[i]] = i;
+  }
+  bool in_range = true;
+  for (int32_t l = 0; l < n; ++l) {
+    double yy[1], dg;
+    cgp::lat_apply<1>(v, l,
+                      [&](int32_t k, int) {
+                        if (k < 0 || k >= n) {
+                          in_range = false;
+                          return 0.0;
+                        }
+                        return xl[k];
+                      },
+                      yy, dg);
+    y[node[l]] = yy[0];
+    diag[node[l]] = dg;
+    if (cgp::lat_diag(v, l) != dg) return fail(CGP_ERR_INVALID, "lattice diagonals disagree");
+  }
+  if (!in_range) return fail(CGP_ERR_INVALID, "lattice stencil index out of range");
+  return CGP_OK;
 }
 
 int cgp_query_ndchol(const cgp_ctx* c, cgp_ndchol_info* out) {

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "lattice.hpp"
+
 namespace cgp {
 
 constexpr int kBlock = 256;    // threads per block (4 wave64)
@@ -102,11 +104,11 @@ void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* par
 
 // ---------------------------------------------------------------- Chebyshev mass solves
 int cheb_iterations(double tol);
-// Solves M x = b for nr (2 or 3) right-hand sides interleaved [n][nr]; returns the
+// Solves M x = b for nr (2 or 3) right-hand sides interleaved [n][nr] in the
+// lattice layout (velocity components 0 at Dirichlet nodes); returns the
 // buffer (one of x[0..2]) holding the result.  `timer(tctx)`, when given,
 // supplies an event pair per product launch.
-double* launch_cheb(const DLevel& L, const double* Mval, const int32_t* dir_index,
-                    const double* b, int nr,
+double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx);
 
@@ -134,12 +136,12 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double* Mval,
                         double dt, double nu, int chi, int mass_mode, const double* phi_f,
                         const double* ut, const double* p_in, double* rhs, double* u_out,
-                        double* p_out, hipStream_t s);
+                        double* p_out, const int32_t* lat_of, hipStream_t s);
 // U = U~ + dU from the solved increments du [n][nr]; P = P + phi (+ du[2]
 // when nr = 3) unless write_p is false
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
                          const double* phi_f, int nr, bool write_p, double* u_out,
-                         double* p_out, hipStream_t s);
+                         double* p_out, const int32_t* lat_of, hipStream_t s);
 
 // ---------------------------------------------------------------- small vector ops
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);

@@ -836,43 +836,37 @@ __global__ void k_make_ell(DLevel L, const double* __restrict__ val,
 // fused kernel per iteration with the iterates in three rotating buffers.
 // Right-hand sides and iterates are interleaved per node ([n][NR]) so that a
 // gathered neighbour costs one contiguous access.
+// One Chebyshev step of the mass solves on the lattice layout (one thread per
+// lattice node): x_new = x_k + ca (x_k - x_{k-1}) + cb D^-1 (b - M x_k), the
+// velocity components held at 0 on Dirichlet nodes.  M x_k and D come from
+// the lattice stencils (no matrix read away from the coarse vertices).  The
+// first step (x_0 = 0) needs only D and also clears x_k, which the next step
+// reads back as x_{k-1}.
 template <int NR>
 __global__ void __launch_bounds__(kBlock)
-k_cheb(DLevel L, const double* __restrict__ M, const int32_t* __restrict__ dir_index,
-       const double* __restrict__ b, double* __restrict__ xk, const double* __restrict__ xkm,
-       double* __restrict__ xnew, double ca, double cb, int first) {
-  __shared__ TileStage<double> st;
-  {  // one block per tile, in block order: a mapping that gave each XCD a
-     // contiguous range of tiles was measured slower (227 -> 321 us at 2049^2)
-    const int t = blockIdx.x;
-    const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    int s0 = 0;
-    if (!first) s0 = stage_tile(st, L, M, r0, r1);
-    const int row = r0 + threadIdx.x;
-    if (row >= r1) return;
-    double mx[NR];
-    if (!first)
-      tile_row<double, NR>(st, L, s0, row, [&](int d, int c) { return xk[(int64_t)c * NR + d]; },
-                           mx);
-    // Jacobi scaling by the diagonal (the first entry of the row), which is
-    // in LDS already; the first step reads it from memory
-    const double mii = first ? M[L.rowptr[row]] : st.val[L.rowptr[row] - s0];
-    const double di = 1.0 / mii;
-    const bool masked = dir_index[row] >= 0;
-    const int64_t base = (int64_t)row * NR;
+k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __restrict__ xk,
+               const double* __restrict__ xkm, double* __restrict__ xnew, double ca, double cb,
+               int first) {
+  const int32_t l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= n) return;
+  const bool masked = L.ldir[l] != 0;
+  const int64_t base = (int64_t)l * NR;
+  if (first) {
+    const double di = 1.0 / lat_diag(L, l);
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
-      const int64_t k = base + d;
-      double v;
-      if (d < 2 && masked)
-        v = 0.0;
-      else if (first)
-        v = cb * di * b[k];
-      else
-        v = xk[k] + ca * (xk[k] - xkm[k]) + cb * di * (b[k] - mx[d]);
-      xnew[k] = v;
-      if (first) xk[k] = 0.0;  // x_0 = 0 is read back as x_{k-1} by the next step
+      xnew[base + d] = (d < 2 && masked) ? 0.0 : cb * di * b[base + d];
+      xk[base + d] = 0.0;
     }
+    return;
+  }
+  double y[NR], diag;
+  lat_apply<NR>(L, l, [&](int32_t i, int d) { return xk[(int64_t)i * NR + d]; }, y, diag);
+  const double di = 1.0 / diag;
+#pragma unroll
+  for (int d = 0; d < NR; ++d) {
+    const int64_t k = base + d;
+    xnew[k] = (d < 2 && masked) ? 0.0 : xk[k] + ca * (xk[k] - xkm[k]) + cb * di * (b[k] - y[d]);
   }
 }
 
@@ -1042,7 +1036,8 @@ __global__ void __launch_bounds__(kBlock)
 k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __restrict__ M,
               double dt, double nu, int chi, int mode, const double* __restrict__ phi,
               const double* __restrict__ ut, const double* __restrict__ p_in,
-              double* __restrict__ rhs, double* __restrict__ u_out, double* __restrict__ p_out) {
+              double* __restrict__ rhs, double* __restrict__ u_out, double* __restrict__ p_out,
+              const int32_t* __restrict__ lat_of) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
   for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
@@ -1076,16 +1071,18 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __r
       const double rx = dir ? 0.0 : (dt / 9.0) * acc[0];
       const double ry = dir ? 0.0 : (dt / 9.0) * acc[1];
       const double rp = -nu * acc[2];
+      // mass-solve right-hand sides go to the lattice layout
+      const int64_t li = lat_of[i];
       if (mode == CGP_MASS_CONSISTENT) {
         const int nr = chi ? 3 : 2;
-        rhs[(int64_t)i * nr] = rx;
-        rhs[(int64_t)i * nr + 1] = ry;
-        if (chi) rhs[(int64_t)i * nr + 2] = rp;
+        rhs[li * nr] = rx;
+        rhs[li * nr + 1] = ry;
+        if (chi) rhs[li * nr + 2] = rp;
       } else {
         const double ml = 2.0 * M[beg];  // lumped mass: row sum of M
         if (mode == CGP_MASS_LUMPED_P) {
-          rhs[(int64_t)i * 2] = rx;
-          rhs[(int64_t)i * 2 + 1] = ry;
+          rhs[li * 2] = rx;
+          rhs[li * 2 + 1] = ry;
         } else {
           u_out[i] = ui + rx / ml;
           u_out[n + i] = vi + ry / ml;
@@ -1101,10 +1098,10 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __r
 __global__ void __launch_bounds__(kBlock)
 k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restrict__ du,
                const double* p_in, const double* __restrict__ phi, int nr, int write_p,
-               double* __restrict__ u_out, double* p_out) {
+               double* __restrict__ u_out, double* p_out, const int32_t* __restrict__ lat_of) {
   const int64_t n = n32;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int64_t k = (int64_t)i * nr;
+    const int64_t k = (int64_t)lat_of[i] * nr;
     u_out[i] = ut[i] + du[k];
     u_out[n + i] = ut[n + i] + du[k + 1];
     if (write_p) {
@@ -1406,13 +1403,12 @@ int cheb_iterations(double tol) {
   return m < 1 ? 1 : m;
 }
 
-double* launch_cheb(const DLevel& L, const double* Mval, const int32_t* dir_index,
-                    const double* b, int nr,
+double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx) {
   const double lo = 0.5, hi = 2.0;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  const int g = L.ntiles;
+  const int g = (n + kBlock - 1) / kBlock;
   double rho = 1.0 / sigma;
   for (int k = 0; k < iters; ++k) {
     double ca = 0.0, cb = 1.0 / theta;
@@ -1428,9 +1424,9 @@ double* launch_cheb(const DLevel& L, const double* Mval, const int32_t* dir_inde
     hipEvent_t* ev = (timer && k > 0) ? timer(tctx) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (nr == 3)
-      k_cheb<3><<<g, kBlock, 0, s>>>(L, Mval, dir_index, b, xk, xkm, xn, ca, cb, k == 0);
+      k_cheb_lattice<3><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
     else
-      k_cheb<2><<<g, kBlock, 0, s>>>(L, Mval, dir_index, b, xk, xkm, xn, ca, cb, k == 0);
+      k_cheb_lattice<2><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
     if (ev) (void)hipEventRecord(ev[1], s);
   }
   return x[iters % 3];
@@ -1473,16 +1469,16 @@ void launch_prolong(int32_t n_f, const int32_t* pcode, const int32_t* tri_c, int
 void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double* Mval,
                         double dt, double nu, int chi, int mass_mode, const double* phi_f,
                         const double* ut, const double* p_in, double* rhs, double* u_out,
-                        double* p_out, hipStream_t s) {
+                        double* p_out, const int32_t* lat_of, hipStream_t s) {
   k_correct_rhs<<<row_group_grid(L.n), kBlock, 0, s>>>(L, dir_index, Mval, dt, nu, chi, mass_mode,
-                                                       phi_f, ut, p_in, rhs, u_out, p_out);
+                                                       phi_f, ut, p_in, rhs, u_out, p_out, lat_of);
 }
 
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
                          const double* phi_f, int nr, bool write_p, double* u_out,
-                         double* p_out, hipStream_t s) {
+                         double* p_out, const int32_t* lat_of, hipStream_t s) {
   k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, nr,
-                                                        write_p ? 1 : 0, u_out, p_out);
+                                                        write_p ? 1 : 0, u_out, p_out, lat_of);
 }
 
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
