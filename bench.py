@@ -72,7 +72,9 @@ def log(*a):
 
 
 # committed rocprofv3 counter summaries of the timed kernel, per workload
-TRAFFIC_RECORDS = {("tg2049_k3_fp64", "mass_spmv"): "k_cheb3_tg2049_k3_fp64_traffic.md"}
+TRAFFIC_RECORDS = {("tg2049_k3_fp64", "mass_spmv"): "k_cheb_lattice3_tg2049_k3_fp64_traffic.md"}
+# the sources a record's kernel is compiled from (its hash must match)
+TRAFFIC_SOURCES = ("mass.hip", "lattice.hpp")
 
 
 def stored_traffic(workload, kernel):
@@ -83,10 +85,12 @@ def stored_traffic(workload, kernel):
     if not name:
         return None, "no counter summary for this workload and kernel"
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_1812_00185_amd", "csrc", "kernels.hip")
     try:
         text = open(path).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, "paper_1812_00185_amd", "csrc", f), "rb").read())
+        digest = h.hexdigest()
     except OSError as e:
         return None, str(e)
     rec = {}
@@ -94,7 +98,7 @@ def stored_traffic(workload, kernel):
         if line.startswith("    ") and ": " in line:
             k, v = line.strip().split(": ", 1)
             rec[k] = v
-    if rec.get("kernels_hip_sha256") != digest:
+    if rec.get("sources_sha256") != digest:
         return None, "kernels changed since the counters were taken"
     return int(rec["traffic_bytes_per_launch"]), f"profiles/{name}"
 

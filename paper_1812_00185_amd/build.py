@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcgp.so")
 
-SOURCES = ["mesh.cpp", "lattice.cpp", "ndchol.cpp", "kernels.hip", "mpnn.hip", "ndchol.hip", "api.hip"]
+SOURCES = ["mesh.cpp", "lattice.cpp", "ndchol.cpp", "kernels.hip", "mpnn.hip", "ndchol.hip", "mass.hip", "api.hip"]
 ARCH = "gfx950"
 
 
