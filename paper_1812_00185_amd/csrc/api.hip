@@ -349,7 +349,8 @@ int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
                  hipStream_t s) {
   const cgp_problem& P = c->prob;
   cgp::launch_momentum_assemble(c->F, c->dir_index, P.dt, P.nu, u_prev, u, p, u_dir, c->ndir,
-                                f, c->Aval, c->invdA, c->rhs, ut, s, timer(c, CGP_K_MOM_ASSEMBLE));
+                                f, c->Aval, c->invdA, c->rhs, ut,
+                                c->phat, c->shat, s, timer(c, CGP_K_MOM_ASSEMBLE));
   cgp::BicgVecs V{ut, c->r, c->rhat, c->p, c->v, c->phat, c->shat, c->t, c->rhs, c->invdA};
   cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
   Scal out[2];

@@ -57,7 +57,8 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
                               double* Aval, double* invdA, double* rhs, double* x0,
-                              hipStream_t s, hipEvent_t* ev = nullptr);
+                              double* scratch_w, double* scratch_r, hipStream_t s,
+                              hipEvent_t* ev = nullptr);
 
 // ---------------------------------------------------------------- BiCGSTAB (2 rhs)
 struct BicgVecs {

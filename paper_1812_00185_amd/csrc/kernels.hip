@@ -278,12 +278,32 @@ k_coarse_assemble(DLevel L, const uint8_t* __restrict__ nat, double* __restrict_
 // group per row, one lane per off-diagonal slot; Dirichlet rows become
 // identity rows with the boundary value as right-hand side and as initial
 // guess.
+// Per node, the two fields the assembly gathers at neighbours, as pairs:
+// W = 2 U^n - U^{n-1} (convecting velocity) and R = 2 U^n - 1/2 U^{n-1} + dt F
+// (the mass-weighted right-hand-side field), so a neighbour costs two 16-byte
+// loads instead of six 8-byte ones.
+__global__ void k_momentum_fields(int32_t n32, const double* __restrict__ up,
+                                  const double* __restrict__ u, const double* __restrict__ f,
+                                  double dt, double2* __restrict__ W, double2* __restrict__ R) {
+  const int64_t n = n32;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double ux = u[i], uy = u[n + i], px = up[i], py = up[n + i];
+    double rx = 2.0 * ux - 0.5 * px, ry = 2.0 * uy - 0.5 * py;
+    if (f) {
+      rx += dt * f[i];
+      ry += dt * f[n + i];
+    }
+    W[i] = make_double2(2.0 * ux - px, 2.0 * uy - py);
+    R[i] = make_double2(rx, ry);
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
-                    const double* __restrict__ up, const double* __restrict__ u,
+                    const double2* __restrict__ W, const double2* __restrict__ R,
                     const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
-                    const double* __restrict__ f, double* __restrict__ A,
-                    double* __restrict__ invdA, double* __restrict__ rhs,
+                    double* __restrict__ A, double* __restrict__ invdA, double* __restrict__ rhs,
                     double* __restrict__ x0) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
@@ -308,16 +328,16 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
     }
     const double2 pi = L.xy[i];
     const double Pi = p[i];
-    const double uix = u[i], uiy = u[n + i], upix = up[i], upiy = up[n + i];
-    const double wix = 2.0 * uix - upix, wiy = 2.0 * uiy - upiy;
+    const double2 wi = W[i];
+    const double wix = wi.x, wiy = wi.y;
     // dm, dk, dn, rx, ry, gx, gy
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
       const int j = L.col[s];
       const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
       const double2 pj = L.xy[j];
-      const double ujx = u[j], ujy = u[n + j], upjx = up[j], upjy = up[n + j];
-      const double wjx = 2.0 * ujx - upjx, wjy = 2.0 * ujy - upjy;
+      const double2 wj = W[j], rj = R[j];
+      const double wjx = wj.x, wjy = wj.y;
       const double Pj = p[j];
       double m = 0.0, kk = 0.0, nn = 0.0;
 #pragma unroll
@@ -325,7 +345,8 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
         const int k = q == 0 ? sd.x : sd.y;
         if (k < 0) continue;
         const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
-        const double wkx = 2.0 * u[k] - up[k], wky = 2.0 * u[n + k] - up[n + k];
+        const double2 wk = W[k];
+        const double wkx = wk.x, wky = wk.y;
         m += g.area * (1.0 / 12.0);
         kk += (g.bi * g.bj + g.ci * g.cj) / (4.0 * g.area);
         nn += ((2.0 * wix + wjx + wkx) * g.bj + (2.0 * wiy + wjy + wky) * g.cj) * (1.0 / 24.0);
@@ -336,21 +357,13 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       acc[0] += m;
       acc[1] += kk;
       acc[2] += nn;
-      double bx = 2.0 * ujx - 0.5 * upjx, by = 2.0 * ujy - 0.5 * upjy;
-      if (f) {
-        bx += dt * f[j];
-        by += dt * f[n + j];
-      }
-      acc[3] += m * bx;
-      acc[4] += m * by;
+      acc[3] += m * rj.x;
+      acc[4] += m * rj.y;
     }
     group_sum<7>(acc);
     if (lane == 0) {
-      double bxi = 2.0 * uix - 0.5 * upix, byi = 2.0 * uiy - 0.5 * upiy;
-      if (f) {
-        bxi += dt * f[i];
-        byi += dt * f[n + i];
-      }
+      const double2 ri = R[i];
+      const double bxi = ri.x, byi = ri.y;
       const double aii = 1.5 * acc[0] - dtnu * acc[1] - dt * acc[2];
       A[beg] = aii;
       invdA[i] = 1.0 / aii;
@@ -1296,10 +1309,14 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
                               double* Aval, double* invdA, double* rhs, double* x0,
-                              hipStream_t s, hipEvent_t* ev) {
+                              double* scratch_w, double* scratch_r, hipStream_t s,
+                              hipEvent_t* ev) {
+  double2* W = reinterpret_cast<double2*>(scratch_w);
+  double2* R = reinterpret_cast<double2*>(scratch_r);
   if (ev) (void)hipEventRecord(ev[0], s);
+  k_momentum_fields<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L.n, u_prev, u, f, dt, W, R);
   k_momentum_assemble<<<row_group_grid(L.n), kBlock, 0, s>>>(
-      L, dir_index, dt, dt * nu, u_prev, u, p, u_dir, n_dir, f, Aval, invdA, rhs, x0);
+      L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, Aval, invdA, rhs, x0);
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 
