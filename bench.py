@@ -32,6 +32,7 @@ reported beside it in the same JSON line.
 from __future__ import annotations
 
 import argparse
+import copy
 import hashlib
 import json
 import os
@@ -107,6 +108,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# oracle configuration (mass mode, coarse solver) matching each form
+FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg"), "lumped_fp64": ("lumped", "pcg"),
+              "ndchol_fp64": ("consistent", "exact"), "ndchol_lumped_fp64": ("lumped", "exact")}
+
+
 def cpu_baseline(w, g_fine_xy, first_steps):
     """Oracle (as it stands) on one step of the same workload, single thread;
     returns the baseline record and the parity of each form's first GPU step
@@ -126,8 +132,18 @@ def cpu_baseline(w, g_fine_xy, first_steps):
         t_step = time.perf_counter() - t0
     assert np.array_equal(ora.fine_xy, g_fine_xy)
     parity = {"pcg_iters_oracle": r.stats["pcg_iters"]}
+    # each form against the oracle configured like it (mass matrices of
+    # Eqs. 25-27, coarse solver); the operators of the timed oracle are shared
+    refs = {("consistent", "pcg"): r.state}
     for form, (U_g, P_g) in first_steps.items():
-        parity[form] = {"u": rel(U_g, r.state.U), "p": rel(P_g, r.state.P)}
+        mode = FORM_MODES.get(form, ("consistent", "pcg"))
+        if mode not in refs:
+            o2 = copy.copy(ora)
+            o2.mass_mode, o2.coarse_solver = mode
+            refs[mode] = o2.step(st, uD).state
+        ref = refs[mode]
+        parity[form] = {"u": rel(U_g, ref.U), "p": rel(P_g, ref.P),
+                        "oracle": f"mass={mode[0]}, coarse={mode[1]}"}
     dof = 3 * ora.nf
     return {
         "value": dof / t_step, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",

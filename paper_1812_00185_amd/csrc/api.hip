@@ -73,8 +73,9 @@ struct cgp_ctx {
   int ell_w = 0;
   int mom_expect = 0;  // iterations of the last momentum solve (0: unknown)
   int32_t* ell_col = nullptr;
-  double* ell_val = nullptr;
-  float* ell_val32 = nullptr;
+  double* ell_val = nullptr;    // K (factor-preconditioned PCG)
+  double* ell_sval = nullptr;   // K D^-1 (Jacobi PCG, FP64)
+  float* ell_sval32 = nullptr;  // K D^-1 (Jacobi PCG, FP32)
   double *ut = nullptr, *rhs = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr,
          *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
   double* phi_f = nullptr;
@@ -181,7 +182,8 @@ size_t carve(cgp_ctx* c, void* base) {
   }
   c->ell_col = w.take<int32_t>((size_t)c->ell_w * nc);
   c->ell_val = w.take<double>((size_t)c->ell_w * nc);
-  c->ell_val32 = w.take<float>((size_t)c->ell_w * nc);
+  c->ell_sval = w.take<double>((size_t)c->ell_w * nc);
+  c->ell_sval32 = w.take<float>((size_t)c->ell_w * nc);
   c->Dxc = w.take<double>(nnzc);
   c->Dyc = w.take<double>(nnzc);
   c->invdKc = w.take<double>(nc);
@@ -451,7 +453,7 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
     cgp::PcgVecs<double> V{x,          c->cp,       {c->cr2[0], c->cr2[1]},
                            {c->cw2[0], c->cw2[1]}, {c->cs2[0], c->cs2[1]},
                            b,          c->invdKc,   c->Kc,
-                           c->ell_col, c->ell_val,  c->ell_w};
+                           c->ell_col, c->ell_sval, c->ell_w};
     cgp::launch_pcg_init<double>(c->C, V, false, c->scal, c->part, c->nb_c, s);
     Scal out[1];
     rc = drive(c, c->scal, 1, P.max_iter + 1, 32, true,
@@ -503,7 +505,7 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
       cgp::PcgVecs<float> V{c->cx32,     c->cp32,       {c->cr32[0], c->cr32[1]},
                             {c->cw32[0], c->cw32[1]}, {c->cs32[0], c->cs32[1]},
                             c->cb32,     c->invdKc32,   c->Kc32,
-                            c->ell_col,  c->ell_val32,  c->ell_w};
+                            c->ell_col,  c->ell_sval32, c->ell_w};
       cgp::launch_pcg_init<float>(c->C, V, true, c->scal, c->part, c->nb_c, s);
       Scal out[1];
       const int budget = std::max(1, P.max_iter - inner_total);
@@ -778,7 +780,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   cgp::launch_mass_assemble(c->F, c->Mval, s);
   cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
                               c->invdKc32, c->lumped_c, s);
-  cgp::launch_make_ell(c->C, c->Kc, c->Kc32, c->ell_w, c->ell_col, c->ell_val, c->ell_val32, s);
+  cgp::launch_make_ell(c->C, c->Kc, c->invdKc, c->ell_w, c->ell_col, c->ell_val, c->ell_sval,
+                       c->ell_sval32, s);
   cgp::net::launch_edge_features(c->C, c->hbar, c->net, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -87,7 +87,7 @@ struct PcgVecs {
   const T* val;       // CSR values (set-up kernels)
   // fixed-width (ELL) copy of the matrix for the iteration kernel, column
   // major: entry k of row i at [k * n + i]; width a multiple of kEllPad,
-  // short rows padded with (i, 0)
+  // short rows padded with (i, 0); values scaled by column, K_ij / K_jj
   const int32_t* ell_col;
   const T* ell_val;
   int32_t ell_w;
@@ -95,9 +95,11 @@ struct PcgVecs {
 template <typename T>
 void launch_pcg_init(const DLevel& L, const PcgVecs<T>& V, bool zero_x0, Scal* sc, double* part,
                      int nb, hipStream_t s);
-// ELL copy (see PcgVecs) of a CSR matrix's FP64 and FP32 values
-void launch_make_ell(const DLevel& L, const double* val, const float* val32, int w,
-                     int32_t* ell_col, double* ell_val, float* ell_val32, hipStream_t s);
+// ELL copies (see PcgVecs) of a CSR matrix: its FP64 values, and its values
+// scaled by column (K D^-1, with invd = 1 / diag) in FP64 and FP32
+void launch_make_ell(const DLevel& L, const double* val, const double* invd, int w,
+                     int32_t* ell_col, double* ell_val, double* ell_sval, float* ell_sval32,
+                     hipStream_t s);
 // `ev`, when not null, is a pair of events recorded around the iteration kernel.
 template <typename T>
 void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* part, int nb, int it,

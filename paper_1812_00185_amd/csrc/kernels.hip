@@ -714,7 +714,7 @@ k_pcg_iter(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, doub
   double g = 0.0, dl = 0.0, rr = 0.0;
   const int first_row = blockIdx.x * kBlock + threadIdx.x;
   T xr = T(0), pr = T(0), rv = T(0), wv = T(0), sv = T(0), dv = T(0);
-  T gv[kRowBatch], gr[kRowBatch], gw[kRowBatch], gs[kRowBatch], gd[kRowBatch];
+  T gv[kRowBatch], gr[kRowBatch], gw[kRowBatch], gs[kRowBatch];
   // Loads carry no per-entry conditions, so that all of a batch's index loads
   // are in flight together and then all of its gathers (a condition per entry
   // splits the batch into blocks that each wait for their own index).  The
@@ -741,7 +741,6 @@ k_pcg_iter(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, doub
       const int c = cix[u];
       gr[u] = ro[c];
       gw[u] = wo[c];
-      gd[u] = dinv[c];
       gs[u] = so[c];
     }
   };
@@ -804,7 +803,7 @@ k_pcg_iter(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, doub
 #pragma unroll
       for (int u = 0; u < kRowBatch; ++u) {
         const T snc = start ? gw[u] : gw[u] + beta * gs[u];
-        acc += gv[u] * (gd[u] * (gr[u] - alpha * snc));
+        acc += gv[u] * (gr[u] - alpha * snc);  // ELL values hold K_ij / K_jj
       }
     }
     V.x[row] = xr + alpha * pnw;
@@ -825,17 +824,25 @@ k_pcg_iter(int32_t n, PcgVecs<T> V, Scal* sc, double* part, int nb, int it, doub
 
 // ELL copy of a CSR matrix (row order kept: diagonal first, then columns
 // ascending; padding (i, 0))
+// ELL copies of a CSR matrix K: column indices, K in FP64, and K D^-1 (each
+// column scaled by 1 / K_jj, so that products with z = D^-1 r need no
+// gather of the diagonal) in FP64 and FP32.
 __global__ void k_make_ell(DLevel L, const double* __restrict__ val,
-                           const float* __restrict__ val32, int w, int32_t* __restrict__ ecol,
-                           double* __restrict__ ev, float* __restrict__ ev32) {
+                           const double* __restrict__ invd, int w, int32_t* __restrict__ ecol,
+                           double* __restrict__ ev, double* __restrict__ evs,
+                           float* __restrict__ evs32) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L.n; i += gridDim.x * blockDim.x) {
     const int beg = L.rowptr[i], len = L.rowptr[i + 1] - beg;
     for (int k = 0; k < w; ++k) {
       const int64_t e = (int64_t)k * L.n + i;
       const bool in = k < len;
-      ecol[e] = in ? L.col[beg + k] : i;
-      ev[e] = in ? val[beg + k] : 0.0;
-      ev32[e] = in ? val32[beg + k] : 0.0f;
+      const int c = in ? L.col[beg + k] : i;
+      const double v = in ? val[beg + k] : 0.0;
+      const double vs = v * invd[c];
+      ecol[e] = c;
+      ev[e] = v;
+      evs[e] = vs;
+      evs32[e] = (float)vs;
     }
   }
 }
@@ -1354,10 +1361,11 @@ void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* par
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 
-void launch_make_ell(const DLevel& L, const double* val, const float* val32, int w,
-                     int32_t* ell_col, double* ell_val, float* ell_val32, hipStream_t s) {
-  k_make_ell<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, val, val32, w, ell_col, ell_val,
-                                                       ell_val32);
+void launch_make_ell(const DLevel& L, const double* val, const double* invd, int w,
+                     int32_t* ell_col, double* ell_val, double* ell_sval, float* ell_sval32,
+                     hipStream_t s) {
+  k_make_ell<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, val, invd, w, ell_col, ell_val, ell_sval,
+                                                       ell_sval32);
 }
 
 template void launch_pcg_init<double>(const DLevel&, const PcgVecs<double>&, bool, Scal*, double*,
