@@ -29,6 +29,12 @@ to (U^{n+1}, P^{n+1}, Phi_c^{n+1}):
      chi = 1 solves Eq. 26 with the consistent mass matrix:
        M dp = -nu D U~,  P^{n+1} = P^n + Phi_f + dp.
 
+Non-incremental form (scheme='nonincremental', the "NCGP" the paper compares
+with, Sect. 2.3): the momentum equation has no pressure term, the coarse
+Poisson problem of Eq. 23 is solved for the pressure itself (same right-hand
+side and scaling), the velocity correction is Eq. 25, and P^{n+1} = Phi_f;
+it has no rotational form (chi = 0).
+
 Readings where the paper is silent:
   * the linear solvers are Jacobi-PCG (symmetric) and Jacobi-BiCGSTAB
     (momentum) with ||r|| <= tol ||b||; the momentum solve starts from w with
@@ -92,9 +98,18 @@ MASS_MODES = ("consistent", "lumped_p", "lumped")
 class OracleCGP:
     def __init__(self, coarse_mesh, levels, dt, nu, chi, pcg_tol=1e-8,
                  mom_tol=1e-12, mass_tol=1e-12, max_iter=20000, restrict="galerkin",
-                 mass="consistent", coarse="pcg"):
+                 mass="consistent", coarse="pcg", scheme="incremental"):
         if restrict not in ("galerkin", "inject"):
             raise ValueError("restrict must be 'galerkin' or 'inject'")
+        if scheme not in ("incremental", "nonincremental"):
+            raise ValueError("scheme must be 'incremental' or 'nonincremental'")
+        if scheme == "nonincremental" and chi != 0:
+            raise ValueError("the non-incremental scheme has no rotational form (chi = 0)")
+        # 'incremental': the paper's method (Eqs. 21-26); 'nonincremental': the
+        # CGP form it is compared with (Sect. 2.3): no pressure in the momentum
+        # equation, the coarse Poisson problem solved for the pressure itself,
+        # P^{n+1} = Phi_f
+        self.scheme = scheme
         if coarse not in ("pcg", "exact"):
             raise ValueError("coarse must be 'pcg' or 'exact'")
         # 'pcg': Jacobi-PCG to pcg_tol from the guess; 'exact': the exact
@@ -147,7 +162,9 @@ class OracleCGP:
         GP = self.F.grad(P)
         rhs = np.empty((2, self.nf))
         for d in range(2):
-            r = -dt * GP[d] + 2.0 * (M @ U[d]) - 0.5 * (M @ U_prev[d])
+            r = 2.0 * (M @ U[d]) - 0.5 * (M @ U_prev[d])
+            if self.scheme == "incremental":
+                r = r - dt * GP[d]
             if F is not None:
                 r = r + dt * (M @ F[d])
             r[self.dir] = uD[d]
@@ -234,6 +251,8 @@ class OracleCGP:
         """chi = 0: P + phi_f (Eq. 16, algebraic form).  chi = 1: P + phi_f + dp
         with M dp = -nu D U~ (Eq. 26 / 20, consistent M) or dp = M_L^-1 (-nu D U~)
         with the lumped M_L (Eq. 27)."""
+        if self.scheme == "nonincremental":
+            return phi_f.copy(), 0
         if self.chi == 0:
             return P + phi_f, 0
         rhs = -self.nu * self.F.div(Ut)
@@ -272,7 +291,7 @@ def build(workload):
     return OracleCGP(workload.coarse_mesh(), workload.levels, workload.dt, workload.nu,
                      workload.chi, workload.pcg_tol, workload.mom_tol, workload.mass_tol,
                      workload.max_iter, workload.restrict, workload.mass,
-                     "exact" if workload.precond == "ndchol" else "pcg")
+                     "exact" if workload.precond == "ndchol" else "pcg", workload.scheme)
 
 
 def run(workload, steps=None, record=None, F=None):

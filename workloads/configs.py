@@ -38,6 +38,7 @@ class Workload:
     restrict: str = "galerkin"     # 'galerkin' | 'inject'
     mass: str = "consistent"       # 'consistent' | 'lumped_p' (Eq. 27) | 'lumped'
     precond: str = "jacobi"        # coarse PCG preconditioner: 'jacobi' | 'ndchol' (exact factor)
+    scheme: str = "incremental"    # 'incremental' (the method) | 'nonincremental' (NCGP, chi = 0)
     lid_speed: float = 1.0
     channel_h: float = 0.0082
     seed: int = 0
