@@ -15,6 +15,8 @@ run over the same trajectory:
   ndchol_fp64    FP64 PCG preconditioned by the nested-dissection Cholesky
                  factor of K_c (one iteration to rounding level)
   ndchol_lumped_fp64  ndchol_fp64 with lumped mass in Eqs. 25 and 27
+  ncgp_fp64      the non-incremental CGP form the paper compares with
+                 (no pressure in the momentum equation, P = Phi_f; chi = 0)
 and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
@@ -108,9 +110,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-# oracle configuration (mass mode, coarse solver) matching each form
-FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg"), "lumped_fp64": ("lumped", "pcg"),
-              "ndchol_fp64": ("consistent", "exact"), "ndchol_lumped_fp64": ("lumped", "exact")}
+# oracle configuration (mass mode, coarse solver, scheme) matching each form
+FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
+              "lumped_fp64": ("lumped", "pcg", "incremental"),
+              "ndchol_fp64": ("consistent", "exact", "incremental"),
+              "ndchol_lumped_fp64": ("lumped", "exact", "incremental"),
+              "ncgp_fp64": ("consistent", "pcg", "nonincremental")}
 
 
 def cpu_baseline(w, g_fine_xy, first_steps):
@@ -134,16 +139,18 @@ def cpu_baseline(w, g_fine_xy, first_steps):
     parity = {"pcg_iters_oracle": r.stats["pcg_iters"]}
     # each form against the oracle configured like it (mass matrices of
     # Eqs. 25-27, coarse solver); the operators of the timed oracle are shared
-    refs = {("consistent", "pcg"): r.state}
+    refs = {("consistent", "pcg", "incremental"): r.state}
     for form, (U_g, P_g) in first_steps.items():
-        mode = FORM_MODES.get(form, ("consistent", "pcg"))
+        mode = FORM_MODES.get(form, ("consistent", "pcg", "incremental"))
         if mode not in refs:
             o2 = copy.copy(ora)
-            o2.mass_mode, o2.coarse_solver = mode
+            o2.mass_mode, o2.coarse_solver, o2.scheme = mode
+            if o2.scheme == "nonincremental":
+                o2.chi = 0
             refs[mode] = o2.step(st, uD).state
         ref = refs[mode]
         parity[form] = {"u": rel(U_g, ref.U), "p": rel(P_g, ref.P),
-                        "oracle": f"mass={mode[0]}, coarse={mode[1]}"}
+                        "oracle": f"mass={mode[0]}, coarse={mode[1]}, scheme={mode[2]}"}
     dof = 3 * ora.nf
     return {
         "value": dof / t_step, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
@@ -193,7 +200,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
-                            "ndchol_fp64,ndchol_lumped_fp64")
+                            "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain FP64 form only: no training, no learned forms or legs")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -242,6 +249,9 @@ def main():
         if form in forms:
             solvers[form] = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64",
                                 mass=mass, precond=pre, **kw)
+    if "ncgp_fp64" in forms:
+        solvers["ncgp_fp64"] = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64",
+                                   scheme="nonincremental", **{**kw, "chi": 0})
     torch.cuda.synchronize()
     log(f"[bench] {w.name}: N_f={g.nf} N_c={g.nc} nnz_f={g.sizes.nnz_fine} "
         f"set-up {time.perf_counter() - t0:.1f} s")
@@ -264,7 +274,7 @@ def main():
             f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
               "lumped_p_fp64": None, "lumped_fp64": None, "ndchol_fp64": None,
-              "ndchol_lumped_fp64": None}
+              "ndchol_lumped_fp64": None, "ncgp_fp64": None}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]

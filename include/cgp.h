@@ -70,6 +70,13 @@ extern "C" {
 #define CGP_PRECOND_JACOBI 0 /* diagonal: single-reduction PCG, FP64 or mixed   */
 #define CGP_PRECOND_NDCHOL 1 /* nested-dissection Cholesky factor of K_c (FP64) */
 
+/* projection scheme */
+#define CGP_SCHEME_INCREMENTAL 0    /* the method: Eqs. 21-26 (standard or rotational) */
+#define CGP_SCHEME_NONINCREMENTAL 1 /* the non-incremental CGP form the paper compares
+                                       with (Sect. 2.3): no pressure in the momentum
+                                       equation, Eq. 23 solved for the pressure itself,
+                                       P^{n+1} = Phi_f; chi must be 0 */
+
 /* reading of the coarse divergence in Eq. 23 (Sect. 2.2) */
 #define CGP_RESTRICT_GALERKIN 0 /* coarse shape functions against the fine velocity */
 #define CGP_RESTRICT_INJECT 1   /* inject U~ at the coarse nodes (Eq. 22), then D_c */
@@ -123,6 +130,7 @@ typedef struct cgp_problem {
                             nodes the last coarse node N_c - 1 is pinned, as
                             K_c is singular), computed once on the host in
                             cgp_assemble; requires precision = CGP_FP64      */
+  int32_t scheme;         /* CGP_SCHEME_INCREMENTAL or CGP_SCHEME_NONINCREMENTAL */
 } cgp_problem;
 
 typedef struct cgp_sizes {
@@ -199,7 +207,8 @@ int cgp_assemble(cgp_ctx* ctx, void* workspace, size_t bytes, void* stream);
  * by right-Jacobi-preconditioned BiCGSTAB from U~ = w (u_dir at the
  * Dirichlet nodes), stopping when
  * ||r|| <= mom_tol ||rhs||.  u_prev, u, u_tilde: device [2][N_f]; p device
- * [N_f]; u_dir device [2][n_dirichlet]; f device [2][N_f] or NULL (no
+ * [N_f] (not read, and may be NULL, with CGP_SCHEME_NONINCREMENTAL, whose
+ * momentum equation has no pressure term); u_dir device [2][n_dirichlet]; f device [2][N_f] or NULL (no
  * forcing).  u_tilde must not alias the inputs.  stats may be NULL; when
  * given, the call synchronises `stream` to fill it. */
 int cgp_momentum(cgp_ctx* ctx, const double* u_prev, const double* u, const double* p,
@@ -239,7 +248,8 @@ int cgp_prolong(cgp_ctx* ctx, const double* phi_c, double* phi_f, void* stream);
  * p_out = p_in + phi_f + dp.  The mass solves run together as Chebyshev
  * iteration on [1/2, 2] (the spectrum of the Jacobi-scaled P1 mass matrix),
  * with the iteration count fixed by mass_tol (27 for 1e-12); stats report
- * that count and its a-priori error bound.  p_out may alias p_in.
+ * that count and its a-priori error bound.  With CGP_SCHEME_NONINCREMENTAL
+ * p_out = phi_f (p_in not read, may be NULL).  p_out may alias p_in.
  * u_tilde, u_out device [2][N_f]; phi_f, p_in, p_out device [N_f].  stats:
  * [3] (u, v, rotational) or NULL. */
 int cgp_correct(cgp_ctx* ctx, const double* u_tilde, const double* phi_f, const double* p_in,

@@ -28,6 +28,7 @@ CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
 CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED = 0, 1, 2
 CGP_PRECOND_JACOBI, CGP_PRECOND_NDCHOL = 0, 1
+CGP_SCHEME_INCREMENTAL, CGP_SCHEME_NONINCREMENTAL = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -45,7 +46,8 @@ class Problem(C.Structure):
                 ("inner_tol", C.c_double), ("mom_tol", C.c_double), ("mass_tol", C.c_double),
                 ("max_iter", C.c_int32), ("mom_max_iter", C.c_int32),
                 ("mass_max_iter", C.c_int32), ("max_outer", C.c_int32),
-                ("mass_mode", C.c_int32), ("coarse_precond", C.c_int32)]
+                ("mass_mode", C.c_int32), ("coarse_precond", C.c_int32),
+                ("scheme", C.c_int32)]
 
 
 class NdcholInfo(C.Structure):

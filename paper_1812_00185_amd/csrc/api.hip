@@ -623,6 +623,10 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     return fail(CGP_ERR_INVALID, "unknown mass_mode");
   if (prob->coarse_precond != CGP_PRECOND_JACOBI && prob->coarse_precond != CGP_PRECOND_NDCHOL)
     return fail(CGP_ERR_INVALID, "unknown coarse_precond");
+  if (prob->scheme != CGP_SCHEME_INCREMENTAL && prob->scheme != CGP_SCHEME_NONINCREMENTAL)
+    return fail(CGP_ERR_INVALID, "unknown scheme");
+  if (prob->scheme == CGP_SCHEME_NONINCREMENTAL && prob->chi != 0)
+    return fail(CGP_ERR_INVALID, "the non-incremental scheme has no rotational form (chi = 0)");
   if (prob->coarse_precond == CGP_PRECOND_NDCHOL && prob->precision != CGP_FP64)
     return fail(CGP_ERR_INVALID, "CGP_PRECOND_NDCHOL requires precision CGP_FP64");
   cgp::Mesh cm;
@@ -823,11 +827,12 @@ int cgp_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
                  const double* u_dir, const double* f, double* u_tilde, cgp_solve_stats st[2],
                  void* stream) {
   if (int rc = check_ready(c)) return rc;
-  if (!u_prev || !u || !p || !u_tilde || (c->ndir && !u_dir))
+  const bool noninc = c->prob.scheme == CGP_SCHEME_NONINCREMENTAL;
+  if (!u_prev || !u || (!p && !noninc) || !u_tilde || (c->ndir && !u_dir))
     return fail(CGP_ERR_INVALID, "null device pointer");
   if (u_tilde == u || u_tilde == u_prev) return fail(CGP_ERR_INVALID, "u_tilde aliases an input");
   hipStream_t s = as_stream(stream);
-  int rc = run_momentum(c, u_prev, u, p, u_dir, f, u_tilde, st, s);
+  int rc = run_momentum(c, u_prev, u, noninc ? nullptr : p, u_dir, f, u_tilde, st, s);
   HIPCHK(hipGetLastError());
   return rc;
 }
@@ -860,9 +865,11 @@ int cgp_prolong(cgp_ctx* c, const double* phic, double* phif, void* stream) {
 int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
                 double* u_out, double* p_out, cgp_solve_stats st[3], void* stream) {
   if (int rc = check_ready(c)) return rc;
-  if (!ut || !phi_f || !p_in || !u_out || !p_out) return fail(CGP_ERR_INVALID, "null device pointer");
+  const bool noninc = c->prob.scheme == CGP_SCHEME_NONINCREMENTAL;
+  if (!ut || !phi_f || (!p_in && !noninc) || !u_out || !p_out)
+    return fail(CGP_ERR_INVALID, "null device pointer");
   if (u_out == ut) return fail(CGP_ERR_INVALID, "u_out aliases u_tilde");
-  int rc = run_correct(c, ut, phi_f, p_in, u_out, p_out, st, as_stream(stream));
+  int rc = run_correct(c, ut, phi_f, noninc ? nullptr : p_in, u_out, p_out, st, as_stream(stream));
   HIPCHK(hipGetLastError());
   return rc;
 }
@@ -962,7 +969,8 @@ int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
   hipStream_t s = as_stream(stream);
   cgp_step_stats local{};
   cgp_step_stats* T = st ? st : &local;
-  int rc = run_momentum(c, S->u_prev, S->u, S->p, u_dir, f, c->ut, T->momentum, s);
+  const bool noninc = c->prob.scheme == CGP_SCHEME_NONINCREMENTAL;
+  int rc = run_momentum(c, S->u_prev, S->u, noninc ? nullptr : S->p, u_dir, f, c->ut, T->momentum, s);
   if (rc < 0) return rc;
   run_restrict(c, c->ut, c->bc, s);
   double* phi_new = S->phi_hist[3];
@@ -984,7 +992,7 @@ int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
   if (rc < 0) return rc;
   cgp::launch_prolong(c->nf, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f, s);
   cgp_solve_stats cs[3];
-  rc = worst(rc, run_correct(c, c->ut, c->phi_f, S->p, S->u_prev, S->p, cs, s));
+  rc = worst(rc, run_correct(c, c->ut, c->phi_f, noninc ? nullptr : S->p, S->u_prev, S->p, cs, s));
   if (rc < 0) return rc;
   T->mass[0] = cs[0];
   T->mass[1] = cs[1];

@@ -327,7 +327,8 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       continue;
     }
     const double2 pi = L.xy[i];
-    const double Pi = p[i];
+    // p == nullptr: no pressure term (the non-incremental scheme)
+    const double Pi = p ? p[i] : 0.0;
     const double2 wi = W[i];
     const double wix = wi.x, wiy = wi.y;
     // dm, dk, dn, rx, ry, gx, gy
@@ -338,7 +339,7 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       const double2 pj = L.xy[j];
       const double2 wj = W[j], rj = R[j];
       const double wjx = wj.x, wjy = wj.y;
-      const double Pj = p[j];
+      const double Pj = p ? p[j] : 0.0;
       double m = 0.0, kk = 0.0, nn = 0.0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -1064,7 +1065,9 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __r
           u_out[i] = ui + rx / ml;
           u_out[n + i] = vi + ry / ml;
         }
-        p_out[i] = chi ? p_in[i] + phii + rp / ml : p_in[i] + phii;
+        // p_in == nullptr: the increment is the pressure (non-incremental)
+        const double pold = p_in ? p_in[i] : 0.0;
+        p_out[i] = chi ? pold + phii + rp / ml : pold + phii;
       }
     }
   }
@@ -1082,7 +1085,7 @@ k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restr
     u_out[i] = ut[i] + du[k];
     u_out[n + i] = ut[n + i] + du[k + 1];
     if (write_p) {
-      const double pv = p_in[i] + phi[i];
+      const double pv = (p_in ? p_in[i] : 0.0) + phi[i];  // p_in == nullptr: P = phi
       p_out[i] = nr == 3 ? pv + du[k + 2] : pv;
     }
   }

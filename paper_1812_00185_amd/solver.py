@@ -38,7 +38,7 @@ class CGP:
                  inner_tol: float = 1e-5, mom_tol: float = 1e-12, mass_tol: float = 1e-12,
                  max_iter: int = 20000, mom_max_iter: int = 1000, mass_max_iter: int = 1000,
                  max_outer: int = 20, mass: str = "consistent", precond: str = "jacobi",
-                 device="cuda:0"):
+                 scheme: str = "incremental", device="cuda:0"):
         import torch
 
         self.lib = N.load()
@@ -58,9 +58,11 @@ class CGP:
         mmode = {"consistent": N.CGP_MASS_CONSISTENT, "lumped_p": N.CGP_MASS_LUMPED_P,
                  "lumped": N.CGP_MASS_LUMPED}[mass]
         pmode = {"jacobi": N.CGP_PRECOND_JACOBI, "ndchol": N.CGP_PRECOND_NDCHOL}[precond]
+        smode = {"incremental": N.CGP_SCHEME_INCREMENTAL,
+                 "nonincremental": N.CGP_SCHEME_NONINCREMENTAL}[scheme]
         self.problem = N.Problem(mesh, levels, chi, prec, rmode, dt, nu, pcg_tol, inner_tol,
                                  mom_tol, mass_tol, max_iter, mom_max_iter, mass_max_iter,
-                                 max_outer, mmode, pmode)
+                                 max_outer, mmode, pmode, smode)
         ctx = C.c_void_p()
         N.check(self.lib.cgp_create(C.byref(self.problem), C.byref(ctx)))
         self.ctx = ctx

@@ -38,7 +38,7 @@ def make(w, **kw):
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
             precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
             pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol,
-            max_iter=w.max_iter, mass=w.mass, precond=w.precond, **kw)
+            max_iter=w.max_iter, mass=w.mass, precond=w.precond, scheme=w.scheme, **kw)
     o = build_oracle(w)
     return g, o
 
@@ -464,3 +464,36 @@ def test_not_converged_and_nan_status():
     with pytest.raises(N.CGPError) as e:
         g.pcg_solve(bad, g.zeros(g.nc))
     assert e.value.code == N.CGP_ERR_NAN
+
+
+# ----------------------------------------------------------------- non-incremental form
+@pytest.mark.parametrize("name,wf,steps", [
+    ("tg_k1", lambda: tg(9, 1), 20),
+    ("cavity_k2", lambda: cavity(17, 2), 20),
+    ("channel_k1", lambda: channel(1, 0.05), 10),
+    ("jobelin_disc_k2", lambda: get_workload("jobelin_disc_chi0"), 10),
+])
+def test_nonincremental_trajectories(name, wf, steps, monkeypatch):
+    """The non-incremental CGP form (no pressure in the momentum equation,
+    P^{n+1} = Phi_f) against the oracle's, step by step, within 1e-10 or 10x
+    the oracle's own rounding sensitivity where the trajectory is
+    ill-conditioned (the channel); P is the prolonged coarse solution
+    exactly."""
+    w = wf().with_(scheme="nonincremental", chi=0)
+    g, o = make(w)
+    Um, U0, P0 = w.initial_fields(o.fine_xy)
+    so, sg = o.initial_state(Um, U0, P0), g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    worst = 0.0
+    for n in range(steps):
+        t = (n + 1) * w.dt
+        uD, F = w.dirichlet_values(xyd, t), w.forcing(o.fine_xy, t)
+        so = o.step(so, uD, F).state
+        st = g.step(sg, g.to_device(uD), f=None if F is None else g.to_device(F), stats=True)
+        assert st["poisson"]["converged"]
+        worst = max(worst, rel(np_(sg.U), so.U), rel(np_(sg.P), so.P))
+    assert np.array_equal(np_(sg.P), np_(g.prolong(sg.phi_hist[0])))
+    sens = oracle_sensitivity(w, steps, monkeypatch) if worst > TOL64 else 0.0
+    print(f"[result] non-incremental {name}: worst relative L2 over {steps} steps {worst:.3e}, "
+          f"oracle self-sensitivity {sens:.3e}", flush=True)
+    assert worst <= max(TOL64, 10 * sens)

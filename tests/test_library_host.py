@@ -54,12 +54,12 @@ def _create(lib, mesh, levels, **kw):
                be.ctypes.data_as(C.POINTER(C.c_int32)), bt.ctypes.data_as(C.POINTER(C.c_int32)))
     p = dict(chi=0, precision=0, restrict_mode=0, dt=1e-3, nu=1e-2, pcg_tol=1e-8, inner_tol=1e-5,
              mom_tol=1e-12, mass_tol=1e-12, max_iter=100, mom_max_iter=100, mass_max_iter=100,
-             max_outer=5, mass_mode=0, coarse_precond=0)
+             max_outer=5, mass_mode=0, coarse_precond=0, scheme=0)
     p.update(kw)
     prob = N.Problem(m, levels, p["chi"], p["precision"], p["restrict_mode"], p["dt"], p["nu"],
                      p["pcg_tol"], p["inner_tol"], p["mom_tol"], p["mass_tol"], p["max_iter"],
                      p["mom_max_iter"], p["mass_max_iter"], p["max_outer"], p["mass_mode"],
-                     p["coarse_precond"])
+                     p["coarse_precond"], p["scheme"])
     ctx = C.c_void_p()
     rc = lib.cgp_create(C.byref(prob), C.byref(ctx))
     return rc, ctx
@@ -131,6 +131,12 @@ def test_mesh_errors(lib):
     assert _create(lib, base, 1, dt=0.0)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, chi=2)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, mass_mode=3)[0] == N.CGP_ERR_INVALID
+    assert _create(lib, base, 1, scheme=2)[0] == N.CGP_ERR_INVALID
+    assert _create(lib, base, 1, scheme=1, chi=1)[0] == N.CGP_ERR_INVALID
+    assert b"rotational" in lib.cgp_last_error()
+    rc, ctx = _create(lib, base, 1, scheme=1)
+    assert rc == 0
+    lib.cgp_destroy(ctx)
     for mode in (N.CGP_MASS_LUMPED_P, N.CGP_MASS_LUMPED):
         rc, ctx = _create(lib, base, 1, chi=1, mass_mode=mode)
         assert rc == 0
