@@ -891,23 +891,28 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const i
     xl[L.lat_of[i]] = x[i];
     node[L.lat_of[i]] = i;
   }
-  bool in_range = true;
-  for (int32_t l = 0; l < n; ++l) {
-    double yy[1], dg;
-    cgp::lat_apply<1>(v, l,
-                      [&](int32_t k, int) {
-                        if (k < 0 || k >= n) {
-                          in_range = false;
-                          return 0.0;
-                        }
-                        return xl[k];
-                      },
-                      yy, dg);
-    y[node[l]] = yy[0];
-    diag[node[l]] = dg;
-    if (cgp::lat_diag(v, l) != dg) return fail(CGP_ERR_INVALID, "lattice diagonals disagree");
-  }
+  bool in_range = true, diag_ok = true;
+  const bool known = cgp::lat_dispatch(v.m, [&](auto lat) {
+    constexpr int M = decltype(lat)::kM;
+    for (int32_t l = 0; l < n; ++l) {
+      double yy[1], dg;
+      cgp::lat_apply<1, M>(v, l,
+                           [&](int32_t k, int) {
+                             if (k < 0 || k >= n) {
+                               in_range = false;
+                               return 0.0;
+                             }
+                             return xl[k];
+                           },
+                           yy, dg);
+      y[node[l]] = yy[0];
+      diag[node[l]] = dg;
+      if (cgp::lat_diag(v, l) != dg) diag_ok = false;
+    }
+  });
+  if (!known) return fail(CGP_ERR_INVALID, "unsupported lattice size");
   if (!in_range) return fail(CGP_ERR_INVALID, "lattice stencil index out of range");
+  if (!diag_ok) return fail(CGP_ERR_INVALID, "lattice diagonals disagree");
   return CGP_OK;
 }
 

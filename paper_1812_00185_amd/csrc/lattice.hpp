@@ -78,22 +78,106 @@ CGP_HD inline int32_t lat_index(const LatDev& L, int32_t T, int32_t a, int32_t b
   return L.EB + (e >> 1) * (m - 1) + (t - 1);
 }
 
+// Index arithmetic with the lattice size m = M fixed at compile time (M in
+// {1, 2, 4, 8}): constant divisions, an unrolled row decode, and stencil
+// indices computed from a triangle's edge codes and vertices held in
+// registers (LatTri), so that a node's neighbours cost no dependent loads.
+struct LatTri {
+  int32_t te[3], tv[3];
+};
+
+template <int M>
+struct Lat {
+  static constexpr int32_t kM = M;
+  static constexpr int32_t NI = (M - 1) * (M - 2) / 2;  // interior nodes per triangle
+
+  CGP_HD static LatTri tri(const LatDev& L, int32_t T) {
+    LatTri t;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      t.te[j] = L.tri_e[3 * T + j];
+      t.tv[j] = L.tri_v[3 * T + j];
+    }
+    return t;
+  }
+
+  // node of local edge code e at p steps from the edge's first vertex v_j
+  CGP_HD static int32_t edge_pt(const LatDev& L, int32_t e, int32_t p) {
+    const int32_t t = (e & 1) ? M - p : p;
+    return L.EB + (e >> 1) * (M - 1) + (t - 1);
+  }
+
+  // lattice index of point (a, b) of T (0 <= a, b; a + b <= M)
+  CGP_HD static int32_t index(const LatDev& L, int32_t T, const LatTri& t, int32_t a, int32_t b) {
+    if (a >= 1 && b >= 1 && a + b <= M - 1)
+      return T * NI + ((a - 1) * (M - 1) - ((a - 1) * a) / 2) + (b - 1);
+    if (b == 0) return a == 0 ? L.VB + t.tv[0] : (a == M ? L.VB + t.tv[1] : edge_pt(L, t.te[0], a));
+    if (a + b == M) return b == M ? L.VB + t.tv[2] : edge_pt(L, t.te[1], b);
+    return edge_pt(L, t.te[2], M - b);  // a == 0, 0 < b < M
+  }
+
+  // the seven-point stencil of the interior node l = (a, b) of T: nb[0] = l,
+  // then (a+1, b), (a, b+1), (a-1, b), (a, b-1), (a+1, b-1), (a-1, b+1).
+  // Each neighbour is interior (a fixed offset in the row layout) or one
+  // known point of an edge of T, never a vertex: one select each.
+  CGP_HD static void interior_nbrs(const LatDev& L, int32_t l, int32_t a, int32_t b,
+                                   const LatTri& t, int32_t (&nb)[7]) {
+    const int32_t up = M - 1 - a, dn = M - a;  // row offsets to rows a + 1 and a - 1
+    const bool in_hi = a + b + 1 <= M - 1;
+    nb[0] = l;
+    nb[1] = in_hi ? l + up : edge_pt(L, t.te[1], b);
+    nb[2] = in_hi ? l + 1 : edge_pt(L, t.te[1], b + 1);
+    nb[3] = a >= 2 ? l - dn : edge_pt(L, t.te[2], M - b);
+    nb[4] = b >= 2 ? l - 1 : edge_pt(L, t.te[0], a);
+    nb[5] = b >= 2 ? l + up - 1 : edge_pt(L, t.te[0], a + 1);
+    nb[6] = a >= 2 ? l - dn + 1 : edge_pt(L, t.te[2], M - b - 1);
+  }
+
+  // triangle and point of an interior node l < EB
+  CGP_HD static void interior(int32_t l, int32_t& T, int32_t& a, int32_t& b) {
+    constexpr int32_t D = NI > 0 ? NI : 1;
+    T = l / D;
+    int32_t r = l - T * D;
+    a = 1;
+#pragma unroll
+    for (int32_t k = 1; k <= M - 3; ++k) {
+      const int32_t len = M - 1 - k;  // length of row k
+      const bool next = a == k && r >= len;
+      r = next ? r - len : r;
+      a = next ? k + 1 : a;
+    }
+    b = r + 1;
+  }
+
+  // coarse edge and steps from its lower end of an edge node EB <= l < VB
+  CGP_HD static void edge(const LatDev& L, int32_t l, int32_t& E, int32_t& t) {
+    constexpr int32_t D = M > 1 ? M - 1 : 1;
+    E = (l - L.EB) / D;
+    t = (l - L.EB) - E * D + 1;
+  }
+
+  // point (a, b) in T of the node at t steps from the lower end of T's local
+  // edge j
+  CGP_HD static void edge_point(const LatTri& tr, int32_t j, int32_t t, int32_t& a, int32_t& b) {
+    const int32_t e = j == 0 ? tr.te[0] : (j == 1 ? tr.te[1] : tr.te[2]);
+    const int32_t p = (e & 1) ? M - t : t;  // steps from v_j
+    a = j == 0 ? p : (j == 1 ? M - p : 0);
+    b = j == 0 ? 0 : (j == 1 ? p : M - p);
+  }
+};
+
 // (M x)_l for NR interleaved components (x(idx, d) reads component d of
 // lattice node idx) and the diagonal M_ll
-template <int NR, class X>
+template <int NR, int M, class X>
 CGP_HD inline void lat_apply(const LatDev& L, int32_t l, X x, double (&y)[NR], double& diag) {
-  const int32_t m = L.m;
+  using G = Lat<M>;
   if (l < L.EB) {
-    const int32_t T = l / L.nI;
-    int32_t r = l - T * L.nI, a = 1;
-    while (r >= m - 1 - a) {
-      r -= m - 1 - a;
-      ++a;
-    }
-    const int32_t b = r + 1;
-    const int32_t nb[6] = {lat_index(L, T, a, b - 1),     lat_index(L, T, a, b + 1),
-                           lat_index(L, T, a + 1, b),     lat_index(L, T, a + 1, b - 1),
-                           lat_index(L, T, a - 1, b),     lat_index(L, T, a - 1, b + 1)};
+    int32_t T, a, b;
+    G::interior(l, T, a, b);
+    const LatTri t = G::tri(L, T);
+    int32_t st[7];
+    G::interior_nbrs(L, l, a, b, t, st);
+    const int32_t nb[6] = {st[4], st[2], st[1], st[5], st[3], st[6]};
     const double A = L.af[T];
     diag = A;
 #pragma unroll
@@ -105,10 +189,10 @@ CGP_HD inline void lat_apply(const LatDev& L, int32_t l, X x, double (&y)[NR], d
     return;
   }
   if (l < L.VB) {
-    const int32_t E = (l - L.EB) / (m - 1);
-    const int32_t t = (l - L.EB) - E * (m - 1) + 1;
+    int32_t E, t;
+    G::edge(L, l, E, t);
     const int32_t prev = t == 1 ? L.VB + L.edge_v[2 * E] : l - 1;
-    const int32_t next = t == m - 1 ? L.VB + L.edge_v[2 * E + 1] : l + 1;
+    const int32_t next = t == M - 1 ? L.VB + L.edge_v[2 * E + 1] : l + 1;
     double acc[NR];
     double asum = 0.0;
 #pragma unroll
@@ -117,17 +201,20 @@ CGP_HD inline void lat_apply(const LatDev& L, int32_t l, X x, double (&y)[NR], d
       const int32_t tj = L.edge_t[2 * E + q];
       if (tj < 0) continue;
       const int32_t T = tj >> 2, j = tj & 3;
-      const int32_t p = (L.tri_e[3 * T + j] & 1) ? m - t : t;  // steps from v_j
+      const LatTri tr = G::tri(L, T);
+      int32_t a, b;
+      G::edge_point(tr, j, t, a, b);
+      // the two neighbours inside T, one step off the edge towards its interior
       int32_t i1, i2;
       if (j == 0) {
-        i1 = lat_index(L, T, p, 1);
-        i2 = lat_index(L, T, p - 1, 1);
+        i1 = G::index(L, T, tr, a, 1);
+        i2 = G::index(L, T, tr, a - 1, 1);
       } else if (j == 1) {
-        i1 = lat_index(L, T, m - p - 1, p);
-        i2 = lat_index(L, T, m - p, p - 1);
+        i1 = G::index(L, T, tr, a - 1, b);
+        i2 = G::index(L, T, tr, a, b - 1);
       } else {
-        i1 = lat_index(L, T, 1, m - p);
-        i2 = lat_index(L, T, 1, m - p - 1);
+        i1 = G::index(L, T, tr, 1, b);
+        i2 = G::index(L, T, tr, 1, b - 1);
       }
       const double A = L.af[T];
       asum += A;
@@ -170,6 +257,19 @@ CGP_HD inline double lat_diag(const LatDev& L, int32_t l) {
   for (int32_t s = L.rowptr[v]; s < L.rowptr[v + 1]; ++s)
     if (L.col[s] == v) return L.M[s];
   return 0.0;
+}
+
+// calls f(Lat<M>{}) for the compile-time lattice size M equal to m; returns
+// false for an unsupported m
+template <class F>
+CGP_HD inline bool lat_dispatch(int32_t m, F f) {
+  switch (m) {
+    case 1: f(Lat<1>{}); return true;
+    case 2: f(Lat<2>{}); return true;
+    case 4: f(Lat<4>{}); return true;
+    case 8: f(Lat<8>{}); return true;
+    default: return false;
+  }
 }
 
 }  // namespace cgp

@@ -27,7 +27,7 @@ namespace {
 // the lattice stencils (no matrix read away from the coarse vertices).  The
 // first step (x_0 = 0) needs only D and also clears x_k, which the next step
 // reads back as x_{k-1}.
-template <int NR>
+template <int NR, int M>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __restrict__ xk,
                const double* __restrict__ xkm, double* __restrict__ xnew, double ca, double cb,
@@ -46,7 +46,7 @@ k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __rest
     return;
   }
   double y[NR], diag;
-  lat_apply<NR>(L, l, [&](int32_t i, int d) { return xk[(int64_t)i * NR + d]; }, y, diag);
+  lat_apply<NR, M>(L, l, [&](int32_t i, int d) { return xk[(int64_t)i * NR + d]; }, y, diag);
   const double di = 1.0 / diag;
 #pragma unroll
   for (int d = 0; d < NR; ++d) {
@@ -85,10 +85,13 @@ double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
     double* xn = x[(k + 1) % 3];
     hipEvent_t* ev = (timer && k > 0) ? timer(tctx) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
-    if (nr == 3)
-      k_cheb_lattice<3><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
-    else
-      k_cheb_lattice<2><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
+    lat_dispatch(L.m, [&](auto lat) {
+      constexpr int M = decltype(lat)::kM;
+      if (nr == 3)
+        k_cheb_lattice<3, M><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
+      else
+        k_cheb_lattice<2, M><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
+    });
     if (ev) (void)hipEventRecord(ev[1], s);
   }
   return x[iters % 3];
