@@ -27,31 +27,95 @@ namespace {
 // the lattice stencils (no matrix read away from the coarse vertices).  The
 // first step (x_0 = 0) needs only D and also clears x_k, which the next step
 // reads back as x_{k-1}.
+//
+// Memory access: a block's 256 nodes own a contiguous range of 256 NR
+// doubles in every vector.  The block moves its ranges of b, x_{k-1}, x_k
+// (read) and x_new (written) between HBM and LDS as contiguous 16-byte
+// pieces, so these streams cost whole cache lines per instruction instead of
+// NR strided 8-byte accesses per node (on MI355X the strided form measured
+// 169 us per launch against 127 us staged, 2049^2 k = 3, NR = 3); neighbours
+// inside the block's range are read from LDS, the others gathered from x_k.
+// b and the iterates must be 16-byte aligned (the workspace pieces are
+// 256-byte aligned).
 template <int NR, int M>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __restrict__ xk,
                const double* __restrict__ xkm, double* __restrict__ xnew, double ca, double cb,
                int first) {
-  const int32_t l = blockIdx.x * kBlock + threadIdx.x;
-  if (l >= n) return;
-  const bool masked = L.ldir[l] != 0;
-  const int64_t base = (int64_t)l * NR;
-  if (first) {
-    const double di = 1.0 / lat_diag(L, l);
+  constexpr int kVals = kBlock * NR;  // doubles per block
+  constexpr int kPieces = kVals / 2;  // 16-byte pieces per block
+  __shared__ double2 sb[kPieces], sm[kPieces], sx[kPieces];
+  const int32_t l0 = blockIdx.x * kBlock;
+  const int32_t l = l0 + threadIdx.x;
+  const int64_t v0 = (int64_t)l0 * NR;  // first double of the block
+  const int64_t vend = (int64_t)n * NR;  // doubles in the vector
+  const double2* b2 = reinterpret_cast<const double2*>(b + v0);
+  const double2* m2 = reinterpret_cast<const double2*>(xkm + v0);
+  const double2* x2 = reinterpret_cast<const double2*>(xk + v0);
 #pragma unroll
-    for (int d = 0; d < NR; ++d) {
-      xnew[base + d] = (d < 2 && masked) ? 0.0 : cb * di * b[base + d];
-      xk[base + d] = 0.0;
+  for (int q = threadIdx.x; q < kPieces; q += kBlock) {
+    if (v0 + 2 * q + 1 < vend) {
+      sb[q] = b2[q];
+      if (!first) {
+        sm[q] = m2[q];
+        sx[q] = x2[q];
+      }
+    } else if (v0 + 2 * q < vend) {
+      sb[q] = make_double2(b[v0 + 2 * q], 0.0);
+      if (!first) {
+        sm[q] = make_double2(xkm[v0 + 2 * q], 0.0);
+        sx[q] = make_double2(xk[v0 + 2 * q], 0.0);
+      }
     }
-    return;
   }
-  double y[NR], diag;
-  lat_apply<NR, M>(L, l, [&](int32_t i, int d) { return xk[(int64_t)i * NR + d]; }, y, diag);
-  const double di = 1.0 / diag;
+  __syncthreads();
+  const double* sbd = reinterpret_cast<const double*>(sb);
+  const double* smd = reinterpret_cast<const double*>(sm);
+  const double* sxd = reinterpret_cast<const double*>(sx);
+  double out[NR];
+  if (l < n) {
+    const bool masked = L.ldir[l] != 0;
+    const int t = threadIdx.x * NR;
+    if (first) {
+      const double di = 1.0 / lat_diag(L, l);
 #pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    const int64_t k = base + d;
-    xnew[k] = (d < 2 && masked) ? 0.0 : xk[k] + ca * (xk[k] - xkm[k]) + cb * di * (b[k] - y[d]);
+      for (int d = 0; d < NR; ++d) out[d] = (d < 2 && masked) ? 0.0 : cb * di * sbd[t + d];
+    } else {
+      double y[NR], diag;
+      // neighbours inside the block's range come from LDS
+      lat_apply<NR, M>(
+          L, l,
+          [&](int32_t i, int d) {
+            const uint32_t r = (uint32_t)(i - l0);
+            return r < (uint32_t)kBlock ? sxd[r * NR + d] : xk[(int64_t)i * NR + d];
+          },
+          y, diag);
+      const double di = 1.0 / diag;
+#pragma unroll
+      for (int d = 0; d < NR; ++d) {
+        const double xv = sxd[t + d];
+        out[d] = (d < 2 && masked) ? 0.0 : xv + ca * (xv - smd[t + d]) + cb * di * (sbd[t + d] - y[d]);
+      }
+    }
+  }
+  __syncthreads();  // every read of sm is done: it now stages x_new
+  double* smw = reinterpret_cast<double*>(sm);
+  if (l < n) {
+#pragma unroll
+    for (int d = 0; d < NR; ++d) smw[threadIdx.x * NR + d] = out[d];
+  }
+  __syncthreads();
+  double2* o2 = reinterpret_cast<double2*>(xnew + v0);
+  double2* k2 = reinterpret_cast<double2*>(xk + v0);
+#pragma unroll
+  for (int q = threadIdx.x; q < kPieces; q += kBlock) {
+    if (v0 + 2 * q + 1 < vend) {
+      o2[q] = sm[q];
+      if (first) k2[q] = make_double2(0.0, 0.0);
+    } else if (v0 + 2 * q < vend) {
+      xnew[v0 + 2 * q] = smw[2 * q];
+      if (first) xk[v0 + 2 * q] = 0.0;
+    }
   }
 }
 
