@@ -193,7 +193,7 @@ __device__ __forceinline__ SideGeo side_geo(double2 pi, double2 pj, double2 pk, 
   return g;
 }
 
-constexpr int kRowLanes = 8;   // lanes per row in the side-based row kernels
+constexpr int kRowLanes = 4;   // lanes per row in the side-based row kernels (rows of 7 entries)
 
 template <int NS>
 __device__ __forceinline__ void group_sum(double (&v)[NS]) {
@@ -379,7 +379,8 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
 // ------------------------------------------------------------------ BiCGSTAB
 // Right-Jacobi-preconditioned BiCGSTAB on two right-hand sides sharing A.
 // One iteration = five kernels:
-//   B1  stopping test on r, rho = (r^, r), p = r + beta (p - omega v), p^ = D^-1 p
+//   B1  stopping test on r, rho = (r^, r), p = r + beta (p - omega v) (p = r in the
+//       first iteration), p^ = D^-1 p
 //   B2  v = A p^,                         partial (r^, v)
 //   B3  alpha, s = r - alpha v (in r),    s^ = D^-1 s, partial (s, s)
 //   B4  half-step test (x += alpha p^ and stop) or t = A s^, partials (t, s), (t, t)
@@ -403,8 +404,6 @@ k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double
         const double r = b - ax[d];
         V.r[d * n + row] = r;
         V.rhat[d * n + row] = r;
-        V.p[d * n + row] = 0.0;
-        V.v[d * n + row] = 0.0;
         rr[d] += r * r;
         bb[d] += b * b;
       }
@@ -460,7 +459,9 @@ k_bicg_b1(int32_t n32, BicgVecs V, Scal* sc, const double* part, int nb, int it,
     for (int d = 0; d < 2; ++d) {
       if (zero_rhs[d]) V.x[d * n + i] = 0.0;
       if (!upd[d]) continue;
-      const double pv = V.r[d * n + i] + beta[d] * (V.p[d * n + i] - omega[d] * V.v[d * n + i]);
+      // the first direction is the residual itself (p and v are not read)
+      const double pv = it == 1 ? V.r[d * n + i]
+                                : V.r[d * n + i] + beta[d] * (V.p[d * n + i] - omega[d] * V.v[d * n + i]);
       V.p[d * n + i] = pv;
       V.phat[d * n + i] = dinv * pv;
     }
