@@ -74,24 +74,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# committed rocprofv3 counter summaries of the timed kernel, per workload
-TRAFFIC_RECORDS = {("tg2049_k3_fp64", "mass_spmv"): "k_cheb_lattice3_tg2049_k3_fp64_traffic.md"}
-# the sources a record's kernel is compiled from (its hash must match)
-TRAFFIC_SOURCES = ("mass.hip", "lattice.hpp")
+# committed rocprofv3 counter summaries of a timed kernel, per workload, with
+# the sources the kernel is compiled from (their hash must match the record's)
+TRAFFIC_RECORDS = {
+    ("tg2049_k3_fp64", "mass_spmv"): ("k_cheb_lattice3_tg2049_k3_fp64_traffic.md",
+                                      ("mass.hip", "lattice.hpp")),
+    ("sq2049_k0_pcg", "coarse_spmv"): ("k_pcg_iter_sq2049_k0_fp64_traffic.md",
+                                       ("kernels.hip",)),
+}
 
 
 def stored_traffic(workload, kernel):
     """Measured HBM bytes per launch (FETCH_SIZE and WRITE_SIZE passes scaled
     by a calibration kernel) from the committed counter summary, or None when
     there is none or the kernels' source has changed since it was taken."""
-    name = TRAFFIC_RECORDS.get((workload, kernel))
-    if not name:
+    rec_entry = TRAFFIC_RECORDS.get((workload, kernel))
+    if not rec_entry:
         return None, "no counter summary for this workload and kernel"
+    name, sources = rec_entry
     path = os.path.join(ROOT, "profiles", name)
     try:
         text = open(path).read()
         h = hashlib.sha256()
-        for f in TRAFFIC_SOURCES:
+        for f in sources:
             h.update(open(os.path.join(ROOT, "paper_1812_00185_amd", "csrc", f), "rb").read())
         digest = h.hexdigest()
     except OSError as e:
@@ -160,6 +165,52 @@ def cpu_baseline(w, g_fine_xy, first_steps):
     }, parity
 
 
+def pcg_calibration(torch, iters, n_side=2049):
+    """The coarse PCG iteration kernel at fine scale: the n_side^2 unit square
+    with no coarsening, so the Poisson system has all fine nodes (4.2 M rows,
+    29.4 M nonzeros at 2049^2) and the iteration streams from HBM instead of
+    sitting in cache.  Jacobi-PCG runs `iters` iterations from a zero guess on
+    a seeded zero-mean right-hand side (the tolerance is out of reach, so the
+    count is fixed); one untimed solve, then one with HIP events around every
+    iteration kernel."""
+    from paper_1812_00185_amd import CGP
+    from workloads import unit_square
+
+    t0 = time.perf_counter()
+    g = CGP(unit_square(n_side), 0, 2e-4, 0.005, chi=1, pcg_tol=1e-300, max_iter=iters)
+    t_setup = time.perf_counter() - t0
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    b = torch.randn(g.nc, dtype=torch.float64, device="cuda", generator=gen)
+    b -= b.mean()
+    x = g.zeros(g.nc)
+    g.pcg_solve(b, x)
+    x.zero_()
+    torch.cuda.synchronize()
+    g.timing_enable(KERNELS["coarse_spmv"][0])
+    t0 = time.perf_counter()
+    st = g.pcg_solve(b, x)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nl = g.timing_read()
+    g.timing_enable(0)
+    nnz = int(g.sizes.nnz_coarse)
+    bpl = KERNELS["coarse_spmv"][1](g.nc, nnz, 0, 0, 0, 0)
+    avg_s = (kms / 1e3) / max(nl, 1)
+    achieved = bpl / avg_s / 1e9
+    traffic, src = stored_traffic(f"sq{n_side}_k0_pcg", "coarse_spmv")
+    out = {"workload": f"unit square {n_side}x{n_side}, no coarsening, Jacobi-PCG FP64",
+           "rows": g.nc, "nnz": nnz, "iterations": st["iters"], "launches": nl,
+           "avg_us": avg_s * 1e6, "bytes_per_launch": bpl, "achieved": achieved,
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": traffic, "traffic_source": src,
+           "measured_gbs": (traffic / avg_s / 1e9) if traffic else None,
+           "wall_us_per_iteration": 1e6 * wall / max(st["iters"], 1), "set_up_s": t_setup}
+    g.close()
+    del g, b, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_form(torch, g, uD, fields, warmup, steps, theta=None, kid=0):
     """W untimed steps, then K timed steps (synchronised on both sides, the
     selected kernel bracketed by HIP events), then one untimed step with
@@ -203,6 +254,10 @@ def main():
                             "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain FP64 form only: no training, no learned forms or legs")
+    ap.add_argument("--pcg-calibration-iters", type=int, default=100,
+                    help="iterations of the fine-scale coarse-PCG calibration (0: skip)")
+    ap.add_argument("--pcg-calibration-only", action="store_true",
+                    help="run only the fine-scale PCG calibration and print it as JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run an FP64 scale-by-one kernel over this many MiB (reads "
                          "and writes that many bytes): the reference for HBM counter scaling")
@@ -232,6 +287,11 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {args.copy_calibration_mb} MiB read + written")
         del src, dst
+
+    if args.pcg_calibration_only:
+        print(json.dumps({"calibration": {"pcg_fine_k0": pcg_calibration(
+            torch, max(args.pcg_calibration_iters, 1))}}), flush=True)
+        return
 
     w = get_workload(args.workload)
     forms = args.forms.split(",")
@@ -372,6 +432,11 @@ def main():
         log(f"[bench] {wl.name}: {json.dumps(ttl)}")
         del gl, glm
 
+    calib = None
+    if args.pcg_calibration_iters > 0:
+        calib = {"pcg_fine_k0": pcg_calibration(torch, args.pcg_calibration_iters)}
+        log(f"[bench] PCG calibration: {json.dumps(calib)}")
+
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
@@ -388,7 +453,7 @@ def main():
                    "levels": w.levels, "dt": w.dt, "nu": w.nu, "chi": w.chi,
                    "restrict": w.restrict, "pcg_tol": w.pcg_tol, "mom_tol": w.mom_tol},
         "forms": results, "roofline": roofline, "cpu_baseline": cpu,
-        "parity_rel_l2": parity, "time_to_tol": ttt,
+        "parity_rel_l2": parity, "time_to_tol": ttt, "calibration": calib,
     }
     print(json.dumps(out), flush=True)
 
