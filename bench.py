@@ -59,7 +59,9 @@ HBM_PEAK_GBS = 8000.0
 #               (32 B); per coarse edge its ends and triangles (16 B); the CSR
 #               rows of the coarse vertices (2E + V entries of 16 B: value,
 #               column, its lattice index) and their row pointers
-#  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written
+#  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written (the
+#               average includes the launches queued past convergence, which
+#               return at once: a bound, not a bandwidth figure)
 #  coarse_spmv: one single-reduction PCG iteration: x, p, r, w, s, D^-1 read,
 #               x, p, r, w, s written
 KERNELS = {
