@@ -590,6 +590,7 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   if (nr == 0) return CGP_OK;  // the kernel wrote U and P
   const double* du = cgp::launch_cheb(c->latd, c->nf, c->mrhs, nr, c->mx, c->cheb_iters, s,
                                       c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
+  if (!du) return fail(CGP_ERR_INVALID, "mass solve: misaligned vectors or unsupported lattice size");
   // with the lumped pressure update the kernel above wrote P already
   cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, nr, cheb_p || !chi, u_out, p_out,
                            c->latd.lat_of, s);

@@ -109,8 +109,10 @@ void launch_pcg_iter(const DLevel& L, const PcgVecs<T>& V, Scal* sc, double* par
 int cheb_iterations(double tol);
 // Solves M x = b for nr (2 or 3) right-hand sides interleaved [n][nr] in the
 // lattice layout (velocity components 0 at Dirichlet nodes); returns the
-// buffer (one of x[0..2]) holding the result.  `timer(tctx)`, when given,
-// supplies an event pair per product launch.
+// buffer (one of x[0..2]) holding the result, or nullptr (nothing launched)
+// when b or an iterate is not 16-byte aligned or the lattice size is not one
+// of 1, 2, 4, 8.  `timer(tctx)`, when given, supplies an event pair per
+// product launch.
 double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx);

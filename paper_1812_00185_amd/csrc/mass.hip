@@ -132,6 +132,9 @@ int cheb_iterations(double tol) {
 double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
                     void* tctx) {
+  // the kernel moves its block ranges as 16-byte pieces
+  const uintptr_t align = (uintptr_t)b | (uintptr_t)x[0] | (uintptr_t)x[1] | (uintptr_t)x[2];
+  if ((align & 15) != 0 || !lat_dispatch(L.m, [](auto) {})) return nullptr;
   const double lo = 0.5, hi = 2.0;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   const int g = (n + kBlock - 1) / kBlock;
