@@ -6,7 +6,9 @@ of every coarse solve <= tol and the fields within 1e-6 of the oracle).
 * channel minus cylinder (h = 0.0082 seeded Delaunay, about 31k coarse
   triangles refined twice), rotational, mixed precision, 2 steps;
 * Taylor-Green 2049 x 2049, k = 3, rotational, one step from the exact
-  fields (4.2 M fine nodes; the oracle needs about 10 s for it).
+  fields (4.2 M fine nodes; the oracle needs about 10 s for it), and the same
+  step with the factor preconditioner, with lumped mass (Eqs. 25 and 27) and
+  in the non-incremental form.
 """
 import numpy as np
 import pytest
@@ -31,7 +33,8 @@ def solver(w):
     return CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
                precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
                pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol,
-               mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass, precond=w.precond)
+               mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass, precond=w.precond,
+               scheme=w.scheme)
 
 
 def run(w, steps):
@@ -86,3 +89,22 @@ def test_taylor_green_2049_k3_ndchol_two_steps():
     for du, dp, st in run(w, 2):
         assert st["poisson"]["converged"] and st["poisson"]["iters"] <= 2
         assert du <= 1e-10 and dp <= 1e-10
+
+
+def test_taylor_green_2049_k3_lumped_one_step():
+    """Lumped mass in the velocity correction and the pressure update (Eq. 27)
+    at full size, against the oracle in the same mode."""
+    w = get_workload("tg2049_k3_fp64").with_(mass="lumped")
+    ((du, dp, st),) = run(w, 1)
+    assert st["poisson"]["converged"]
+    assert du <= 1e-10 and dp <= 1e-10
+
+
+def test_taylor_green_2049_k3_nonincremental_one_step():
+    """The non-incremental form (no pressure in the momentum equation,
+    P^{n+1} = Phi_f, chi = 0) at full size, against the oracle in the same
+    form."""
+    w = get_workload("tg2049_k3_fp64").with_(scheme="nonincremental", chi=0)
+    ((du, dp, st),) = run(w, 1)
+    assert st["poisson"]["converged"]
+    assert du <= 1e-10 and dp <= 1e-10
