@@ -243,9 +243,11 @@ def main():
     ap.add_argument("--workload", default="tg2049_k3_fp64")
     ap.add_argument("--learned-workload", default="cavity257_k1_learned")
     ap.add_argument("--learned-runs", type=int, default=4)
-    ap.add_argument("--learned-steps", type=int, default=150)
+    # the learned-guess configuration: 4 runs x 500 steps = 2000 training
+    # pairs, then 1000 new steps
+    ap.add_argument("--learned-steps", type=int, default=500)
     ap.add_argument("--learned-epochs", type=int, default=3)
-    ap.add_argument("--learned-eval", type=int, default=300)
+    ap.add_argument("--learned-eval", type=int, default=1000)
     ap.add_argument("--timed-kernel", default="mass_spmv", choices=sorted(KERNELS))
     ap.add_argument("--train-runs", type=int, default=3)
     ap.add_argument("--train-steps", type=int, default=40)
