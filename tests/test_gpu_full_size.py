@@ -108,3 +108,61 @@ def test_taylor_green_2049_k3_nonincremental_one_step():
     ((du, dp, st),) = run(w, 1)
     assert st["poisson"]["converged"]
     assert du <= 1e-10 and dp <= 1e-10
+
+
+def oracle_sensitivity(w, steps, monkeypatch):
+    """How far the oracle's own trajectory moves when every solver right-hand
+    side carries 1e-15 relative noise: no other rounding order can agree with
+    it more closely than this."""
+    import oracle.cgp as oc
+
+    rng = np.random.default_rng(0)
+    pcg, bicg = oc.pcg_jacobi, oc.bicgstab_jacobi
+
+    def noisy(fn):
+        def f(A, b, **kw):
+            return fn(A, b * (1 + 1e-15 * rng.standard_normal(b.shape)), **kw)
+        return f
+
+    def traj():
+        o = build_oracle(w)
+        st = o.initial_state(*w.initial_fields(o.fine_xy))
+        out = []
+        for n in range(steps):
+            st = o.step(st, w.dirichlet_values(o.fine_xy[o.dir], (n + 1) * w.dt)).state
+            out.append((st.U.copy(), st.P.copy()))
+        return out
+
+    clean = traj()
+    with monkeypatch.context() as m:
+        m.setattr(oc, "pcg_jacobi", noisy(pcg))
+        m.setattr(oc, "bicgstab_jacobi", noisy(bicg))
+        pert = traj()
+    return max(max(rel(u1, u0), rel(p1, p0)) for (u0, p0), (u1, p1) in zip(clean, pert))
+
+
+def test_channel_full_mesh_fp64(monkeypatch):
+    """The channel-cylinder configuration on the FP64 path (natural outflow,
+    pressure mesh with phi = 0 rows).  Starting from rest, the first
+    projection removes a divergent part much larger than U^{n+1}, so
+    rounding-level differences in the correction are magnified in u: the
+    bound is 1e-10 or 10x the oracle's own rounding sensitivity."""
+    w = get_workload("channel_k2").with_(precision=0)
+    res = run(w, 2)
+    sens = oracle_sensitivity(w, 2, monkeypatch)
+    worst = max(max(du, dp) for du, dp, _ in res)
+    bound = max(1e-10, 10 * sens)
+    print(f"[result] GPU vs oracle {worst:.3e}, oracle self-sensitivity {sens:.3e}, "
+          f"bound {bound:.3e}", flush=True)
+    for du, dp, st in res:
+        assert st["poisson"]["converged"]
+    assert worst <= bound, (worst, sens)
+
+
+def test_cavity_257_k3_standard():
+    """The cavity with three levels of coarsening (33 x 33 pressure mesh),
+    standard scheme, 3 steps from rest."""
+    w = get_workload("cavity257_k3_chi0_fp64")
+    for du, dp, st in run(w, 3):
+        assert st["poisson"]["converged"]
+        assert du <= 1e-10 and dp <= 1e-10
