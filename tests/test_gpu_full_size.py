@@ -166,3 +166,14 @@ def test_cavity_257_k3_standard():
     for du, dp, st in run(w, 3):
         assert st["poisson"]["converged"]
         assert du <= 1e-10 and dp <= 1e-10
+
+
+def test_taylor_green_2049_k3_mixed_one_step():
+    """The mixed-precision path (FP32 inner PCG, FP64 refinement) at full
+    size: the FP64 true residual of the coarse solve within the tolerance,
+    the fields within 1e-6 of the FP64 oracle."""
+    w = get_workload("tg2049_k3_mixed")
+    assert w.precision == 1
+    ((du, dp, st),) = run(w, 1)
+    assert st["poisson"]["converged"] and st["poisson"]["rel_res"] <= w.pcg_tol
+    assert du <= 1e-6 and dp <= 1e-6
