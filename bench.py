@@ -5,7 +5,7 @@
 A step is one full CGP time step (Eqs. 21-26: momentum, restriction, coarse
 Poisson solve, prolongation, velocity and pressure correction) of the
 2049 x 2049 Taylor-Green workload with 3 coarsening levels (257 x 257 pressure
-mesh, rotational form), inputs resident on the GPU.  Three forms of the step
+mesh, rotational form), inputs resident on the GPU.  These forms of the step
 run over the same trajectory:
   plain_fp64     FP64 Jacobi-PCG from the previous increment (the paper's step)
   learned_mixed  guarded learned guess + FP32-inner / FP64-refinement PCG
@@ -15,6 +15,8 @@ run over the same trajectory:
   ndchol_fp64    FP64 PCG preconditioned by the nested-dissection Cholesky
                  factor of K_c (one iteration to rounding level)
   ndchol_lumped_fp64  ndchol_fp64 with lumped mass in Eqs. 25 and 27
+  s4_fp64        plain_fp64 with the coarse Jacobi-PCG in s-step form (four
+                 iterations per launch from one reduction; the same iterates)
   ncgp_fp64      the non-incremental CGP form the paper compares with
                  (no pressure in the momentum equation, P = Phi_f; chi = 0)
 and, for Taylor-Green, each form's error against the exact solution.
@@ -122,7 +124,8 @@ FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
               "lumped_fp64": ("lumped", "pcg", "incremental"),
               "ndchol_fp64": ("consistent", "exact", "incremental"),
               "ndchol_lumped_fp64": ("lumped", "exact", "incremental"),
-              "ncgp_fp64": ("consistent", "pcg", "nonincremental")}
+              "ncgp_fp64": ("consistent", "pcg", "nonincremental"),
+              "s4_fp64": ("consistent", "pcg", "incremental")}
 
 
 def cpu_baseline(w, g_fine_xy, first_steps):
@@ -255,7 +258,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
-                            "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64")
+                            "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64")
     ap.add_argument("--no-learned", action="store_true",
                     help="plain FP64 form only: no training, no learned forms or legs")
     ap.add_argument("--pcg-calibration-iters", type=int, default=100,
@@ -309,7 +312,8 @@ def main():
     for form, mass, pre in (("lumped_p_fp64", "lumped_p", "jacobi"),
                             ("lumped_fp64", "lumped", "jacobi"),
                             ("ndchol_fp64", "consistent", "ndchol"),
-                            ("ndchol_lumped_fp64", "lumped", "ndchol")):
+                            ("ndchol_lumped_fp64", "lumped", "ndchol"),
+                            ("s4_fp64", "consistent", "jacobi_s4")):
         if form in forms:
             solvers[form] = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64",
                                 mass=mass, precond=pre, **kw)
@@ -338,7 +342,7 @@ def main():
             f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
               "lumped_p_fp64": None, "lumped_fp64": None, "ndchol_fp64": None,
-              "ndchol_lumped_fp64": None, "ncgp_fp64": None}
+              "ndchol_lumped_fp64": None, "ncgp_fp64": None, "s4_fp64": None}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]

@@ -69,6 +69,11 @@ extern "C" {
  * with ILU(0), Sect. 2.3; the choice of coarse solver is open) */
 #define CGP_PRECOND_JACOBI 0 /* diagonal: single-reduction PCG, FP64 or mixed   */
 #define CGP_PRECOND_NDCHOL 1 /* nested-dissection Cholesky factor of K_c (FP64) */
+#define CGP_PRECOND_JACOBI_S4 2 /* diagonal, s-step form (FP64): the iterates of
+                                  Jacobi-PCG, four iterations per launch from
+                                  one Gram-matrix reduction (Chebyshev basis of
+                                  the scaled operator); every iteration keeps
+                                  the ||b - K phi|| stopping test             */
 
 /* projection scheme */
 #define CGP_SCHEME_INCREMENTAL 0    /* the method: Eqs. 21-26 (standard or rotational) */
@@ -124,7 +129,11 @@ typedef struct cgp_problem {
                             matrix, Eq. 27) or CGP_MASS_LUMPED (Eq. 27 and the
                             velocity correction with the lumped mass matrix;
                             no mass solves)                                  */
-  int32_t coarse_precond; /* CGP_PRECOND_JACOBI, or CGP_PRECOND_NDCHOL: PCG in
+  int32_t coarse_precond; /* CGP_PRECOND_JACOBI, CGP_PRECOND_JACOBI_S4 (the same
+                            solver in s-step form; requires precision =
+                            CGP_FP64; cgp_create fails with CGP_ERR_INVALID
+                            if a coarse node's depth-4 graph neighbourhood
+                            exceeds 1024 nodes), or CGP_PRECOND_NDCHOL: PCG in
                             FP64 preconditioned by the exact Cholesky factor
                             of K_c (phi = 0 nodes removed; without natural
                             nodes the last coarse node N_c - 1 is pinned, as
@@ -227,7 +236,9 @@ int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream)
  * phi = 0 rows/columns removed) from the guess held in phi_c, stopping when
  * ||b - K phi|| <= pcg_tol ||b||; CGP_FP64 runs Jacobi-PCG in FP64,
  * CGP_MIXED runs FP64 refinement steps around FP32 Jacobi-PCG (FP64 dot
- * products and norms); CGP_PRECOND_NDCHOL runs FP64 PCG whose
+ * products and norms); CGP_PRECOND_JACOBI_S4 runs FP64 Jacobi-PCG in s-step
+ * form (same iterates up to rounding, same test after every iteration);
+ * CGP_PRECOND_NDCHOL runs FP64 PCG whose
  * preconditioner is the factor (one iteration reaches rounding level; the
  * FP64 residual is tested before the first and after every iteration).  For the pure Neumann problem the lumped-mass mean of
  * the result is removed.  b_c, phi_c device [N_c].  stats may be NULL (then
@@ -381,6 +392,18 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const
 int cgp_ndchol_solve_host(int32_t n, const int32_t* rowptr, const int32_t* col,
                           const double* val, const double* xy, const uint8_t* skip,
                           const double* r, double* z, cgp_ndchol_info* info);
+
+/* Host-only: the tiling of CGP_PRECOND_JACOBI_S4 for a symmetric CSR graph
+ * (rowptr [n+1], col; every row holds its diagonal; xy [2n] node
+ * coordinates).  perm [n] receives the internal order (internal index ->
+ * node), own_off [n+1] the internal range [own_off[t], own_off[t+1]) of the
+ * nodes tile t owns (at most 512), info [4] = (tiles, most nodes a tile owns,
+ * largest depth-4 neighbourhood (at most 1024 nodes), ELL width; a tile's
+ * rows within distance 3 times the width is at most 7680).  The plan is checked against every
+ * invariant the kernels rely on before it is returned.  All host.
+ * Errors: CGP_ERR_INVALID (arguments, or a neighbourhood over capacity). */
+int cgp_ca_plan_host(int32_t n, const int32_t* rowptr, const int32_t* col, const double* xy,
+                     int32_t* perm, int32_t* own_off, int32_t* info);
 
 /* Releases host memory and the pinned buffer; the workspace stays the
  * caller's.  Safe on NULL. */

@@ -27,7 +27,7 @@ CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
 CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED = 0, 1, 2
-CGP_PRECOND_JACOBI, CGP_PRECOND_NDCHOL = 0, 1
+CGP_PRECOND_JACOBI, CGP_PRECOND_NDCHOL, CGP_PRECOND_JACOBI_S4 = 0, 1, 2
 CGP_SCHEME_INCREMENTAL, CGP_SCHEME_NONINCREMENTAL = 0, 1
 
 _dp = C.POINTER(C.c_double)
@@ -127,6 +127,7 @@ SIGNATURES = [
     ("cgp_lattice_mass_apply_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, _dp, _dp, _dp]),
     ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,
                                         C.POINTER(C.c_uint8), _dp, _dp, C.POINTER(NdcholInfo)]),
+    ("cgp_ca_plan_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _ip, _ip, _ip]),
     ("cgp_destroy", None, [C.c_void_p]),
     ("cgp_last_error", C.c_char_p, []),
 ]
@@ -183,3 +184,24 @@ def ndchol_solve_host(rowptr, col, val, xy, skip, r):
         xy.ctypes.data_as(_dp), skip.ctypes.data_as(C.POINTER(C.c_uint8)),
         r.ctypes.data_as(_dp), z.ctypes.data_as(_dp), C.byref(info)), allow_not_converged=False)
     return z, info.as_dict()
+
+
+def ca_plan_host(rowptr, col, xy):
+    """Tiling of the s-step coarse PCG through the library's host planner:
+    (perm, own_off, info dict)."""
+    import numpy as np
+
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    xy = np.ascontiguousarray(xy, np.float64)
+    n = rowptr.size - 1
+    perm = np.empty(n, np.int32)
+    own_off = np.full(n + 1, -1, np.int32)
+    info = np.zeros(4, np.int32)
+    check(load().cgp_ca_plan_host(
+        n, rowptr.ctypes.data_as(_ip), col.ctypes.data_as(_ip), xy.ctypes.data_as(_dp),
+        perm.ctypes.data_as(_ip), own_off.ctypes.data_as(_ip), info.ctypes.data_as(_ip)),
+        allow_not_converged=False)
+    t = int(info[0])
+    return perm, own_off[:t + 1].copy(), dict(ntiles=t, max_own=int(info[1]),
+                                             max_ext=int(info[2]), width=int(info[3]))

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcgp.so")
 
-SOURCES = ["mesh.cpp", "lattice.cpp", "ndchol.cpp", "kernels.hip", "mpnn.hip", "ndchol.hip", "mass.hip", "api.hip"]
+SOURCES = ["mesh.cpp", "lattice.cpp", "ndchol.cpp", "capcg.cpp", "kernels.hip", "mpnn.hip", "ndchol.hip",
+           "mass.hip", "capcg.hip", "api.hip"]
 ARCH = "gfx950"
 
 

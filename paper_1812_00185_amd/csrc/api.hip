@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "capcg.hpp"
 #include "cgp.h"
 #include "device.hpp"
 #include "mesh.hpp"
@@ -116,6 +117,10 @@ struct cgp_ctx {
   double* nd_z = nullptr;
   double* nd_p[2] = {nullptr, nullptr};
   double* nd_q = nullptr;
+
+  // s-step Jacobi-PCG (CGP_PRECOND_JACOBI_S4): host plan and device view
+  cgp::CaPlan ca;
+  cgp::CaDev cad{};
 
   // measurement hook (cgp_timing_enable)
   int timed_id = 0;
@@ -228,6 +233,30 @@ size_t carve(cgp_ctx* c, void* base) {
     c->nd_p[0] = w.take<double>(nc);
     c->nd_p[1] = w.take<double>(nc);
     c->nd_q = w.take<double>(nc);
+  }
+  if (c->prob.coarse_precond == CGP_PRECOND_JACOBI_S4) {
+    const cgp::CaPlan& pl = c->ca;
+    cgp::CaDev& d = c->cad;
+    d.n = c->nc;
+    d.ntiles = pl.ntiles;
+    d.ntiles_pad = pl.ntiles_pad;
+    d.width = pl.width;
+    d.perm = w.take<int32_t>(pl.perm.size());
+    d.own_off = w.take<int32_t>(pl.own_off.size());
+    d.ext_off = w.take<int32_t>(pl.ext_off.size());
+    d.ext = w.take<int32_t>(pl.ext.size());
+    d.layer = w.take<int32_t>(pl.layer.size());
+    d.ell_off = w.take<int32_t>(pl.ell_off.size());
+    d.ell_col = w.take<uint16_t>(pl.ell_col.size());
+    d.ell_slot = w.take<int32_t>(pl.ell_slot.size());
+    d.ell_val = w.take<double>(pl.ell_col.size());
+    d.sq = w.take<double>(nc);
+    d.xh = w.take<double>(nc);
+    d.r0 = w.take<double>(nc);
+    d.V[0] = w.take<double>((size_t)cgp::kCaM * nc);
+    d.V[1] = w.take<double>((size_t)cgp::kCaM * nc);
+    d.gpart = w.take<double>((size_t)2 * cgp::kCaNG * pl.ntiles_pad);
+    d.spart = w.take<double>((size_t)2 * pl.ntiles_pad);
   }
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
@@ -449,6 +478,22 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
   if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
   if (P.coarse_precond == CGP_PRECOND_NDCHOL) {
     rc = run_pcg_nd(c, b, x, st, s);
+  } else if (P.coarse_precond == CGP_PRECOND_JACOBI_S4) {
+    // one launch per kCaS iterations (launch 1 tests the guess); the scalars
+    // are polled every 8 launches, one chunk behind
+    const cgp::CaDev& d = c->cad;
+    cgp::launch_ca_start(d, c->ell_col, c->ell_val, c->ell_w, b, x, c->scal, s);
+    Scal out[1];
+    const int last = 1 + (P.max_iter + cgp::kCaS - 1) / cgp::kCaS;
+    rc = drive(c, c->scal, 1, last, 8, false,
+               [&](int o, bool) {
+                 cgp::launch_ca_outer(d, c->scal, o, P.pcg_tol, P.max_iter, cgp::stamp(o, 1), s,
+                                      timer(c, CGP_K_COARSE_SPMV));
+               },
+               s, out);
+    if (rc) return rc;
+    cgp::launch_ca_final(d, x, s);
+    rc = stats_status(out, 1, P.max_iter, st);
   } else if (P.precision == CGP_FP64) {
     cgp::PcgVecs<double> V{x,          c->cp,       {c->cr2[0], c->cr2[1]},
                            {c->cw2[0], c->cw2[1]}, {c->cs2[0], c->cs2[1]},
@@ -622,7 +667,8 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     return fail(CGP_ERR_INVALID, "dt, nu, tolerances and iteration caps must be positive");
   if (prob->mass_mode < CGP_MASS_CONSISTENT || prob->mass_mode > CGP_MASS_LUMPED)
     return fail(CGP_ERR_INVALID, "unknown mass_mode");
-  if (prob->coarse_precond != CGP_PRECOND_JACOBI && prob->coarse_precond != CGP_PRECOND_NDCHOL)
+  if (prob->coarse_precond != CGP_PRECOND_JACOBI && prob->coarse_precond != CGP_PRECOND_NDCHOL &&
+      prob->coarse_precond != CGP_PRECOND_JACOBI_S4)
     return fail(CGP_ERR_INVALID, "unknown coarse_precond");
   if (prob->scheme != CGP_SCHEME_INCREMENTAL && prob->scheme != CGP_SCHEME_NONINCREMENTAL)
     return fail(CGP_ERR_INVALID, "unknown scheme");
@@ -630,6 +676,8 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     return fail(CGP_ERR_INVALID, "the non-incremental scheme has no rotational form (chi = 0)");
   if (prob->coarse_precond == CGP_PRECOND_NDCHOL && prob->precision != CGP_FP64)
     return fail(CGP_ERR_INVALID, "CGP_PRECOND_NDCHOL requires precision CGP_FP64");
+  if (prob->coarse_precond == CGP_PRECOND_JACOBI_S4 && prob->precision != CGP_FP64)
+    return fail(CGP_ERR_INVALID, "CGP_PRECOND_JACOBI_S4 requires precision CGP_FP64");
   cgp::Mesh cm;
   cm.n_nodes = m.n_nodes;
   cm.n_tris = m.n_tris;
@@ -704,6 +752,18 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     if (!err.empty()) {
       delete c;
       return fail(CGP_ERR_INVALID, err);
+    }
+  }
+  if (prob->coarse_precond == CGP_PRECOND_JACOBI_S4) {
+    try {
+      err = cgp::ca_plan(c->nc, c->h.gc.rowptr, c->h.gc.col, c->h.coarse.xy.data(), cgp::kCaS,
+                         cgp::kCaThreads, cgp::kCaExtMax, cgp::kCaEllMax, c->ca);
+    } catch (const std::exception& e) {
+      err = std::string("s-step plan failed: ") + e.what();
+    }
+    if (!err.empty()) {
+      delete c;
+      return fail(CGP_ERR_INVALID, "CGP_PRECOND_JACOBI_S4: " + err);
     }
   }
   c->ws_bytes = carve(c, nullptr);
@@ -788,6 +848,19 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
   cgp::launch_make_ell(c->C, c->Kc, c->invdKc, c->ell_w, c->ell_col, c->ell_val, c->ell_sval,
                        c->ell_sval32, s);
   cgp::net::launch_edge_features(c->C, c->hbar, c->net, s);
+  if (c->prob.coarse_precond == CGP_PRECOND_JACOBI_S4) {
+    const cgp::CaPlan& pl = c->ca;
+    const cgp::CaDev& d = c->cad;
+    HIPCHK(up((void*)d.perm, pl.perm.data(), 4 * pl.perm.size()));
+    HIPCHK(up((void*)d.own_off, pl.own_off.data(), 4 * pl.own_off.size()));
+    HIPCHK(up((void*)d.ext_off, pl.ext_off.data(), 4 * pl.ext_off.size()));
+    HIPCHK(up((void*)d.ext, pl.ext.data(), 4 * pl.ext.size()));
+    HIPCHK(up((void*)d.layer, pl.layer.data(), 4 * pl.layer.size()));
+    HIPCHK(up((void*)d.ell_off, pl.ell_off.data(), 4 * pl.ell_off.size()));
+    HIPCHK(up((void*)d.ell_col, pl.ell_col.data(), 2 * pl.ell_col.size()));
+    HIPCHK(up((void*)d.ell_slot, pl.ell_slot.data(), 4 * pl.ell_slot.size()));
+    cgp::launch_ca_setup(d, c->C.rowptr, c->Kc, s);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   if (c->prob.coarse_precond == CGP_PRECOND_NDCHOL) {
@@ -925,6 +998,33 @@ int cgp_query_ndchol(const cgp_ctx* c, cgp_ndchol_info* out) {
   out->height = f.height;
   out->max_front = f.max_front;
   out->g_entries = f.g_entries;
+  return CGP_OK;
+}
+
+int cgp_ca_plan_host(int32_t n, const int32_t* rowptr, const int32_t* col, const double* xy,
+                     int32_t* perm, int32_t* own_off, int32_t* info) {
+  if (n < 1 || !rowptr || !col || !xy || !perm || !own_off || !info)
+    return fail(CGP_ERR_INVALID, "null or empty argument");
+  if (rowptr[0] != 0) return fail(CGP_ERR_INVALID, "rowptr[0] must be 0");
+  for (int32_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] <= rowptr[i]) return fail(CGP_ERR_INVALID, "every row needs its diagonal");
+  std::vector<int32_t> rp(rowptr, rowptr + n + 1), cl(col, col + rowptr[n]);
+  for (int32_t j : cl)
+    if (j < 0 || j >= n) return fail(CGP_ERR_INVALID, "column out of range");
+  cgp::CaPlan pl;
+  std::string err;
+  try {
+    err = cgp::ca_plan(n, rp, cl, xy, cgp::kCaS, cgp::kCaThreads, cgp::kCaExtMax, cgp::kCaEllMax, pl);
+  } catch (const std::exception& e) {
+    err = e.what();
+  }
+  if (!err.empty()) return fail(CGP_ERR_INVALID, err);
+  std::memcpy(perm, pl.perm.data(), sizeof(int32_t) * n);
+  std::memcpy(own_off, pl.own_off.data(), sizeof(int32_t) * pl.own_off.size());
+  info[0] = pl.ntiles;
+  info[1] = pl.max_own;
+  info[2] = pl.max_ext;
+  info[3] = pl.width;
   return CGP_OK;
 }
 

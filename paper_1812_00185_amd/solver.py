@@ -57,7 +57,8 @@ class CGP:
         rmode = {"galerkin": N.CGP_RESTRICT_GALERKIN, "inject": N.CGP_RESTRICT_INJECT}[restrict]
         mmode = {"consistent": N.CGP_MASS_CONSISTENT, "lumped_p": N.CGP_MASS_LUMPED_P,
                  "lumped": N.CGP_MASS_LUMPED}[mass]
-        pmode = {"jacobi": N.CGP_PRECOND_JACOBI, "ndchol": N.CGP_PRECOND_NDCHOL}[precond]
+        pmode = {"jacobi": N.CGP_PRECOND_JACOBI, "ndchol": N.CGP_PRECOND_NDCHOL,
+                 "jacobi_s4": N.CGP_PRECOND_JACOBI_S4}[precond]
         smode = {"incremental": N.CGP_SCHEME_INCREMENTAL,
                  "nonincremental": N.CGP_SCHEME_NONINCREMENTAL}[scheme]
         self.problem = N.Problem(mesh, levels, chi, prec, rmode, dt, nu, pcg_tol, inner_tol,

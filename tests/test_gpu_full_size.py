@@ -91,6 +91,16 @@ def test_taylor_green_2049_k3_ndchol_two_steps():
         assert du <= 1e-10 and dp <= 1e-10
 
 
+def test_taylor_green_2049_k3_sstep_one_step():
+    """The plain FP64 step with the coarse Jacobi-PCG in s-step form (four
+    iterations per launch from one reduction), against the oracle's
+    Jacobi-PCG at the same tolerance."""
+    w = get_workload("tg2049_k3_fp64").with_(precond="jacobi_s4")
+    ((du, dp, st),) = run(w, 1)
+    assert st["poisson"]["converged"]
+    assert du <= 1e-10 and dp <= 1e-10
+
+
 def test_taylor_green_2049_k3_lumped_one_step():
     """Lumped mass in the velocity correction and the pressure update (Eq. 27)
     at full size, against the oracle in the same mode."""
