@@ -22,10 +22,12 @@ run over the same trajectory:
 and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
-trajectories than the timed one).  `value` is the plain_fp64 throughput in
-fine DOF * steps / s (DOF = 3 N_f: u, v, p), the form that matches the FP64
-oracle to 1e-10; the other forms (which agree with it to the solver
-tolerance), the coarse-solve time to tolerance of each guess on this
+trajectories than the timed one).  `value` is the throughput in fine
+DOF * steps / s (DOF = 3 N_f: u, v, p) of the paper's step with FP64
+Jacobi-PCG, run in its s-step form (s4_fp64: the iterations of plain_fp64,
+four per launch; --main-form picks another form), which matches the FP64
+oracle to 1e-10 like plain_fp64; the other forms (which agree with it to the
+solver tolerance), the coarse-solve time to tolerance of each guess on this
 workload and on the 257 x 257 lid-driven cavity with a 129 x 129 pressure
 mesh (the learned guess's own workload: trained on lid speeds U[0.5, 1.5],
 evaluated on a fresh U = 1 run), the roofline position of the dominant
@@ -259,8 +261,10 @@ def main():
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
                             "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64")
+    ap.add_argument("--main-form", default="s4_fp64",
+                    help="the form whose throughput is `value` (if it runs; else plain_fp64)")
     ap.add_argument("--no-learned", action="store_true",
-                    help="plain FP64 form only: no training, no learned forms or legs")
+                    help="the plain FP64 forms only (Jacobi-PCG, standard and s-step): no training, no learned forms or legs")
     ap.add_argument("--pcg-calibration-iters", type=int, default=100,
                     help="iterations of the fine-scale coarse-PCG calibration (0: skip)")
     ap.add_argument("--pcg-calibration-only", action="store_true",
@@ -270,7 +274,7 @@ def main():
                          "and writes that many bytes): the reference for HBM counter scaling")
     args = ap.parse_args()
     if args.no_learned:
-        args.forms = "plain_fp64"
+        args.forms = "plain_fp64,s4_fp64"
         args.learned_workload = ""
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -359,7 +363,8 @@ def main():
         del s1
 
     kid, kbytes = KERNELS[args.timed_kernel]
-    main_form = "plain_fp64" if "plain_fp64" in forms else forms[0]
+    main_form = args.main_form if args.main_form in forms else (
+        "plain_fp64" if "plain_fp64" in forms else forms[0])
     results, finals = {}, {}
     for form in forms:
         el, kms, nl, st, state = run_form(torch, solvers[form], uD, (Um, U0, P0),

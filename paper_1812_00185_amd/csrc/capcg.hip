@@ -18,12 +18,38 @@ constexpr int LDE = EXT + 1;       // LDS row stride of the basis (odd: rows in 
 constexpr int PER = (EXT + T - 1) / T;     // neighbourhood nodes per thread
 constexpr int PERE = (EMAX + T - 1) / T;   // ELL entries per thread
 constexpr int kSPW = (NG + kW - 1) / kW;   // Gram entries per wave
-constexpr int kTPL = 4;                    // tiles per lane per pass over the partials
+constexpr int kTPL = 3;                    // tiles per lane per pass over the partials
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane sums on DPP row permutations (VALU, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each row of 16 lanes: quad_perm [1,0,3,2] and [2,3,0,1] (lane xor 1,
+// xor 2), then row_half_mirror (lane i <- 7 - i within eight) and row_mirror
+// (i <- 15 - i).  Every lane of the row ends with the same value (each step
+// adds the same two numbers, only in swapped order).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
   return v;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, in a fixed order, the same value in every lane.
+__device__ __forceinline__ double wsum(double v) {
+  v = row_sum16(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Position of (u, v), u <= v, in the packed upper triangle of an M x M matrix.
@@ -74,22 +100,21 @@ __device__ __forceinline__ void apply_b(const double (&a)[M], double (&Ba)[M]) {
   }
 }
 
-// x' G y with row i of G held by lane i of each 16-lane group (zero rows on
-// lanes i >= M); the sum over the group is taken by a butterfly and then
-// read from the group's first lane, so every lane of the work-group holds
-// the same value.
+// x' G y with row i of G held by lane i of each 16-lane row (zero rows on
+// lanes i >= M); every lane of the work-group ends with the same value.
 __device__ __forceinline__ double quad(const double (&row)[M], int r16, const double (&x)[M],
                                        const double (&y)[M]) {
-  double t = 0.0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
-  for (int j = 0; j < M; ++j) t += row[j] * y[j];
+  for (int j = 0; j < M; j += 3) {
+    t0 += row[j] * y[j];
+    if (j + 1 < M) t1 += row[j + 1] * y[j + 1];
+    if (j + 2 < M) t2 += row[j + 2] * y[j + 2];
+  }
   double xi = 0.0;
 #pragma unroll
   for (int m = 0; m < M; ++m) xi = r16 == m ? x[m] : xi;
-  double v = xi * t;
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-  return __shfl(v, 0, 16);
+  return row_sum16(xi * ((t0 + t1) + t2));
 }
 
 __global__ void k_ca_sq(CaDev d, const int32_t* __restrict__ rowptr, const double* __restrict__ Kval) {
@@ -160,6 +185,8 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
   __shared__ double gs[NG];
   __shared__ double sd[T];
   __shared__ double sh[2 * kW];
+  __shared__ double cf[3 * M + 1];  // a, c, e and ||r||^2 from wave 0
+  __shared__ int cfi[3];            // steps taken, stop, NaN
   const int t = blockIdx.x;
   const int o0 = d.own_off[t], no = d.own_off[t + 1] - o0;
   const int e0 = d.ext_off[t], ne = d.ext_off[t + 1] - e0;
@@ -295,51 +322,78 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
       if (lane == 0 && kk < NG) gs[kk] = a;
     }
     __syncthreads();
-    const int r16 = lane & 15;
-    double grow[M], gdrow[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int pk = r16 <= j ? upk(r16, j) : upk(j, r16);
-      grow[j] = r16 < M ? gs[pk] : 0.0;
-      gdrow[j] = r16 < M ? gs[NU + pk] : 0.0;
-    }
-    // (4) the s CG steps on coefficient vectors (every thread, same values)
+    // (4) the s CG steps on coefficient vectors, on wave 0 (the others wait;
+    // a wave64 FP64 instruction holds its SIMD for four cycles, so the serial
+    // steps are run once), results through LDS
     const int it0 = (o - 2) * S;
     const int nin = min(S, max_iter - it0);
+    if (wv == 0) {
+      const int r16 = lane & 15;
+      double grow[M], gdrow[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int pk = r16 <= j ? upk(r16, j) : upk(j, r16);
+        grow[j] = r16 < M ? gs[pk] : 0.0;
+        gdrow[j] = r16 < M ? gs[NU + pk] : 0.0;
+      }
+      double a[M], c[M], e[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) a[m] = c[m] = e[m] = 0.0;
+      a[0] = 1.0;
+      c[S + 1] = 1.0;
+      double rz = quad(grow, r16, c, c);
+      bool fin = false, nan = false;
+      double rr = 0.0;
+      const double tol2bb = tol * tol * bb_prev;  // ||r|| <= tol ||b||
+      int j = 0;
+      while (j < nin) {
+        double Ba[M];
+        apply_b(a, Ba);
+        const double al = rz / quad(grow, r16, a, Ba);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          e[m] += al * a[m];
+          c[m] -= al * Ba[m];
+        }
+        ++j;
+        rr = quad(gdrow, r16, c, c);
+        nan = !isfinite(rr) || !isfinite(al);
+        if (nan || fabs(rr) <= tol2bb) {
+          fin = true;
+          break;
+        }
+        const double rzn = quad(grow, r16, c, c);
+        const double be = rzn / rz;
+        rz = rzn;
+#pragma unroll
+        for (int m = 0; m < M; ++m) a[m] = c[m] + be * a[m];
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          cf[m] = a[m];
+          cf[M + m] = c[m];
+          cf[2 * M + m] = e[m];
+        }
+        cf[3 * M] = rr;
+        cfi[0] = j;
+        cfi[1] = fin ? 1 : 0;
+        cfi[2] = nan ? 1 : 0;
+      }
+    }
+    __syncthreads();
     double a[M], c[M], e[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) a[m] = c[m] = e[m] = 0.0;
-    a[0] = 1.0;
-    c[S + 1] = 1.0;
-    double rz = quad(grow, r16, c, c);
-    bool fin = false, nan = false;
-    double rel = 0.0;
-    int j = 0;
-    while (j < nin) {
-      double Ba[M];
-      apply_b(a, Ba);
-      const double al = rz / quad(grow, r16, a, Ba);
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        e[m] += al * a[m];
-        c[m] -= al * Ba[m];
-      }
-      ++j;
-      const double rr = quad(gdrow, r16, c, c);
-      rel = bb_prev > 0.0 ? sqrt(fabs(rr) / bb_prev) : 0.0;
-      nan = !isfinite(rel) || !isfinite(al);
-      if (nan || rel <= tol) {
-        fin = true;
-        break;
-      }
-      const double rzn = quad(grow, r16, c, c);
-      const double be = rzn / rz;
-      rz = rzn;
-#pragma unroll
-      for (int m = 0; m < M; ++m) a[m] = c[m] + be * a[m];
+    for (int m = 0; m < M; ++m) {
+      a[m] = cf[m];
+      c[m] = cf[M + m];
+      e[m] = cf[2 * M + m];
     }
+    const double rr = cf[3 * M];
+    const int j = cfi[0];
+    const bool fin = cfi[1] != 0, nan = cfi[2] != 0;
     if (t == 0 && tid == 0) {
-      sc[0].rel = rel;
+      sc[0].rel = bb_prev > 0.0 ? sqrt(fabs(rr) / bb_prev) : 0.0;
       if (fin) {
         sc[0].done_stamp = my_stamp;
         sc[0].iters = it0 + j;
@@ -384,6 +438,20 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
 
   // (6) matrix powers from LDS: level j of the p-block on distance <= s - j,
   // of the r-block on distance <= s - 1 - j
+  // the first 8 entries of the thread's rows tid and tid + T, held in
+  // registers over all passes (rows <= EXT = 2 T)
+  int rc[2][8];
+  double rv[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = tid + h * T;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool ok = r < rows && u < wd;
+      rc[h][u] = ok ? scol[u * rows + r] : 0;
+      rv[h][u] = ok ? sval[u * rows + r] : 0.0;
+    }
+  }
   for (int j = 1; j <= S; ++j) {
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
@@ -393,11 +461,22 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
       const double* src = lv + (base + j - 1) * LDE;
       const double* src2 = lv + (base + (j >= 2 ? j - 2 : 0)) * LDE;  // read only for j >= 2
       double* dst = lv + (base + j) * LDE;
-      // two rows per thread in flight; per batch of 8 entries the index and
-      // value reads, then the gathers (the sum keeps the row order)
-      for (int r0 = tid; r0 < nrow; r0 += 2 * T) {
+      {
+        const int r0 = tid;
         double y[2] = {0.0, 0.0};
-        for (int k0 = 0; k0 < wd; k0 += 8) {
+        {
+          double xs[2][8];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xs[h][u] = src[rc[h][u]];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) y[h] += rv[h][u] * xs[h][u];
+        }
+        // entries beyond the first 8 (wider rows), per batch of 8
+        for (int k0 = 8; k0 < wd; k0 += 8) {
           int cc[2][8];
           double va[2][8], xs[2][8];
 #pragma unroll
@@ -447,8 +526,11 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) ag[i][j] = ad[i][j] = 0.0;
-#pragma unroll 2
-    for (int k = lane; k < no; k += 64) {
+    // every own node slot of the lane (at most T / 64), all reads issued together
+#pragma unroll
+    for (int q = 0; q < T / 64; ++q) {
+      const int k = lane + 64 * q;
+      if (k >= no) continue;
       double xu[3], xw[3];
       const double dk = sd[k];
 #pragma unroll
@@ -490,6 +572,7 @@ __global__ void k_ca_final(CaDev d, double* __restrict__ x) {
 
 static_assert(kCaM == 9 && kCaThreads >= 6 * 64, "Gram partials: six waves, 3 x 3 blocks");
 static_assert(kCaExtMax <= 65535, "local column indices are 16-bit");
+static_assert(kCaExtMax <= 2 * kCaThreads, "the matrix powers give each thread at most two rows");
 
 void launch_ca_setup(const CaDev& d, const int32_t* rowptr, const double* Kval, hipStream_t s) {
   k_ca_sq<<<(d.n + 255) / 256, 256, 0, s>>>(d, rowptr, Kval);
