@@ -336,6 +336,23 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
         grow[j] = r16 < M ? gs[pk] : 0.0;
         gdrow[j] = r16 < M ? gs[NU + pk] : 0.0;
       }
+      // row r16 of G B, so that p'A^p = a'G(Ba) is a quadratic form in a
+      // alone and B a leaves the critical path
+      double gbrow[M];
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        const int off = blk == 0 ? 0 : S + 1, nb = blk == 0 ? S + 1 : S;
+#pragma unroll
+        for (int jj = 0; jj < nb; ++jj) {
+          const int J = off + jj;
+          double v = 0.0;
+          if (jj + 1 < nb) {
+            v = jj == 0 ? grow[off] + grow[off + 1]
+                        : grow[J] + 0.5 * (grow[J + 1] + grow[J - 1]);
+          }
+          gbrow[J] = v;
+        }
+      }
       double a[M], c[M], e[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) a[m] = c[m] = e[m] = 0.0;
@@ -345,28 +362,35 @@ k_ca_outer(CaDev d, Scal* sc, int o, double tol, int max_iter, int my_stamp) {
       bool fin = false, nan = false;
       double rr = 0.0;
       const double tol2bb = tol * tol * bb_prev;  // ||r|| <= tol ||b||
+      // the four steps unrolled (guarded by the step budget and the stop), so
+      // that the entries of a, c, e still zero at each step fold away
       int j = 0;
-      while (j < nin) {
-        double Ba[M];
-        apply_b(a, Ba);
-        const double al = rz / quad(grow, r16, a, Ba);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          e[m] += al * a[m];
-          c[m] -= al * Ba[m];
-        }
-        ++j;
-        rr = quad(gdrow, r16, c, c);
-        nan = !isfinite(rr) || !isfinite(al);
-        if (nan || fabs(rr) <= tol2bb) {
-          fin = true;
-          break;
-        }
-        const double rzn = quad(grow, r16, c, c);
-        const double be = rzn / rz;
-        rz = rzn;
+      for (int jj = 0; jj < S; ++jj) {
+        if (jj < nin && !fin) {
+          const double den = quad(gbrow, r16, a, a);
+          double Ba[M];
+          apply_b(a, Ba);
+          const double inv_rz = 1.0 / rz;
+          const double al = rz / den;
 #pragma unroll
-        for (int m = 0; m < M; ++m) a[m] = c[m] + be * a[m];
+          for (int m = 0; m < M; ++m) {
+            e[m] += al * a[m];
+            c[m] -= al * Ba[m];
+          }
+          j = jj + 1;
+          rr = quad(gdrow, r16, c, c);
+          const double rzn = quad(grow, r16, c, c);
+          nan = !isfinite(rr) || !isfinite(al);
+          if (nan || fabs(rr) <= tol2bb) {
+            fin = true;
+          } else {
+            const double be = rzn * inv_rz;
+            rz = rzn;
+#pragma unroll
+            for (int m = 0; m < M; ++m) a[m] = c[m] + be * a[m];
+          }
+        }
       }
       if (lane == 0) {
 #pragma unroll
