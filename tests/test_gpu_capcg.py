@@ -121,6 +121,32 @@ def test_zero_rhs_and_converged_guess():
     assert rel(phi.cpu().numpy(), ref) <= 1e-13
 
 
+def test_nan_status_and_recovery():
+    """A non-finite right-hand side, or a guess whose residual norm
+    overflows, ends the solve at the test of the guess with CGP_ERR_NAN; the
+    next solve on the same context is unaffected."""
+    from paper_1812_00185_amd import _native as N
+
+    w, g, o = make(cavity(129, 1))
+    b = compatible_rhs(o, 6)
+    ref, info = o.poisson(b, np.zeros(o.nc))
+    bad = b.copy()
+    bad[100] = float("nan")
+    with pytest.raises(N.CGPError) as e:
+        g.pcg_solve(g.to_device(bad), g.zeros(o.nc))
+    assert e.value.code == N.CGP_ERR_NAN
+    # finite b, a guess whose residual norm overflows
+    huge = np.zeros(o.nc)
+    huge[7] = 1e308
+    with pytest.raises(N.CGPError) as e:
+        g.pcg_solve(g.to_device(b), g.to_device(huge))
+    assert e.value.code == N.CGP_ERR_NAN
+    phi = g.zeros(o.nc)
+    st = g.pcg_solve(g.to_device(b), phi)
+    assert st["converged"] and st["iters"] == info.iters
+    assert rel(phi.cpu().numpy(), ref) <= TOL64
+
+
 def test_bitwise_reproducible():
     w, g, o = make(cavity(129, 1))
     b = g.to_device(compatible_rhs(o, 9))
