@@ -8,8 +8,8 @@ trajectory differs between any two orders of the arithmetic by up to ~10 %
 in the residual near convergence (measured on the CPU: each algorithm's
 recursive residual equals the true residual of its own iterate), so the stop
 may move by an iteration; the solution bar stays at 1e-10.  Single solves on
-pure-Neumann, natural-boundary and unstructured meshes spanning one to a
-hundred tiles, from zero and from arbitrary guesses; the iteration cap (a
+pure-Neumann, natural-boundary and unstructured meshes spanning one to about
+three hundred tiles, from zero and from arbitrary guesses; the iteration cap (a
 partial block of iterations); edge cases; reproducibility; multi-step
 trajectories."""
 import numpy as np
@@ -57,6 +57,9 @@ SOLVE_CASES = [
     ("cavity33_neumann", lambda: cavity(33, 0)),
     ("cavity129_neumann", lambda: cavity(129, 1)),
     ("cavity257_neumann", lambda: cavity(257, 0)),
+    # 148k unknowns, about 290 tiles: the Gram sums take a second pass over
+    # the partials (more than 192 tiles)
+    ("cavity385_neumann", lambda: cavity(385, 0)),
     ("channel_natural", lambda: channel(1, 0.03)),
     ("disc_neumann", lambda: get_workload("jobelin_disc_chi0")),
 ]
