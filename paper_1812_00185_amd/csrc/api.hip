@@ -1011,6 +1011,8 @@ int cgp_ca_plan_host(int32_t n, const int32_t* rowptr, const int32_t* col, const
   std::vector<int32_t> rp(rowptr, rowptr + n + 1), cl(col, col + rowptr[n]);
   for (int32_t j : cl)
     if (j < 0 || j >= n) return fail(CGP_ERR_INVALID, "column out of range");
+  for (int64_t i = 0; i < 2 * (int64_t)n; ++i)
+    if (!std::isfinite(xy[i])) return fail(CGP_ERR_INVALID, "node coordinates must be finite");
   cgp::CaPlan pl;
   std::string err;
   try {

@@ -1,6 +1,7 @@
 // Host plan of the s-step coarse PCG: tiles, their depth-s neighbourhoods
 // and the local ELL blocks of the matrix powers.
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -144,6 +145,7 @@ std::string ca_plan(int32_t n, const std::vector<int32_t>& rowptr,
     p.max_ext = std::max(p.max_ext, (int)out.size());
     const int32_t rows = cum[s - 1];
     const size_t base = p.ell_col.size();
+    if (base + (size_t)width * rows > (size_t)INT32_MAX) return "plan too large (32-bit ELL offsets)";
     p.ell_col.resize(base + (size_t)width * rows);
     p.ell_slot.resize(base + (size_t)width * rows);
     for (int32_t r = 0; r < rows; ++r) {

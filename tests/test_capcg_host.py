@@ -107,6 +107,10 @@ def test_planner_rejects_bad_graphs(N):
     empty_row[1] = 0
     with pytest.raises(N.CGPError):
         N.ca_plan_host(empty_row, col, xy)
+    nan_xy = np.array(xy, np.float64)
+    nan_xy[4, 1] = np.nan
+    with pytest.raises(N.CGPError):
+        N.ca_plan_host(rowptr, col, nan_xy)
 
 
 def test_option_requires_fp64():
