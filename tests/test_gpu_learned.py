@@ -42,3 +42,13 @@ def test_trained_network_reduces_coarse_iterations():
     # the gain over the method without the network
     assert summ["iters_learned"] <= 0.8 * summ["iters_plain"]
     assert summ["accepted"] >= 0.9
+    # the same weights, guard and coarse solves with the FP64 Jacobi-PCG in
+    # s-step form: the same tolerance, the same iterations (structured mesh)
+    gs = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, precision="fp64",
+             pcg_tol=w.pcg_tol, precond="jacobi_s4")
+    _, s4 = learned.evaluate(gs, gm, theta, w.with_(lid_speed=1.0), steps=120, warm=10)
+    print("[result] s-step: " + ", ".join(f"{k} {v:.4g}" for k, v in s4.items()), flush=True)
+    assert s4["max_res_plain"] <= w.pcg_tol and s4["max_res_learned"] <= w.pcg_tol
+    assert s4["iters_learned"] <= 0.8 * s4["iters_plain"]
+    assert abs(s4["iters_plain"] - summ["iters_plain"]) <= 0.02 * summ["iters_plain"]
+    assert abs(s4["iters_learned"] - summ["iters_learned"]) <= 0.02 * summ["iters_learned"] + 1
