@@ -441,9 +441,17 @@ def main():
                            "collect_s": t1 - t0, "s": t2 - t1, "final_loss": losses_l[-1]}
         ttl["config"] = {"fine_nodes": gl.nf, "coarse_nodes": gl.nc, "levels": wl.levels,
                          "pcg_tol": wl.pcg_tol}
+        # the same weights with the FP64 Jacobi-PCG in s-step form
+        gls = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="fp64",
+                  precond="jacobi_s4", **kl)
+        _, tts = learned.evaluate(gls, glm, theta_l, wl.with_(lid_speed=1.0),
+                                  steps=args.learned_eval, warm=10)
+        ttl["s_step_fp64"] = {k: tts[k] for k in ("iters_plain", "iters_extrap", "iters_learned",
+                                                  "ms_plain", "ms_extrap", "ms_learned",
+                                                  "max_res_plain", "max_res_learned", "accepted")}
         ttt[wl.name] = ttl
         log(f"[bench] {wl.name}: {json.dumps(ttl)}")
-        del gl, glm
+        del gl, glm, gls
 
     calib = None
     if args.pcg_calibration_iters > 0:
