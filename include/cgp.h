@@ -20,10 +20,10 @@
  *    finished.  `stream` is a hipStream_t passed as void* (NULL = the null
  *    stream).  Device work is queued on `stream`; a call returns before it
  *    finishes unless stated otherwise.
- *  - The library allocates no device memory.  cgp_query() reports the size of
- *    the device workspace the caller provides to cgp_assemble(); it also
- *    allocates one small pinned host buffer (hipHostMalloc) per context for
- *    convergence flags.
+ *  - The library allocates no device or pinned host memory.  cgp_query()
+ *    reports the size of the device workspace and of the small page-locked
+ *    host buffer (convergence flags the kernels mirror for the host to poll)
+ *    that the caller provides to cgp_assemble().
  *  - Node numbering of the fine mesh (the only numbering seen at the ABI):
  *    refinement level by level appends the midpoint of every edge in
  *    first-encounter order over (triangle, local edge (0,1), (1,2), (2,0));
@@ -59,7 +59,9 @@ extern "C" {
 
 /* boundary-edge tags (problem statement, Sect. 2.1, Eqs. 3-4) */
 #define CGP_DIRICHLET 1 /* velocity prescribed (Eq. 10); grad(phi).n = 0 (Eq. 13) */
-#define CGP_NATURAL 2   /* traction-free outflow (Eq. 11 with t = 0); phi = 0 (Eq. 14) */
+#define CGP_NATURAL 2   /* traction boundary (Eqs. 4, 11): -p n + nu grad(u) n = t_N,
+                           with t_N given per step (t_nat below) or 0 when
+                           none is given; phi = 0 (Eq. 14)                 */
 
 /* coarse-solve precision */
 #define CGP_FP64 0  /* Jacobi-PCG in FP64 throughout */
@@ -149,6 +151,7 @@ typedef struct cgp_sizes {
   int64_t n_dirichlet;               /* fine velocity-Dirichlet nodes         */
   int64_t n_natural_coarse;          /* coarse phi = 0 nodes                  */
   size_t workspace_bytes;            /* device workspace for cgp_assemble     */
+  size_t host_bytes;                 /* page-locked host buffer for cgp_assemble */
 } cgp_sizes;
 
 /* One linear solve.  iters counts Krylov iterations (inner iterations summed
@@ -206,22 +209,33 @@ int cgp_dirichlet_nodes(const cgp_ctx* ctx, int32_t* nodes_host);
 /* Device set-up: carves `workspace` (device, >= workspace_bytes, 256-byte
  * aligned, caller-owned for the life of the context), uploads the index
  * structures and assembles the constant operators (fine mass matrix; coarse
- * stiffness, divergence, lumped masses; Jacobi diagonals).  Synchronises
- * `stream` before returning.  Errors: CGP_ERR_WORKSPACE, CGP_ERR_HIP. */
-int cgp_assemble(cgp_ctx* ctx, void* workspace, size_t bytes, void* stream);
+ * stiffness, divergence, lumped masses; Jacobi diagonals).  `host` is
+ * page-locked host memory that device kernels can write (hipHostMalloc, or
+ * a pinned allocation of the caller's framework), >= host_bytes, 64-byte
+ * aligned, caller-owned for the life of the context and not touched by the
+ * caller meanwhile: the solver kernels mirror their stopping flags there and
+ * the host reads them after an event.  Synchronises `stream` before
+ * returning.  Errors: CGP_ERR_WORKSPACE, CGP_ERR_HIP. */
+int cgp_assemble(cgp_ctx* ctx, void* workspace, size_t bytes, void* host, size_t host_bytes,
+                 void* stream);
 
 /* Step 1 (Eq. 21): solves
- *   (3/2 M + dt N(w) + dt nu K) U~ = -dt G P + dt M F + 2 M U - 1/2 M U_prev,
+ *   (3/2 M + dt N(w) + dt nu K) U~ = -dt G P + dt M F + dt B T + 2 M U - 1/2 M U_prev,
  *   w = 2 U - U_prev, with U~ = u_dir at the Dirichlet nodes (Eq. 10),
  * by right-Jacobi-preconditioned BiCGSTAB from U~ = w (u_dir at the
  * Dirichlet nodes), stopping when
- * ||r|| <= mom_tol ||rhs||.  u_prev, u, u_tilde: device [2][N_f]; p device
+ * ||r|| <= mom_tol ||rhs||.  B T is the traction term of Eq. 11 (Eqs. 4, 8):
+ * B the P1 boundary mass matrix of the CGP_NATURAL edges, T the nodal
+ * traction t_N(t^{n+1}); with G = -D^T the weak form's natural condition is
+ * then -P n + nu grad(U~) n = t_N.  u_prev, u, u_tilde: device [2][N_f]; p device
  * [N_f] (not read, and may be NULL, with CGP_SCHEME_NONINCREMENTAL, whose
  * momentum equation has no pressure term); u_dir device [2][n_dirichlet]; f device [2][N_f] or NULL (no
- * forcing).  u_tilde must not alias the inputs.  stats may be NULL; when
+ * forcing); t_nat device [2][N_f] (read at the nodes of natural edges only)
+ * or NULL (traction free; CGP_ERR_INVALID if given without a natural edge).
+ * u_tilde must not alias the inputs.  stats may be NULL; when
  * given, the call synchronises `stream` to fill it. */
 int cgp_momentum(cgp_ctx* ctx, const double* u_prev, const double* u, const double* p,
-                 const double* u_dir, const double* f, double* u_tilde,
+                 const double* u_dir, const double* f, const double* t_nat, double* u_tilde,
                  cgp_solve_stats stats[2], void* stream);
 
 /* Steps 2-3, right-hand side (Eqs. 22-23): b_c = -(3/(2 dt)) Dbar U~ with
@@ -269,11 +283,13 @@ int cgp_correct(cgp_ctx* ctx, const double* u_tilde, const double* phi_f, const 
 /* One whole CGP step (Eqs. 21-26): momentum, restriction, coarse solve from
  * the guess phi_hist[0] (or `guess` when not NULL), prolongation,
  * correction; then rotates the state as described at cgp_state.  u_dir
- * device [2][n_dirichlet] at t^{n+1}; f device [2][N_f] or NULL; guess
+ * device [2][n_dirichlet] at t^{n+1}; f device [2][N_f] or NULL; t_nat
+ * device [2][N_f] at t^{n+1} or NULL (as in cgp_momentum); guess
  * device [N_c] or NULL.  stats may be NULL; when given the call
  * synchronises `stream` to fill it. */
 int cgp_project_step(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const double* f,
-                     const double* guess, cgp_step_stats* stats, void* stream);
+                     const double* t_nat, const double* guess, cgp_step_stats* stats,
+                     void* stream);
 
 /* ---- Learned initial guess for the coarse solve ------------------------
  * Not part of the paper's method: an accelerator of step 3.  A 3-round
@@ -318,6 +334,12 @@ int cgp_net_train_step(cgp_ctx* ctx, float* theta, float* m, float* v, int32_t s
                        const double* b_c, const double* const* hist, const double* target,
                        float* loss, void* stream);
 
+/* The network-free candidate the network refines: q = 3 hist[0] -
+ * 3 hist[1] + hist[2] (quadratic extrapolation of the last three coarse
+ * increments), 0 at the phi = 0 nodes.  hist: host array of 3 (or 4) device
+ * pointers [N_c]; q device [N_c], may not alias them. */
+int cgp_extrapolate(cgp_ctx* ctx, const double* const* hist, double* q, void* stream);
+
 /* Copies whichever of cand and prev (device [N_c]) has the smaller FP64
  * residual against the coarse system (cand on ties) into out; *chose
  * (device int32, may be NULL) receives 0 for cand, 1 for prev. */
@@ -327,7 +349,8 @@ int cgp_guess_guard(cgp_ctx* ctx, const double* b_c, const double* cand, const d
 /* cgp_project_step with the guarded learned guess for the coarse solve;
  * stats->guess_net reports whether the network's candidate was used. */
 int cgp_project_step_net(cgp_ctx* ctx, cgp_state* state, const double* u_dir, const double* f,
-                         const float* theta, cgp_step_stats* stats, void* stream);
+                         const double* t_nat, const float* theta, cgp_step_stats* stats,
+                         void* stream);
 
 /* Device buffers of the last step's intermediates (read-only views into the
  * workspace, valid until the next call on ctx): U~ [2][N_f], b_c [N_c],
@@ -405,8 +428,8 @@ int cgp_ndchol_solve_host(int32_t n, const int32_t* rowptr, const int32_t* col,
 int cgp_ca_plan_host(int32_t n, const int32_t* rowptr, const int32_t* col, const double* xy,
                      int32_t* perm, int32_t* own_off, int32_t* info);
 
-/* Releases host memory and the pinned buffer; the workspace stays the
- * caller's.  Safe on NULL. */
+/* Releases the context's host memory; the workspace and the page-locked
+ * host buffer stay the caller's.  Safe on NULL. */
 void cgp_destroy(cgp_ctx* ctx);
 
 /* Thread-local description of the last error (never NULL). */

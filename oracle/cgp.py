@@ -6,7 +6,12 @@ to (U^{n+1}, P^{n+1}, Phi_c^{n+1}):
   1. momentum (Eq. 21):
        (3/2 M + dt N(w) + dt nu K) U~ = -dt G P^n + dt M F + 2 M U^n - 1/2 M U^{n-1},
        w = 2 U^n - U^{n-1} (extrapolated convecting velocity, Eq. 9);
-       Dirichlet rows replaced by U~ = u_D(t^{n+1}) (Eq. 10).
+       Dirichlet rows replaced by U~ = u_D(t^{n+1}) (Eq. 10); the traction
+       t_N(t^{n+1}) of Eq. 11 on the natural edges adds dt B T to the
+       right-hand side (B the P1 boundary mass matrix of those edges, T the
+       nodal traction), so that the weak form's natural condition is
+       -p^n n + nu grad(u~) n = t_N (the boundary part of -G P^n supplies
+       -p^n n).
   2.-3. restriction and coarse Poisson (Eqs. 22-23):
        K_c Phi_c = -(3/(2 dt)) Dbar U~, with Phi_c = 0 at natural-boundary
        nodes (Eq. 14, rows and columns removed) and the natural condition of
@@ -152,8 +157,10 @@ class OracleCGP:
                      np.array(P, np.float64), np.zeros((4, self.nc)))
 
     # ---- the six steps ---------------------------------------------------
-    def momentum_system(self, U_prev, U, P, uD, F=None):
-        """Matrix and right-hand sides of Eq. 21 with the Dirichlet rows set."""
+    def momentum_system(self, U_prev, U, P, uD, F=None, T=None):
+        """Matrix and right-hand sides of Eq. 21 with the Dirichlet rows set;
+        T: nodal traction [2, N_f] on the natural edges (Eq. 11), or None
+        (traction free)."""
         dt = self.dt
         w = 2.0 * U - U_prev
         A = (self.A_const + dt * self.F.convection(w[0], w[1])).tocsr()
@@ -167,12 +174,14 @@ class OracleCGP:
                 r = r - dt * GP[d]
             if F is not None:
                 r = r + dt * (M @ F[d])
+            if T is not None:
+                r = r + dt * (self.F.B @ T[d])
             r[self.dir] = uD[d]
             rhs[d] = r
         return A, rhs, w
 
-    def momentum(self, U_prev, U, P, uD, F=None):
-        A, rhs, w = self.momentum_system(U_prev, U, P, uD, F)
+    def momentum(self, U_prev, U, P, uD, F=None, T=None):
+        A, rhs, w = self.momentum_system(U_prev, U, P, uD, F, T)
         # initial guess: w, with the Dirichlet values of Eq. 10 imposed
         x0 = w.copy()
         x0[:, self.dir] = uD
@@ -261,8 +270,8 @@ class OracleCGP:
         dp, info = pcg_jacobi(self.F.M, rhs, tol=self.mass_tol, maxit=self.max_iter)
         return P + phi_f + dp, info.iters
 
-    def step(self, st: State, uD, F=None, guess=None) -> StepResult:
-        Ut, mom_its = self.momentum(st.U_prev, st.U, st.P, uD, F)
+    def step(self, st: State, uD, F=None, guess=None, T=None) -> StepResult:
+        Ut, mom_its = self.momentum(st.U_prev, st.U, st.P, uD, F, T)
         b = self.restrict_rhs(Ut)
         g = st.phi_hist[0] if guess is None else guess
         phi_c, pinfo = self.poisson(b, g)
@@ -295,8 +304,9 @@ def build(workload):
 
 
 def run(workload, steps=None, record=None, F=None):
-    """Run a workload from its initial fields; returns (oracle, final state,
-    per-step stats, recorded StepResults at the requested step numbers)."""
+    """Run a workload from its initial fields (its forcing and traction data
+    when it has them, else F); returns (oracle, final state, per-step stats,
+    recorded StepResults at the requested step numbers)."""
     ora = build(workload)
     Um, U0, P0 = workload.initial_fields(ora.fine_xy)
     st = ora.initial_state(Um, U0, P0)
@@ -305,8 +315,11 @@ def run(workload, steps=None, record=None, F=None):
     recs = {}
     allstats = []
     for n in range(nsteps):
-        uD = workload.dirichlet_values(xy_dir, (n + 1) * workload.dt)
-        res = ora.step(st, uD, F)
+        t = (n + 1) * workload.dt
+        uD = workload.dirichlet_values(xy_dir, t)
+        Fw = workload.forcing(ora.fine_xy, t)
+        res = ora.step(st, uD, F if Fw is None else Fw,
+                       T=workload.traction(ora.fine_xy, t))
         st = res.state
         allstats.append(res.stats)
         if record is not None and (n + 1) in record:

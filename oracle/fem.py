@@ -13,6 +13,8 @@ counter-clockwise vertices (x_i, y_i), i = 0, 1, 2:
   D (divergence)   (D U)_i = int psi_i div u_h          (two blocks Dx, Dy)
   G (gradient)     G = -D^T, i.e. (G P)_i = -int p_h div(psi_i)
   N(w) (convection) N_ij = int psi_i (w_h . grad psi_j)
+  B (boundary mass) B_ij = int_{Gamma_N} psi_i psi_j ds  (natural edges only;
+                    on an edge of length L: L/3 on the diagonal, L/6 off it)
 
 Readings: L_p is taken as -K so that Eq. 18 reads K Phi = -(3/(2 dt)) D U
 (the weak form of Eq. 12 with the natural condition Eq. 13); D is the strong
@@ -23,6 +25,8 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+
+from workloads.meshes import NATURAL
 
 
 def element_geometry(xy, tri):
@@ -67,6 +71,22 @@ def element_convection(area, b, c, wx, wy):
     return (sx[:, :, None] * b[:, None, :] + sy[:, :, None] * c[:, None, :]) / 24.0
 
 
+def edge_mass(xy, edges):
+    """[E,2,2]: int_e psi_a psi_b ds on straight edges (a, b) of length L,
+    L (1 + delta_ab) / 6 (the 1-D P1 mass matrix)."""
+    d = xy[edges[:, 1]] - xy[edges[:, 0]]
+    length = np.hypot(d[:, 0], d[:, 1])
+    base = (np.ones((2, 2)) + np.eye(2)) / 6.0
+    return length[:, None, None] * base[None]
+
+
+def assemble_edges(edges, n, emat):
+    """Sum edge matrices [E,2,2] into an n x n CSR matrix."""
+    rows = np.repeat(edges, 2, axis=1).ravel()
+    cols = np.tile(edges, (1, 2)).ravel()
+    return sp.coo_matrix((emat.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+
+
 def assemble(tri, n, emat):
     """Sum element matrices [T,3,3] into an n x n CSR matrix."""
     rows = np.repeat(tri, 3, axis=1).ravel()
@@ -91,6 +111,12 @@ class Operators:
         self.Dy = assemble(self.tri, self.n, ey)
         self.Gx = -self.Dx.T.tocsr()
         self.Gy = -self.Dy.T.tocsr()
+        # boundary mass on the natural (traction) edges: the traction data
+        # t_N of Eqs. 4, 8 and 11 enters the momentum right-hand side as B T
+        bedge = np.asarray(mesh.get("bedge", np.zeros((0, 2))), np.int64).reshape(-1, 2)
+        btag = np.asarray(mesh.get("btag", np.zeros(0)), np.int64)
+        nat = bedge[btag == NATURAL]
+        self.B = assemble_edges(nat, self.n, edge_mass(self.xy, nat))
         # lumped mass m_i = sum over incident elements of |e| / 3
         self.lumped = np.bincount(self.tri.ravel(), weights=np.repeat(self.area / 3.0, 3),
                                   minlength=self.n)

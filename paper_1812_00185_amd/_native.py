@@ -63,7 +63,7 @@ class Sizes(C.Structure):
     _fields_ = [("n_fine", C.c_int64), ("n_coarse", C.c_int64), ("n_fine_tris", C.c_int64),
                 ("n_coarse_tris", C.c_int64), ("nnz_fine", C.c_int64), ("nnz_coarse", C.c_int64),
                 ("n_dirichlet", C.c_int64), ("n_natural_coarse", C.c_int64),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t), ("host_bytes", C.c_size_t)]
 
 
 class SolveStats(C.Structure):
@@ -96,9 +96,11 @@ SIGNATURES = [
     ("cgp_query", C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
     ("cgp_fine_nodes", C.c_int, [C.c_void_p, _dp]),
     ("cgp_dirichlet_nodes", C.c_int, [C.c_void_p, _ip]),
-    ("cgp_assemble", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("cgp_assemble", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                               C.c_void_p]),
     ("cgp_momentum", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats),
+                               C.c_void_p]),
     ("cgp_restrict", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cgp_pcg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats),
                                 C.c_void_p]),
@@ -106,11 +108,12 @@ SIGNATURES = [
     ("cgp_correct", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),
     ("cgp_project_step", C.c_int, [C.c_void_p, C.POINTER(State), C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
+                                   C.c_void_p, C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
     ("cgp_intermediates", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_void_p)]),
     ("cgp_project_step_net", C.c_int, [C.c_void_p, C.POINTER(State), C.c_void_p, C.c_void_p,
-                                       C.c_void_p, C.POINTER(StepStats), C.c_void_p]),
+                                       C.c_void_p, C.c_void_p, C.POINTER(StepStats),
+                                       C.c_void_p]),
     ("cgp_net_init", C.c_int, [C.POINTER(C.c_float), C.c_uint64]),
     ("cgp_net_guess", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p),
                                 C.c_void_p, C.c_void_p]),
@@ -119,6 +122,7 @@ SIGNATURES = [
     ("cgp_net_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                      C.c_float, C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
+    ("cgp_extrapolate", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     ("cgp_guess_guard", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]),
     ("cgp_timing_enable", C.c_int, [C.c_void_p, C.c_int]),

@@ -53,6 +53,10 @@ struct Carver {
   }
 };
 
+// page-locked host buffer the caller provides to cgp_assemble: two chunks of
+// eight mirrored solver-scalar records
+constexpr size_t kHostBytes = sizeof(cgp::Scal) * 16;
+
 }  // namespace
 
 struct cgp_ctx {
@@ -96,7 +100,7 @@ struct cgp_ctx {
   double* part = nullptr;
   Scal* scal = nullptr;
 
-  Scal* pinned = nullptr;  // [2][8] host-pinned copies of the solver scalars
+  Scal* pinned = nullptr;  // [2][8] host-pinned copies of the solver scalars (caller's buffer)
   hipEvent_t ev[2] = {nullptr, nullptr};
 
   // learned initial guess
@@ -376,11 +380,11 @@ int worst(int a, int b) {
 }
 
 int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double* p,
-                 const double* u_dir, const double* f, double* ut, cgp_solve_stats* st,
-                 hipStream_t s) {
+                 const double* u_dir, const double* f, const double* t_nat, double* ut,
+                 cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   cgp::launch_momentum_assemble(c->F, c->dir_index, P.dt, P.nu, u_prev, u, p, u_dir, c->ndir,
-                                f, c->Aval, c->invdA, c->rhs, ut,
+                                f, t_nat, c->Aval, c->invdA, c->rhs, ut,
                                 c->phat, c->shat, s, timer(c, CGP_K_MOM_ASSEMBLE));
   cgp::BicgVecs V{ut, c->r, c->rhat, c->p, c->v, c->phat, c->shat, c->t, c->rhs, c->invdA};
   cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
@@ -782,6 +786,7 @@ int cgp_query(const cgp_ctx* c, cgp_sizes* out) {
   out->n_dirichlet = c->ndir;
   out->n_natural_coarse = c->h.n_nat_c;
   out->workspace_bytes = c->ws_bytes;
+  out->host_bytes = kHostBytes;
   return CGP_OK;
 }
 
@@ -797,11 +802,15 @@ int cgp_dirichlet_nodes(const cgp_ctx* c, int32_t* nodes) {
   return CGP_OK;
 }
 
-int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
+int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_bytes,
+                 void* stream) {
   if (!c) return fail(CGP_ERR_INVALID, "null context");
   if (!ws || bytes < c->ws_bytes)
     return fail(CGP_ERR_WORKSPACE, "workspace missing or smaller than cgp_query().workspace_bytes");
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(CGP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!host || host_bytes < kHostBytes)
+    return fail(CGP_ERR_WORKSPACE, "host buffer missing or smaller than cgp_query().host_bytes");
+  if (reinterpret_cast<uintptr_t>(host) & 63) return fail(CGP_ERR_WORKSPACE, "host buffer must be 64-byte aligned");
   hipStream_t s = as_stream(stream);
   carve(c, ws);
   auto up = [&](void* dst, const void* src, size_t n) -> hipError_t {
@@ -835,10 +844,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
     HIPCHK(up((void*)d.ldir, L.ldir.data(), L.ldir.size()));
     HIPCHK(up((void*)d.lat_of, L.lat_of.data(), 4 * L.lat_of.size()));
   }
-  if (!c->pinned) {
-    HIPCHK(hipHostMalloc((void**)&c->pinned, sizeof(Scal) * 16, hipHostMallocDefault));
-    std::memset(c->pinned, 0, sizeof(Scal) * 16);
-  }
+  c->pinned = static_cast<Scal*>(host);
+  std::memset(c->pinned, 0, kHostBytes);
   for (int k = 0; k < 2; ++k)
     if (!c->ev[k]) HIPCHK(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c->scal, 0, sizeof(Scal) * 8, s));
@@ -898,15 +905,16 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* stream) {
 }
 
 int cgp_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double* p,
-                 const double* u_dir, const double* f, double* u_tilde, cgp_solve_stats st[2],
-                 void* stream) {
+                 const double* u_dir, const double* f, const double* t_nat, double* u_tilde,
+                 cgp_solve_stats st[2], void* stream) {
   if (int rc = check_ready(c)) return rc;
   const bool noninc = c->prob.scheme == CGP_SCHEME_NONINCREMENTAL;
   if (!u_prev || !u || (!p && !noninc) || !u_tilde || (c->ndir && !u_dir))
     return fail(CGP_ERR_INVALID, "null device pointer");
   if (u_tilde == u || u_tilde == u_prev) return fail(CGP_ERR_INVALID, "u_tilde aliases an input");
   hipStream_t s = as_stream(stream);
-  int rc = run_momentum(c, u_prev, u, noninc ? nullptr : p, u_dir, f, u_tilde, st, s);
+  if (t_nat && c->h.n_nat_c == 0) return fail(CGP_ERR_INVALID, "traction given but no boundary is natural");
+  int rc = run_momentum(c, u_prev, u, noninc ? nullptr : p, u_dir, f, t_nat, u_tilde, st, s);
   HIPCHK(hipGetLastError());
   return rc;
 }
@@ -1068,17 +1076,20 @@ namespace {
 
 // One step (Eqs. 21-26); `theta` (learned guess) or `guess` may be given.
 int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
-                 const double* guess, const float* theta, cgp_step_stats* st, void* stream) {
+                 const double* t_nat, const double* guess, const float* theta,
+                 cgp_step_stats* st, void* stream) {
   if (int rc = check_ready(c)) return rc;
   if (!S || !S->u_prev || !S->u || !S->p || (c->ndir && !u_dir))
     return fail(CGP_ERR_INVALID, "null state or boundary pointer");
+  if (t_nat && c->h.n_nat_c == 0) return fail(CGP_ERR_INVALID, "traction given but no boundary is natural");
   for (int k = 0; k < 4; ++k)
     if (!S->phi_hist[k]) return fail(CGP_ERR_INVALID, "null phi_hist pointer");
   hipStream_t s = as_stream(stream);
   cgp_step_stats local{};
   cgp_step_stats* T = st ? st : &local;
   const bool noninc = c->prob.scheme == CGP_SCHEME_NONINCREMENTAL;
-  int rc = run_momentum(c, S->u_prev, S->u, noninc ? nullptr : S->p, u_dir, f, c->ut, T->momentum, s);
+  int rc = run_momentum(c, S->u_prev, S->u, noninc ? nullptr : S->p, u_dir, f, t_nat, c->ut,
+                        T->momentum, s);
   if (rc < 0) return rc;
   run_restrict(c, c->ut, c->bc, s);
   double* phi_new = S->phi_hist[3];
@@ -1156,14 +1167,16 @@ int net_check(cgp_ctx* c, const float* theta, const double* b, const double* con
 extern "C" {
 
 int cgp_project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
-                     const double* guess, cgp_step_stats* st, void* stream) {
-  return project_step(c, S, u_dir, f, guess, nullptr, st, stream);
+                     const double* t_nat, const double* guess, cgp_step_stats* st,
+                     void* stream) {
+  return project_step(c, S, u_dir, f, t_nat, guess, nullptr, st, stream);
 }
 
 int cgp_project_step_net(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
-                         const float* theta, cgp_step_stats* st, void* stream) {
+                         const double* t_nat, const float* theta, cgp_step_stats* st,
+                         void* stream) {
   if (!theta) return fail(CGP_ERR_INVALID, "null network parameters");
-  return project_step(c, S, u_dir, f, nullptr, theta, st, stream);
+  return project_step(c, S, u_dir, f, t_nat, nullptr, theta, st, stream);
 }
 
 int cgp_net_init(float* theta, uint64_t seed) {
@@ -1230,6 +1243,14 @@ int cgp_net_train_step(cgp_ctx* c, float* theta, float* m, float* v, int32_t ste
   return CGP_OK;
 }
 
+int cgp_extrapolate(cgp_ctx* c, const double* const* hist, double* q, void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!hist || !hist[0] || !hist[1] || !hist[2] || !q) return fail(CGP_ERR_INVALID, "null argument");
+  cgp::net::launch_extrapolate(c->nc, hist[0], hist[1], hist[2], c->nat_c, q, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return CGP_OK;
+}
+
 int cgp_guess_guard(cgp_ctx* c, const double* b, const double* cand, const double* prev,
                     double* out, int32_t* chose, void* stream) {
   if (int rc = check_ready(c)) return rc;
@@ -1275,7 +1296,6 @@ void cgp_destroy(cgp_ctx* c) {
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   for (int k = 0; k < 2; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
-  if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
 

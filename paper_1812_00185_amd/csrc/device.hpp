@@ -56,8 +56,8 @@ void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, f
 void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double dt, double nu,
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
-                              double* Aval, double* invdA, double* rhs, double* x0,
-                              double* scratch_w, double* scratch_r, hipStream_t s,
+                              const double* t_nat, double* Aval, double* invdA, double* rhs,
+                              double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
                               hipEvent_t* ev = nullptr);
 
 // ---------------------------------------------------------------- BiCGSTAB (2 rhs)

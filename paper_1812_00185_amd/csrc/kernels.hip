@@ -299,11 +299,18 @@ __global__ void k_momentum_fields(int32_t n32, const double* __restrict__ up,
   }
 }
 
+// kTrac: the traction t_N of Eq. 11 (nodal values tn [2][N]) on the natural
+// edges adds dt int_{Gamma_N} t_h psi_i ds to the right-hand side.  On a free
+// row every boundary slot (i, j) (an edge with one side missing) is a
+// natural edge, since a node on a Dirichlet edge is a Dirichlet row; on an
+// edge of length l the P1 boundary mass gives l (2 t_i + t_j) / 6.
+template <bool kTrac>
 __global__ void __launch_bounds__(kBlock)
 k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
                     const double2* __restrict__ W, const double2* __restrict__ R,
                     const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
-                    double* __restrict__ A, double* __restrict__ invdA, double* __restrict__ rhs,
+                    const double* __restrict__ tn, double* __restrict__ A,
+                    double* __restrict__ invdA, double* __restrict__ rhs,
                     double* __restrict__ x0) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
@@ -331,12 +338,22 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
     const double Pi = p ? p[i] : 0.0;
     const double2 wi = W[i];
     const double wix = wi.x, wiy = wi.y;
-    // dm, dk, dn, rx, ry, gx, gy
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    // dm, dk, dn, rx, ry, gx, gy (, tx, ty: traction)
+    constexpr int NA = kTrac ? 9 : 7;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
       const int j = L.col[s];
       const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
       const double2 pj = L.xy[j];
+      if constexpr (kTrac) {
+        if (sd.x < 0 || sd.y < 0) {  // boundary edge: natural on a free row
+          const double l = sqrt((pj.x - pi.x) * (pj.x - pi.x) + (pj.y - pi.y) * (pj.y - pi.y));
+          acc[7] += l * (2.0 * tn[i] + tn[j]) * (1.0 / 6.0);
+          acc[8] += l * (2.0 * tn[n + i] + tn[n + j]) * (1.0 / 6.0);
+        }
+      }
       const double2 wj = W[j], rj = R[j];
       const double wjx = wj.x, wjy = wj.y;
       const double Pj = p ? p[j] : 0.0;
@@ -361,15 +378,21 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       acc[3] += m * rj.x;
       acc[4] += m * rj.y;
     }
-    group_sum<7>(acc);
+    group_sum<NA>(acc);
     if (lane == 0) {
       const double2 ri = R[i];
       const double bxi = ri.x, byi = ri.y;
       const double aii = 1.5 * acc[0] - dtnu * acc[1] - dt * acc[2];
       A[beg] = aii;
       invdA[i] = 1.0 / aii;
-      rhs[i] = acc[3] + acc[0] * bxi + (dt / 6.0) * acc[5];
-      rhs[n + i] = acc[4] + acc[0] * byi + (dt / 6.0) * acc[6];
+      double rx = acc[3] + acc[0] * bxi + (dt / 6.0) * acc[5];
+      double ry = acc[4] + acc[0] * byi + (dt / 6.0) * acc[6];
+      if constexpr (kTrac) {
+        rx += dt * acc[7];
+        ry += dt * acc[8];
+      }
+      rhs[i] = rx;
+      rhs[n + i] = ry;
       x0[i] = wix;
       x0[n + i] = wiy;
     }
@@ -1319,15 +1342,19 @@ void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, f
 void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double dt, double nu,
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
-                              double* Aval, double* invdA, double* rhs, double* x0,
-                              double* scratch_w, double* scratch_r, hipStream_t s,
+                              const double* t_nat, double* Aval, double* invdA, double* rhs,
+                              double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
                               hipEvent_t* ev) {
   double2* W = reinterpret_cast<double2*>(scratch_w);
   double2* R = reinterpret_cast<double2*>(scratch_r);
   if (ev) (void)hipEventRecord(ev[0], s);
   k_momentum_fields<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L.n, u_prev, u, f, dt, W, R);
-  k_momentum_assemble<<<row_group_grid(L.n), kBlock, 0, s>>>(
-      L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, Aval, invdA, rhs, x0);
+  if (t_nat)
+    k_momentum_assemble<true><<<row_group_grid(L.n), kBlock, 0, s>>>(
+        L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
+  else
+    k_momentum_assemble<false><<<row_group_grid(L.n), kBlock, 0, s>>>(
+        L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs, x0);
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 

@@ -277,6 +277,16 @@ __global__ void k_edge_grad_reduce(const float* __restrict__ part, int nblk,
 }
 
 // ---------------------------------------------------------------- features, decoder, loss
+// The network-free quadratic extrapolation of the history that the network
+// refines, q = 3 phi^n - 3 phi^{n-1} + phi^{n-2}, zero at the phi = 0 nodes.
+__global__ void __launch_bounds__(kB)
+k_extrapolate(int n, const double* __restrict__ h0, const double* __restrict__ h1,
+              const double* __restrict__ h2, const uint8_t* __restrict__ nat,
+              double* __restrict__ q) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    q[i] = (nat && nat[i]) ? 0.0 : 3.0 * h0[i] - 3.0 * h1[i] + h2[i];
+}
+
 // Per-block partial sums (double) of b^2, e^2, (phi^n)^2, d1^2, d2^2 with
 // e = phi^n - 3 phi^{n-1} + 3 phi^{n-2} - phi^{n-3}, d1 = phi^n - phi^{n-1},
 // d2 = phi^n - 2 phi^{n-1} + phi^{n-2}.
@@ -582,6 +592,11 @@ size_t Buffers::carve(float* base, int n, int nnz) {
   epart = take((size_t)nblocks(n, kB / 32) * 128);
   q = reinterpret_cast<double*>(take(2 * N));
   return used;
+}
+
+void launch_extrapolate(int n, const double* h0, const double* h1, const double* h2,
+                        const uint8_t* nat, double* q, hipStream_t s) {
+  k_extrapolate<<<nblocks(n, kB, 1024), kB, 0, s>>>(n, h0, h1, h2, nat, q);
 }
 
 void launch_edge_features(const DLevel& C, double hbar, const Buffers& B, hipStream_t s) {

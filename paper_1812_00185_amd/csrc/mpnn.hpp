@@ -66,6 +66,9 @@ struct Buffers {
 size_t workspace_floats(int n, int nnz);
 
 void launch_edge_features(const DLevel& C, double hbar, const Buffers& B, hipStream_t s);
+// q = 3 h0 - 3 h1 + h2 (0 where nat[i], nat may be null)
+void launch_extrapolate(int n, const double* h0, const double* h1, const double* h2,
+                        const uint8_t* nat, double* q, hipStream_t s);
 void launch_pack(const float* theta, __bf16* wb, hipStream_t s);
 // scales, the extrapolation B.q, inputs, encoder and the three rounds; Kval:
 // the solver's coarse operator (residual feature); dpart: >= 5 * 1024

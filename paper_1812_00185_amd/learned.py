@@ -139,9 +139,9 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         return phi, chose, st
 
     def extrap_solve():
-        q = 3.0 * hist[0] - 3.0 * hist[1] + hist[2]
-        phi, _ = g.guess_guard(b, q, hist[0])
-        return g.pcg_solve(b, phi)
+        q = g.extrapolate(hist)
+        phi, chose = g.guess_guard(b, q, hist[0])
+        return g.pcg_solve(b, phi), chose
 
     for n in range(steps):
         uD = g.to_device(workload.dirichlet_values(xyd, (n + 1) * workload.dt))
@@ -150,7 +150,7 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         hist = [phis[-k] if len(phis) >= k else zeros for k in range(1, 5)]
         phi_a = hist[0].clone()
         st_a, ms_a = timed(lambda: g.pcg_solve(b, phi_a))
-        st_q, ms_q = timed(extrap_solve)
+        (st_q, chose_q), ms_q = timed(extrap_solve)
         (phi_b, chose, st_b), ms_b = timed(lambda: learned_solve(g))
         (phi_c, _, st_c), ms_c = timed(lambda: learned_solve(gm))
         na = torch.linalg.norm(phi_a)
@@ -158,7 +158,8 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
                         iters_learned=st_b["iters"],
                         iters_learned_mixed=st_c["iters"], outer=st_c["outer_iters"],
                         ms_plain=ms_a, ms_learned=ms_b, ms_learned_mixed=ms_c,
-                        accepted=int(chose.item() == 0), res_plain=st_a["rel_res"],
+                        accepted=int(chose.item() == 0),
+                        accepted_extrap=int(chose_q.item() == 0), res_plain=st_a["rel_res"],
                         res_learned=st_b["rel_res"], res_learned_mixed=st_c["rel_res"],
                         diff=float(torch.linalg.norm(phi_b - phi_a) / na),
                         diff_mixed=float(torch.linalg.norm(phi_c - phi_a) / na)))
@@ -168,7 +169,7 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         phis.append(phi_a)
     tail = rec[warm:] if len(rec) > warm else rec
     keys = ("iters_plain", "iters_extrap", "iters_learned", "iters_learned_mixed", "ms_plain",
-            "ms_extrap", "ms_learned", "ms_learned_mixed", "accepted")
+            "ms_extrap", "ms_learned", "ms_learned_mixed", "accepted", "accepted_extrap")
     summary = {k: float(np.mean([r[k] for r in tail])) for k in keys}
     summary["steps"] = len(tail)
     for k in ("res_plain", "res_learned", "res_learned_mixed", "diff", "diff_mixed"):

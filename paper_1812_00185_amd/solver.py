@@ -99,8 +99,15 @@ class CGP:
         off = (-raw.data_ptr()) % 256
         self._raw = raw
         self.workspace = raw[off:off + nbytes]
+        # page-locked host memory the solver kernels mirror their flags into
+        hbytes = int(self.sizes.host_bytes)
+        hraw = torch.empty(hbytes + 64, dtype=torch.uint8, pin_memory=True)
+        hoff = (-hraw.data_ptr()) % 64
+        self._host_raw = hraw
+        self.host_buffer = hraw[hoff:hoff + hbytes]
         N.check(self.lib.cgp_assemble(self.ctx, C.c_void_p(self.workspace.data_ptr()),
-                                      nbytes, self._stream()))
+                                      nbytes, C.c_void_p(self.host_buffer.data_ptr()), hbytes,
+                                      self._stream()))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -125,7 +132,7 @@ class CGP:
         return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
 
     # -------------------------------------------------------------- entry points
-    def momentum(self, u_prev, u, p, u_dir, f=None, out=None):
+    def momentum(self, u_prev, u, p, u_dir, f=None, out=None, t_nat=None):
         import torch
 
         f64 = torch.float64
@@ -134,8 +141,8 @@ class CGP:
         rc = self.lib.cgp_momentum(
             self.ctx, _ptr(u_prev, f64, 2 * self.nf, "u_prev"), _ptr(u, f64, 2 * self.nf, "u"),
             _ptr(p, f64, self.nf, "p"), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
-            _ptr(f, f64, 2 * self.nf, "f"), _ptr(out, f64, 2 * self.nf, "u_tilde"), st,
-            self._stream())
+            _ptr(f, f64, 2 * self.nf, "f"), _ptr(t_nat, f64, 2 * self.nf, "t_nat"),
+            _ptr(out, f64, 2 * self.nf, "u_tilde"), st, self._stream())
         N.check(rc)
         return out, [s.as_dict() for s in st]
 
@@ -184,23 +191,25 @@ class CGP:
     def new_state(self, U_prev, U, P):
         return StepState(self, U_prev, U, P)
 
-    def step(self, state: "StepState", u_dir, f=None, guess=None, stats=False, theta=None):
+    def step(self, state: "StepState", u_dir, f=None, guess=None, stats=False, theta=None,
+             t_nat=None):
         """One CGP step; with `theta` the coarse solve starts from the guarded
-        learned guess."""
+        learned guess; t_nat: nodal traction [2, N_f] on the natural edges."""
         import torch
 
         f64 = torch.float64
         st = N.StepStats() if stats else None
+        tn = _ptr(t_nat, f64, 2 * self.nf, "t_nat")
         if theta is not None:
             rc = self.lib.cgp_project_step_net(
                 self.ctx, C.byref(state.c), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
-                _ptr(f, f64, 2 * self.nf, "f"),
+                _ptr(f, f64, 2 * self.nf, "f"), tn,
                 _ptr(theta, torch.float32, N.CGP_NET_PARAMS, "theta"),
                 C.byref(st) if st is not None else None, self._stream())
         else:
             rc = self.lib.cgp_project_step(
                 self.ctx, C.byref(state.c), _ptr(u_dir, f64, 2 * self.ndir, "u_dir"),
-                _ptr(f, f64, 2 * self.nf, "f"), _ptr(guess, f64, self.nc, "guess"),
+                _ptr(f, f64, 2 * self.nf, "f"), tn, _ptr(guess, f64, self.nc, "guess"),
                 C.byref(st) if st is not None else None, self._stream())
         N.check(rc)
         state.sync_from_c()
@@ -257,6 +266,18 @@ class CGP:
             _ptr(target, torch.float64, self.nc, "target"), _ptr(loss, f32, 1, "loss"),
             self._stream()))
         return loss
+
+    def extrapolate(self, hist, out=None):
+        """The quadratic extrapolation 3 h0 - 3 h1 + h2 of the newest three
+        increments (the candidate the network refines)."""
+        import torch
+
+        out = self.zeros(self.nc) if out is None else out
+        ptrs = [_ptr(h, torch.float64, self.nc, "hist") for h in hist[:3]]
+        arr = (C.c_void_p * 3)(*[p.value for p in ptrs])
+        N.check(self.lib.cgp_extrapolate(self.ctx, arr, _ptr(out, torch.float64, self.nc, "q"),
+                                         self._stream()))
+        return out
 
     def guess_guard(self, b_c, cand, prev, out=None):
         import torch

@@ -145,6 +145,11 @@ def test_mesh_errors(lib):
     assert rc == 0
     # device calls before cgp_assemble are rejected without touching the GPU
     assert lib.cgp_restrict(ctx, None, None, None) == N.CGP_ERR_INVALID
-    assert lib.cgp_assemble(ctx, None, 0, None) == N.CGP_ERR_WORKSPACE
+    assert lib.cgp_assemble(ctx, None, 0, None, 0, None) == N.CGP_ERR_WORKSPACE
+    # the page-locked host buffer is the caller's too: its size is reported,
+    # and a missing one is rejected before any device work
+    sz = N.Sizes()
+    assert lib.cgp_query(ctx, C.byref(sz)) == 0 and sz.host_bytes >= 64
+    assert lib.cgp_extrapolate(ctx, None, None, None) == N.CGP_ERR_INVALID
     lib.cgp_destroy(ctx)
     lib.cgp_destroy(None)

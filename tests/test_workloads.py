@@ -101,3 +101,48 @@ def test_jobelin_disc_forcing_balances_navier_stokes():
     np.testing.assert_allclose(ux + vy, 0.0, atol=1e-7)
     np.testing.assert_allclose(ut + u * ux + v * uy + pxx - nu * lap[0] - fx, 0.0, atol=1e-5)
     np.testing.assert_allclose(vt + u * vx + v * vy + pyy - nu * lap[1] - fy, 0.0, atol=1e-5)
+
+
+def test_jobelin_open_forcing_and_traction():
+    """The open-boundary Jobelin vortex (Sect. 3.2): the hand-derived forcing
+    balances the Navier-Stokes equations and the traction equals
+    -p n + nu (grad u) n on x = 0 (n = (-1, 0)), both by central differences;
+    the traction is zero away from the natural side."""
+    w = get_workload("jobelin_open_k0")
+    nu, t, h = w.nu, 0.37, 1e-4
+    pts = np.random.default_rng(5).uniform(0.05, 0.95, (40, 2))
+
+    def F(xy, tt):
+        (u, v), p = w.exact(xy, tt)
+        return u, v, p
+
+    ex, ey = np.array([h, 0.0]), np.array([0.0, h])
+    c = F(pts, t)
+    px, mx, py, my = F(pts + ex, t), F(pts - ex, t), F(pts + ey, t), F(pts - ey, t)
+    tp, tm = F(pts, t + h), F(pts, t - h)
+    d = lambda a, b: [(ai - bi) / (2 * h) for ai, bi in zip(a, b)]  # noqa: E731
+    ux, vx, pxx = d(px, mx)
+    uy, vy, pyy = d(py, my)
+    ut, vt, _ = d(tp, tm)
+    lap = [(px[i] + mx[i] + py[i] + my[i] - 4 * c[i]) / h ** 2 for i in range(2)]
+    fx, fy = w.forcing(pts, t)
+    u, v = c[0], c[1]
+    np.testing.assert_allclose(ux + vy, 0.0, atol=1e-7)
+    np.testing.assert_allclose(ut + u * ux + v * uy + pxx - nu * lap[0] - fx, 0.0, atol=1e-5)
+    np.testing.assert_allclose(vt + u * vx + v * vy + pyy - nu * lap[1] - fy, 0.0, atol=1e-5)
+    # traction on x = 0 from one-sided differences into the domain
+    side = np.stack([np.zeros(15), np.linspace(0, 1, 15)], axis=1)
+    inner = side + ex
+    inner2 = side + 2 * ex
+    a0, a1, a2 = F(side, t), F(inner, t), F(inner2, t)
+    dudx = [(-3 * a0[i] + 4 * a1[i] - a2[i]) / (2 * h) for i in range(2)]
+    T = w.traction(side, t)
+    np.testing.assert_allclose(T[0], a0[2] - nu * dudx[0], atol=1e-6)   # -p(-1) + nu u_x(-1)
+    np.testing.assert_allclose(T[1], -nu * dudx[1], atol=1e-6)
+    assert np.all(w.traction(pts, t) == 0.0)
+    # the literal homogeneous condition of Eq. 34 does not hold for this flow
+    assert np.abs(T[0]).max() > 0.5
+    m = w.coarse_mesh()
+    assert set(np.unique(m["btag"])) == {1, 2}
+    nat = m["bedge"][m["btag"] == 2]
+    assert np.all(m["xy"][nat.ravel(), 0] == 0.0)

@@ -12,7 +12,7 @@ from functools import lru_cache
 import numpy as np
 
 from . import flows
-from .meshes import unit_square, channel_cylinder, disc
+from .meshes import NATURAL, unit_square, channel_cylinder, disc
 
 FP64 = 0
 MIXED = 1
@@ -28,7 +28,7 @@ class Workload:
     nu: float
     steps: int
     chi: int                   # 0 standard, 1 rotational
-    flow: str                  # 'taylor_green' | 'cavity' | 'channel' | 'jobelin_disc'
+    flow: str                  # 'taylor_green' | 'cavity' | 'channel' | 'jobelin_disc' | 'jobelin_open'
     precision: int = FP64
     pcg_tol: float = 1e-8
     inner_tol: float = 1e-5
@@ -43,6 +43,7 @@ class Workload:
     channel_h: float = 0.0082
     seed: int = 0
     phase: tuple = (0.0, 0.0)      # Taylor-Green shift (x0, y0): u(x - x0, y - y0, t)
+    natural: tuple = ()            # square sides tagged NATURAL ('left', ...); others DIRICHLET
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -50,7 +51,7 @@ class Workload:
     # ---- input data -----------------------------------------------------
     def coarse_mesh(self) -> dict:
         if self.mesh == "square":
-            return _square(self.coarse_n)
+            return _square(self.coarse_n, tuple(self.natural))
         if self.mesh == "channel":
             return _channel(self.channel_h, self.seed)
         if self.mesh == "disc":
@@ -66,9 +67,10 @@ class Workload:
             um, vm, _ = flows.taylor_green(x, y, -self.dt, self.nu)
             u0, v0, p0 = flows.taylor_green(x, y, 0.0, self.nu)
             return np.stack([um, vm]), np.stack([u0, v0]), p0
-        if self.flow == "jobelin_disc":
-            um, vm, _ = flows.jobelin_disc(xy[:, 0], xy[:, 1], -self.dt)
-            u0, v0, p0 = flows.jobelin_disc(xy[:, 0], xy[:, 1], 0.0)
+        if self.flow in ("jobelin_disc", "jobelin_open"):
+            fn = flows.jobelin_disc if self.flow == "jobelin_disc" else flows.jobelin_open
+            um, vm, _ = fn(xy[:, 0], xy[:, 1], -self.dt)
+            u0, v0, p0 = fn(xy[:, 0], xy[:, 1], 0.0)
             return np.stack([um, vm]), np.stack([u0, v0]), p0
         z = np.zeros(n)
         return np.stack([z, z]), np.stack([z, z]), z.copy()
@@ -84,13 +86,16 @@ class Workload:
             u, v = flows.channel_inflow(x, y)
         elif self.flow == "jobelin_disc":
             u, v, _ = flows.jobelin_disc(x, y, t)
+        elif self.flow == "jobelin_open":
+            u, v, _ = flows.jobelin_open(x, y, t)
         else:
             raise ValueError(self.flow)
         return np.stack([u, v])
 
     def exact(self, xy: np.ndarray, t: float):
-        if self.flow == "jobelin_disc":
-            u, v, p = flows.jobelin_disc(xy[:, 0], xy[:, 1], t)
+        if self.flow in ("jobelin_disc", "jobelin_open"):
+            fn = flows.jobelin_disc if self.flow == "jobelin_disc" else flows.jobelin_open
+            u, v, p = fn(xy[:, 0], xy[:, 1], t)
             return np.stack([u, v]), p
         if self.flow != "taylor_green":
             return None
@@ -99,9 +104,19 @@ class Workload:
 
     def forcing(self, xy: np.ndarray, t: float):
         """[2, N] nodal body force at time t, or None (zero)."""
-        if self.flow != "jobelin_disc":
+        if self.flow == "jobelin_disc":
+            return np.stack(flows.jobelin_disc_forcing(xy[:, 0], xy[:, 1], t, self.nu))
+        if self.flow == "jobelin_open":
+            return np.stack(flows.jobelin_open_forcing(xy[:, 0], xy[:, 1], t, self.nu))
+        return None
+
+    def traction(self, xy: np.ndarray, t: float):
+        """[2, N] nodal traction t_N = -p n + nu grad(u) n of the exact
+        solution on the natural sides at time t (zero at every other node),
+        or None (traction free)."""
+        if self.flow != "jobelin_open" or not self.natural:
             return None
-        return np.stack(flows.jobelin_disc_forcing(xy[:, 0], xy[:, 1], t, self.nu))
+        return flows.jobelin_open_traction(xy, t, self.nu, self.natural)
 
     def _shifted(self, xy):
         """Coordinates shifted by the Taylor-Green phase (a translated exact
@@ -110,12 +125,12 @@ class Workload:
 
 
 @lru_cache(maxsize=8)
-def _square_cached(n):
-    return unit_square(n)
+def _square_cached(n, natural):
+    return unit_square(n, {s: NATURAL for s in natural})
 
 
-def _square(n):
-    m = _square_cached(n)
+def _square(n, natural=()):
+    m = _square_cached(n, natural)
     return {k: v.copy() for k, v in m.items()}
 
 
@@ -163,6 +178,22 @@ WORKLOADS = {
     **{f"jobelin_disc_chi{c}": Workload(f"jobelin_disc_chi{c}", "disc", 0, 2, 1e-2, 0.1, 100, c,
                                         "jobelin_disc", FP64, pcg_tol=1e-10, mom_tol=1e-15)
        for c in (0, 1)},
+    # the paper's Jobelin vortex with an open boundary (Sect. 3.2): unit
+    # square, natural (traction) boundary on x = 0, Dirichlet elsewhere,
+    # Re = 10, dt = 0.01, t = 1, standard scheme; the paper's finest mesh
+    # has 16384 elements and coarsens up to k = 2: 65x65 fine nodes
+    # (8192 triangles) here, with the exact solution's forcing and traction
+    **{f"jobelin_open_k{k}": Workload(f"jobelin_open_k{k}", "square", (64 >> k) + 1, k, 1e-2,
+                                      0.1, 100, 0, "jobelin_open", FP64, pcg_tol=1e-10,
+                                      mom_tol=1e-14, natural=("left",))
+       for k in range(3)},
+    # the paper's Taylor-Green case (Sect. 3.1): Re = 10, dt = 0.00125, t = 1
+    # (800 steps), velocity Dirichlet data of the exact solution on every
+    # side; 129x129 fine nodes (32768 triangles), coarsening k = 0..3
+    **{f"tg_re10_k{k}_chi{c}": Workload(f"tg_re10_k{k}_chi{c}", "square", (128 >> k) + 1, k,
+                                        0.00125, 0.1, 800, c, "taylor_green", FP64,
+                                        pcg_tol=1e-10)
+       for k in range(4) for c in (0, 1)},
     # 2049x2049 Taylor-Green, 3 levels (257x257 pressure mesh), rotational
     "tg2049_k3_fp64": Workload("tg2049_k3_fp64", "square", 257, 3, 2e-4, 0.005, 200, 1,
                                "taylor_green", FP64, pcg_tol=1e-8),

@@ -71,3 +71,57 @@ def jobelin_disc_forcing(x, y, t, nu):
     fx = np.sin(a + b) + np.sin(a) * np.cos(a) - s + 2.0 * nu * np.sin(a) * np.sin(b)
     fy = -np.sin(a + b) - np.sin(b) * np.cos(b) + s + 2.0 * nu * np.cos(a) * np.cos(b)
     return fx, fy
+
+
+def jobelin_open(x, y, t):
+    """The Jobelin vortex of the paper's open-boundary test (Sect. 3.2,
+    Eqs. 31-33) on [0, 1]^2:
+      u = sin(x) sin(y + t),  v = cos(x) cos(y + t),  p = cos(x) sin(y + t),
+    divergence free."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    b = y + t
+    return np.sin(x) * np.sin(b), np.cos(x) * np.cos(b), np.cos(x) * np.sin(b)
+
+
+def jobelin_open_forcing(x, y, t, nu):
+    """f = u_t + (u . grad) u + grad p - nu lap u for jobelin_open (derived by
+    hand with b = y + t: u_t = sin x cos b, v_t = -cos x sin b,
+    (u . grad) u = sin x cos x, (u . grad) v = -sin b cos b,
+    grad p = (-sin x sin b, cos x cos b), lap u = -2 u, lap v = -2 v)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    b = y + t
+    fx = (np.sin(x) * np.cos(b) + np.sin(x) * np.cos(x) - np.sin(x) * np.sin(b)
+          + 2.0 * nu * np.sin(x) * np.sin(b))
+    fy = (-np.cos(x) * np.sin(b) - np.sin(b) * np.cos(b) + np.cos(x) * np.cos(b)
+          + 2.0 * nu * np.cos(x) * np.cos(b))
+    return fx, fy
+
+
+_SIDE_NORMALS = {"left": (-1.0, 0.0), "right": (1.0, 0.0), "bottom": (0.0, -1.0),
+                 "top": (0.0, 1.0)}
+
+
+def _on_side(x, y, side):
+    return {"left": x == 0.0, "right": x == 1.0, "bottom": y == 0.0, "top": y == 1.0}[side]
+
+
+def jobelin_open_traction(xy, t, nu, sides):
+    """[2, N] traction -p n + nu (grad u) n of jobelin_open at the nodes of
+    the given unit-square sides (outward normal n), zero elsewhere.  The
+    velocity gradient by hand: u_x = cos x sin b, u_y = sin x cos b,
+    v_x = -sin x cos b, v_y = -cos x sin b (b = y + t)."""
+    x = np.asarray(xy[:, 0], np.float64)
+    y = np.asarray(xy[:, 1], np.float64)
+    b = y + t
+    p = np.cos(x) * np.sin(b)
+    ux, uy = np.cos(x) * np.sin(b), np.sin(x) * np.cos(b)
+    vx, vy = -np.sin(x) * np.cos(b), -np.cos(x) * np.sin(b)
+    T = np.zeros((2, x.size))
+    for side in sides:
+        nx, ny = _SIDE_NORMALS[side]
+        m = _on_side(x, y, side)
+        T[0, m] = (-p * nx + nu * (ux * nx + uy * ny))[m]
+        T[1, m] = (-p * ny + nu * (vx * nx + vy * ny))[m]
+    return T
