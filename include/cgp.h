@@ -260,6 +260,21 @@ int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream)
 int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stats* stats,
                   void* stream);
 
+/* cgp_pcg_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same FP64 Jacobi-PCG, iterates and stopping test, but its Krylov vectors,
+ * partial sums and solver scalars live in a file-scope device array of the
+ * library (one per GPU, about 7.5 MB, held until the process ends) instead
+ * of the context's workspace.  The call allocates nothing, host or device.
+ * Requires coarse_precond CGP_PRECOND_JACOBI and precision CGP_FP64
+ * (CGP_ERR_INVALID otherwise) and N_c <= 131072 (CGP_ERR_WORKSPACE
+ * otherwise).  Every context on a GPU shares that GPU's array and it keeps
+ * the last call's contents: calls that overlap on one GPU (two streams, or
+ * two host threads) race and must be serialised by the caller.  Arguments,
+ * results and status as cgp_pcg_solve. */
+int cgp_pcg_solve_noalloc(cgp_ctx* ctx, const double* b_c, double* phi_c,
+                          cgp_solve_stats* stats, void* stream);
+
 /* Step 4 (Eq. 24): phi_f = P phi_c, linear interpolation applied k times
  * (each fine node is the coarse P1 function evaluated there; dyadic weights).
  * FP64 on both precision paths: the velocity correction differentiates

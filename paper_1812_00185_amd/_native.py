@@ -104,6 +104,8 @@ SIGNATURES = [
     ("cgp_restrict", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cgp_pcg_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveStats),
                                 C.c_void_p]),
+    ("cgp_pcg_solve_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(SolveStats), C.c_void_p]),
     ("cgp_prolong", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cgp_correct", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.POINTER(SolveStats), C.c_void_p]),

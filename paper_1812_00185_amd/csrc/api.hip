@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,10 @@
 
 using cgp::DLevel;
 using cgp::Scal;
+
+// The no-alloc scratch (see cgp_pcg_solve_noalloc): 7.5 MB per GPU.
+constexpr size_t kScratchDoubles = 128 + 8 * 2 * 1024 + 7 * 131072;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -56,6 +61,47 @@ struct Carver {
 // page-locked host buffer the caller provides to cgp_assemble: two chunks of
 // eight mirrored solver-scalar records
 constexpr size_t kHostBytes = sizeof(cgp::Scal) * 16;
+
+// ---- device scratch of cgp_pcg_solve_noalloc ----------------------------
+// The FP64 Jacobi-PCG's Krylov vectors (p and the alternating r, w, s),
+// partial sums and solver scalars for callers that cannot allocate: one
+// file-scope array per GPU, alive until the process ends.  Layout in
+// doubles: scalars [0, 128), partial sums [128, 128 + kSlots * 2 * kNbMax),
+// then seven vectors of kNoAllocMaxRows entries (every piece 256-byte
+// aligned).  In host code the array's name is only a stand-in: kernels get
+// the device address that hipGetSymbolAddress returns for the current GPU.
+constexpr int32_t kNoAllocMaxRows = 131072;
+constexpr size_t kScrScal = 0;
+constexpr size_t kScrPart = 128;
+constexpr size_t kScrVec = kScrPart + (size_t)cgp::kSlots * 2 * cgp::kNbMax;
+constexpr size_t kScrDoubles = kScrVec + 7 * (size_t)kNoAllocMaxRows;
+static_assert(sizeof(cgp::Scal) * 8 <= kScrPart * sizeof(double), "scalar slots");
+static_assert((kScrVec * sizeof(double)) % 256 == 0, "vector alignment");
+static_assert((kNoAllocMaxRows * sizeof(double)) % 256 == 0, "vector alignment");
+static_assert(kScrDoubles == kScratchDoubles, "scratch size");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current GPU (looked up once per device).
+int scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CGP_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CGP_ERR_INVALID, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CGP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return CGP_OK;
+}
 
 }  // namespace
 
@@ -125,6 +171,10 @@ struct cgp_ctx {
   // s-step Jacobi-PCG (CGP_PRECOND_JACOBI_S4): host plan and device view
   cgp::CaPlan ca;
   cgp::CaDev cad{};
+
+  // device address of the no-alloc scratch on the context's GPU (set by
+  // cgp_assemble)
+  double* scratch_dev = nullptr;
 
   // measurement hook (cgp_timing_enable)
   int timed_id = 0;
@@ -476,6 +526,40 @@ int run_pcg_nd(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipS
   return rc;
 }
 
+// Krylov vectors, partial sums and scalars of the FP64 Jacobi-PCG: the
+// context's workspace, or the file-scope scratch of cgp_pcg_solve_noalloc.
+struct JacobiBufs {
+  double* p;
+  double* r[2];
+  double* w[2];
+  double* s[2];
+  double* part;
+  Scal* scal;
+  bool timed;  // honour cgp_timing_enable (its events are created on demand)
+};
+
+// FP64 Jacobi-PCG in the single-reduction form from the guess in x, one
+// launch per iteration, the stopping flags polled one chunk behind.
+int jacobi_pcg64(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s,
+                 const JacobiBufs& B) {
+  const cgp_problem& P = c->prob;
+  cgp::PcgVecs<double> V{x,          B.p,         {B.r[0], B.r[1]},
+                         {B.w[0], B.w[1]},        {B.s[0], B.s[1]},
+                         b,          c->invdKc,   c->Kc,
+                         c->ell_col, c->ell_sval, c->ell_w};
+  cgp::launch_pcg_init<double>(c->C, V, false, B.scal, B.part, c->nb_c, s);
+  Scal out[1];
+  int rc = drive(c, B.scal, 1, P.max_iter + 1, 32, true,
+                 [&](int it, bool chk) {
+                   cgp::launch_pcg_iter<double>(
+                       c->C, V, B.scal, B.part, c->nb_c, it, P.pcg_tol, chk, s,
+                       (chk || !B.timed) ? nullptr : timer(c, CGP_K_COARSE_SPMV));
+                 },
+                 s, out);
+  if (rc) return rc;
+  return stats_status(out, 1, P.max_iter, st);
+}
+
 int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   int rc = CGP_OK;
@@ -499,20 +583,10 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
     cgp::launch_ca_final(d, x, s);
     rc = stats_status(out, 1, P.max_iter, st);
   } else if (P.precision == CGP_FP64) {
-    cgp::PcgVecs<double> V{x,          c->cp,       {c->cr2[0], c->cr2[1]},
-                           {c->cw2[0], c->cw2[1]}, {c->cs2[0], c->cs2[1]},
-                           b,          c->invdKc,   c->Kc,
-                           c->ell_col, c->ell_sval, c->ell_w};
-    cgp::launch_pcg_init<double>(c->C, V, false, c->scal, c->part, c->nb_c, s);
-    Scal out[1];
-    rc = drive(c, c->scal, 1, P.max_iter + 1, 32, true,
-               [&](int it, bool chk) {
-                 cgp::launch_pcg_iter<double>(c->C, V, c->scal, c->part, c->nb_c, it, P.pcg_tol,
-                                              chk, s, chk ? nullptr : timer(c, CGP_K_COARSE_SPMV));
-               },
-               s, out);
-    if (rc) return rc;
-    rc = stats_status(out, 1, P.max_iter, st);
+    const JacobiBufs B{c->cp,    {c->cr2[0], c->cr2[1]}, {c->cw2[0], c->cw2[1]},
+                       {c->cs2[0], c->cs2[1]}, c->part, c->scal, true};
+    rc = jacobi_pcg64(c, b, x, st, s, B);
+    if (rc == CGP_ERR_HIP) return rc;
   } else {
     // FP64 iterative refinement around FP32-inner Jacobi-PCG.  A correction
     // that does not halve the FP64 residual (the inner solve went below what
@@ -846,6 +920,7 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
   }
   c->pinned = static_cast<Scal*>(host);
   std::memset(c->pinned, 0, kHostBytes);
+  if (int rc = scratch_address(&c->scratch_dev)) return rc;
   for (int k = 0; k < 2; ++k)
     if (!c->ev[k]) HIPCHK(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c->scal, 0, sizeof(Scal) * 8, s));
@@ -932,6 +1007,39 @@ int cgp_pcg_solve(cgp_ctx* c, const double* b, double* phi, cgp_solve_stats* st,
   if (!b || !phi) return fail(CGP_ERR_INVALID, "null device pointer");
   if (b == phi) return fail(CGP_ERR_INVALID, "b_c and phi_c alias");
   int rc = run_pcg(c, b, phi, st, as_stream(stream));
+  HIPCHK(hipGetLastError());
+  return rc;
+}
+
+int cgp_pcg_solve_noalloc(cgp_ctx* c, const double* b, double* phi, cgp_solve_stats* st,
+                          void* stream) {
+  if (int rc = check_ready(c)) return rc;
+  if (!b || !phi) return fail(CGP_ERR_INVALID, "null device pointer");
+  if (b == phi) return fail(CGP_ERR_INVALID, "b_c and phi_c alias");
+  if (c->prob.coarse_precond != CGP_PRECOND_JACOBI || c->prob.precision != CGP_FP64)
+    return fail(CGP_ERR_INVALID,
+                "cgp_pcg_solve_noalloc: needs coarse_precond CGP_PRECOND_JACOBI and CGP_FP64");
+  if (c->nc > kNoAllocMaxRows)
+    return fail(CGP_ERR_WORKSPACE, "cgp_pcg_solve_noalloc: " + std::to_string(c->nc) +
+                                       " coarse unknowns exceed the scratch maximum of " +
+                                       std::to_string(kNoAllocMaxRows));
+  if (!c->scratch_dev) return fail(CGP_ERR_INVALID, "no scratch address (cgp_assemble)");
+  hipStream_t s = as_stream(stream);
+  double* base = c->scratch_dev;
+  const size_t n = kNoAllocMaxRows;
+  double* v = base + kScrVec;
+  // every vector entry read is written first in the same solve, the partial
+  // sums are stored by every block before they are summed, and the start
+  // kernel resets the scalars: no clearing is needed
+  const JacobiBufs B{v, {v + n, v + 2 * n}, {v + 3 * n, v + 4 * n}, {v + 5 * n, v + 6 * n},
+                     base + kScrPart, reinterpret_cast<Scal*>(base + kScrScal), false};
+  if (c->h.n_nat_c) cgp::launch_zero_masked(phi, c->nat_c, c->nc, s);
+  int rc = jacobi_pcg64(c, b, phi, st, s, B);
+  if (rc == CGP_ERR_HIP) return rc;
+  if (c->h.n_nat_c == 0) {
+    cgp::launch_weighted_sums(c->nc, phi, c->lumped_c, B.part, c->nb_c, s);
+    cgp::launch_remove_mean(c->nc, phi, B.part, c->nb_c, c->lumped_c, s);
+  }
   HIPCHK(hipGetLastError());
   return rc;
 }

@@ -165,6 +165,18 @@ class CGP:
         N.check(rc)
         return st.as_dict()
 
+    def pcg_solve_noalloc(self, b_c, phi_c):
+        """pcg_solve through the entry point that allocates nothing (its
+        Krylov vectors in the library's per-GPU scratch array)."""
+        import torch
+
+        st = N.SolveStats()
+        rc = self.lib.cgp_pcg_solve_noalloc(
+            self.ctx, _ptr(b_c, torch.float64, self.nc, "b_c"),
+            _ptr(phi_c, torch.float64, self.nc, "phi_c"), C.byref(st), self._stream())
+        N.check(rc)
+        return st.as_dict()
+
     def prolong(self, phi_c, out=None):
         import torch
 
