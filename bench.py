@@ -32,7 +32,11 @@ workload and on the 257 x 257 lid-driven cavity with a 129 x 129 pressure
 mesh (the learned guess's own workload: trained on lid speeds U[0.5, 1.5],
 evaluated on a fresh U = 1 run), the roofline position of the dominant
 kernel (HIP events over the timed region), the CPU oracle timed on a bounded
-sample and the parity of the first step against that oracle step are
+sample (the first --parity-steps steps), the parity of the main and the plain
+form against that oracle prefix at every step and of every form's first step,
+and the other configurations (33 x 33 Taylor-Green, the 257 x 257 cavity at
+k = 0..3 in both schemes, plain FP64 and mixed, the channel with the
+cylinder, mixed and FP64), each timed and checked against the oracle, are
 reported beside it in the same JSON line.
 """
 from __future__ import annotations
@@ -130,10 +134,12 @@ FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
               "s4_fp64": ("consistent", "pcg", "incremental")}
 
 
-def cpu_baseline(w, g_fine_xy, first_steps):
-    """Oracle (as it stands) on one step of the same workload, single thread;
-    returns the baseline record and the parity of each form's first GPU step
-    against the oracle's."""
+def cpu_baseline(w, g_fine_xy, first_steps, prefixes, nprefix):
+    """The oracle (as it stands), single thread, over the first `nprefix`
+    steps of the same workload from its initial fields: its throughput is
+    the CPU baseline, and its states give the parity of the GPU forms that
+    ran the same prefix (every step) and of every form's first step (each
+    against the oracle configured like it)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.cgp import build as build_oracle
@@ -142,16 +148,31 @@ def cpu_baseline(w, g_fine_xy, first_steps):
         t0 = time.perf_counter()
         ora = build_oracle(w)
         t_setup = time.perf_counter() - t0
-        st = ora.initial_state(*w.initial_fields(ora.fine_xy))
-        uD = w.dirichlet_values(ora.fine_xy[ora.dir], w.dt)
+        st0 = ora.initial_state(*w.initial_fields(ora.fine_xy))
+        uD1 = w.dirichlet_values(ora.fine_xy[ora.dir], w.dt)
+        states, iters = [], []
+        st = st0
         t0 = time.perf_counter()
-        r = ora.step(st, uD)
-        t_step = time.perf_counter() - t0
+        for n in range(nprefix):
+            r = ora.step(st, w.dirichlet_values(ora.fine_xy[ora.dir], (n + 1) * w.dt))
+            st = r.state
+            states.append((st.U, st.P))
+            iters.append(r.stats["pcg_iters"])
+            log(f"[bench] oracle step {n + 1}/{nprefix}")
+        t_steps = time.perf_counter() - t0
     assert np.array_equal(ora.fine_xy, g_fine_xy)
-    parity = {"pcg_iters_oracle": r.stats["pcg_iters"]}
-    # each form against the oracle configured like it (mass matrices of
-    # Eqs. 25-27, coarse solver); the operators of the timed oracle are shared
-    refs = {("consistent", "pcg", "incremental"): r.state}
+    parity = {"pcg_iters_oracle": iters,
+              "bar": "1e-10 relative L2 per field (FP64 forms); 1e-6 (mixed)"}
+    # every step of the prefix, for the forms that ran it
+    for form, traj in prefixes.items():
+        per = [(rel(Ug, Uo), rel(Pg, Po)) for (Ug, Pg), (Uo, Po) in zip(traj, states)]
+        parity[form + "_prefix"] = {
+            "steps": len(per), "u_last": per[-1][0], "p_last": per[-1][1],
+            "u_max": max(d[0] for d in per), "p_max": max(d[1] for d in per),
+            "oracle": "mass=consistent, coarse=pcg, scheme=incremental"}
+    # first step of each form against the oracle configured like it (mass
+    # matrices of Eqs. 25-27, coarse solver); the operators are shared
+    refs = {("consistent", "pcg", "incremental"): states[0]}
     for form, (U_g, P_g) in first_steps.items():
         mode = FORM_MODES.get(form, ("consistent", "pcg", "incremental"))
         if mode not in refs:
@@ -159,16 +180,18 @@ def cpu_baseline(w, g_fine_xy, first_steps):
             o2.mass_mode, o2.coarse_solver, o2.scheme = mode
             if o2.scheme == "nonincremental":
                 o2.chi = 0
-            refs[mode] = o2.step(st, uD).state
-        ref = refs[mode]
-        parity[form] = {"u": rel(U_g, ref.U), "p": rel(P_g, ref.P),
+            s2 = o2.step(st0, uD1).state
+            refs[mode] = (s2.U, s2.P)
+        Uo, Po = refs[mode]
+        parity[form] = {"u": rel(U_g, Uo), "p": rel(P_g, Po),
                         "oracle": f"mass={mode[0]}, coarse={mode[1]}, scheme={mode[2]}"}
     dof = 3 * ora.nf
     return {
-        "value": dof / t_step, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
-        "sample": f"1 step of {w.name} from its initial fields ({t_step:.1f} s; "
-                  f"set-up {t_setup:.1f} s untimed), numpy/scipy FP64, 1 thread",
-        "s_per_step": t_step,
+        "value": dof * nprefix / t_steps, "unit": "DOF*steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"the first {nprefix} steps of {w.name} from its initial fields "
+                  f"({t_steps:.1f} s; set-up {t_setup:.1f} s untimed), numpy/scipy FP64, "
+                  f"1 thread",
+        "s_per_step": t_steps / nprefix,
     }, parity
 
 
@@ -218,6 +241,132 @@ def pcg_calibration(torch, iters, n_side=2049):
     return out
 
 
+def _solver(CGP, w, **over):
+    kw = dict(chi=w.chi, restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol,
+              mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass,
+              precond=w.precond, scheme=w.scheme,
+              precision="fp64" if w.precision == 0 else "mixed")
+    kw.update(over)
+    return CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, **kw)
+
+
+def _leg(torch, CGP, w, steps, warmup, oracle_states, precision):
+    """Times `steps` steps after `warmup` of workload w in the given
+    precision from its initial fields, and compares the first
+    len(oracle_states) steps (run untimed first) with the oracle's."""
+    g = _solver(CGP, w, precision=precision)
+    Um, U0, P0 = w.initial_fields(g.fine_xy)
+    xyd = g.fine_xy[g.dirichlet_nodes]
+    total = warmup + steps
+    uD = [g.to_device(w.dirichlet_values(xyd, (n + 1) * w.dt)) for n in range(total + 1)]
+    out = {"workload": w.name, "precision": precision, "fine_nodes": g.nf,
+           "coarse_nodes": g.nc, "levels": w.levels, "chi": w.chi, "pcg_tol": w.pcg_tol}
+    if oracle_states:
+        sp = g.new_state(Um, U0, P0)
+        per = []
+        for n, (Uo, Po) in enumerate(oracle_states):
+            g.step(sp, uD[n])
+            per.append((rel(sp.U.cpu().numpy(), Uo), rel(sp.P.cpu().numpy(), Po)))
+        bar = 1e-10 if precision == "fp64" else 1e-6
+        out["parity_vs_fp64_oracle"] = {
+            "steps": len(per), "u_first": per[0][0], "p_first": per[0][1],
+            "u_max": max(d[0] for d in per), "p_max": max(d[1] for d in per),
+            "bar": bar, "within_bar": max(max(d) for d in per) <= bar}
+        del sp
+    el, _, _, st, state = run_form(torch, g, uD, (Um, U0, P0), warmup, steps)
+    out.update({"steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps,
+                "dof_steps_per_s": 3 * g.nf * steps / el,
+                "last_step": {"poisson_iters": st["poisson"]["iters"],
+                              "poisson_outer": st["poisson"]["outer_iters"],
+                              "momentum_iters": [m["iters"] for m in st["momentum"]]}})
+    g.close()
+    del g, state, uD
+    torch.cuda.empty_cache()
+    return out
+
+
+def config_legs(torch, which, steps, warmup, with_oracle):
+    """The other configurations of the problem statement, each in the forms
+    it names: 33x33 Taylor-Green (k = 1, FP64 Jacobi-PCG to 1e-10, its whole
+    100-step run compared with the oracle); the 257x257 cavity at k = 0..3,
+    both schemes, plain FP64 and mixed; the channel with the cylinder
+    (k = 2, rotational) mixed and FP64.  Each form is timed over `steps`
+    steps after `warmup`; the first step (config 1: every step) is compared
+    with the FP64 oracle (bar 1e-10; mixed 1e-6)."""
+    from oracle.cgp import build as build_oracle
+    from paper_1812_00185_amd import CGP
+    from workloads import get_workload
+
+    def oracle_prefix(w, n, noisy=False):
+        """The oracle's first n steps; with `noisy` every solver right-hand
+        side carries 1e-15 relative noise (its rounding sensitivity)."""
+        if not with_oracle:
+            return []
+        import oracle.cgp as oc
+
+        pcg, bicg = oc.pcg_jacobi, oc.bicgstab_jacobi
+        if noisy:
+            rng = np.random.default_rng(0)
+
+            def noisy_fn(fn):
+                def f(A, b, **kw):
+                    return fn(A, b * (1 + 1e-15 * rng.standard_normal(b.shape)), **kw)
+                return f
+            oc.pcg_jacobi, oc.bicgstab_jacobi = noisy_fn(pcg), noisy_fn(bicg)
+        try:
+            o = build_oracle(w.with_(precision=0))
+            st = o.initial_state(*w.initial_fields(o.fine_xy))
+            out = []
+            for k in range(n):
+                st = o.step(st, w.dirichlet_values(o.fine_xy[o.dir], (k + 1) * w.dt)).state
+                out.append((st.U, st.P))
+        finally:
+            oc.pcg_jacobi, oc.bicgstab_jacobi = pcg, bicg
+        return out
+
+    def sensitivity(w, ref):
+        """Largest relative change of the oracle's states over the steps of
+        ref when its solver right-hand sides carry 1e-15 noise: no other
+        rounding order can agree with it more closely."""
+        pert = oracle_prefix(w, len(ref), noisy=True)
+        return max(max(rel(a[0], b[0]), rel(a[1], b[1])) for a, b in zip(pert, ref))
+
+    def settle(leg, w, ref):
+        # FP64 forms: 1e-10, or 10x the oracle's own sensitivity where the
+        # trajectory is ill-conditioned (the impulsive channel start)
+        par = leg.get("parity_vs_fp64_oracle")
+        if par and leg["precision"] == "fp64" and not par["within_bar"]:
+            sens = sensitivity(w, ref)
+            par["oracle_sensitivity"] = sens
+            par["bar"] = max(1e-10, 10 * sens)
+            par["within_bar"] = max(par["u_max"], par["p_max"]) <= par["bar"]
+
+    legs = {}
+    if "tg33_k1" in which:
+        w1 = get_workload("tg33_k1")
+        ref1 = oracle_prefix(w1, w1.steps)
+        legs["tg33_k1"] = _leg(torch, CGP, w1, w1.steps, 0, ref1, "fp64")
+        settle(legs["tg33_k1"], w1, ref1)
+        log(f"[bench] config tg33_k1: {json.dumps(legs['tg33_k1'])}")
+    for k in (range(4) if "cavity257" in which else ()):
+        for chi in (0, 1):
+            w = get_workload(f"cavity257_k{k}_chi{chi}_fp64")
+            ref = oracle_prefix(w, 1)
+            for prec in ("fp64", "mixed"):
+                name = f"cavity257_k{k}_chi{chi}_{prec}"
+                legs[name] = _leg(torch, CGP, w, steps, warmup, ref, prec)
+                settle(legs[name], w, ref)
+                log(f"[bench] config {name}: {legs[name]['ms_per_step']:.3f} ms/step")
+    w3 = get_workload("channel_k2")
+    ref = oracle_prefix(w3, 1) if "channel_k2" in which else []
+    for prec in (("mixed", "fp64") if "channel_k2" in which else ()):
+        legs[f"channel_k2_{prec}"] = _leg(torch, CGP, w3, steps, warmup, ref, prec)
+        settle(legs[f"channel_k2_{prec}"], w3, ref)
+        log(f"[bench] config channel_k2_{prec}: "
+            f"{legs[f'channel_k2_{prec}']['ms_per_step']:.3f} ms/step")
+    return legs
+
+
 def run_form(torch, g, uD, fields, warmup, steps, theta=None, kid=0):
     """W untimed steps, then K timed steps (synchronised on both sides, the
     selected kernel bracketed by HIP events), then one untimed step with
@@ -258,6 +407,14 @@ def main():
     ap.add_argument("--train-steps", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--parity-steps", type=int, default=10,
+                    help="steps of the trajectory prefix compared with the oracle, every "
+                         "step, for the main and the plain form (the oracle run on this "
+                         "prefix is also the CPU baseline)")
+    ap.add_argument("--config-legs", default="tg33_k1,cavity257,channel_k2",
+                    help="the other configurations, each timed and checked against the "
+                         "oracle (empty: none)")
+    ap.add_argument("--config-steps", type=int, default=30)
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
                             "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64")
@@ -365,6 +522,21 @@ def main():
     kid, kbytes = KERNELS[args.timed_kernel]
     main_form = args.main_form if args.main_form in forms else (
         "plain_fp64" if "plain_fp64" in forms else forms[0])
+    # the main form and the plain step over a prefix of the trajectory, every
+    # step kept, for the parity against the oracle over the same prefix
+    nprefix = max(1, min(args.parity_steps, nsteps))
+    prefixes = {}
+    if not args.no_cpu_baseline:
+        for form in dict.fromkeys([main_form, "plain_fp64"]):
+            if form not in forms:
+                continue
+            sp = solvers[form].new_state(Um, U0, P0)
+            traj = []
+            for n in range(nprefix):
+                solvers[form].step(sp, uD[n], theta=thetas[form])
+                traj.append((sp.U.cpu().numpy(), sp.P.cpu().numpy()))
+            prefixes[form] = traj
+            del sp
     results, finals = {}, {}
     for form in forms:
         el, kms, nl, st, state = run_form(torch, solvers[form], uD, (Um, U0, P0),
@@ -458,10 +630,16 @@ def main():
         calib = {"pcg_fine_k0": pcg_calibration(torch, args.pcg_calibration_iters)}
         log(f"[bench] PCG calibration: {json.dumps(calib)}")
 
+    legs = None
+    if args.config_legs:
+        legs = config_legs(torch, set(args.config_legs.split(",")), args.config_steps,
+                           args.warmup, not args.no_cpu_baseline)
+
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
-        cpu, parity = cpu_baseline(w, fine_xy, first)
+        cpu, parity = cpu_baseline(w, fine_xy, first, prefixes, nprefix)
+        del prefixes
 
     out = {
         "metric": METRIC, "value": results[main_form]["value"], "unit": "DOF*steps/s",
@@ -475,6 +653,7 @@ def main():
                    "restrict": w.restrict, "pcg_tol": w.pcg_tol, "mom_tol": w.mom_tol},
         "forms": results, "roofline": roofline, "cpu_baseline": cpu,
         "parity_rel_l2": parity, "time_to_tol": ttt, "calibration": calib,
+        "configs": legs,
     }
     print(json.dumps(out), flush=True)
 
