@@ -19,6 +19,9 @@ run over the same trajectory:
                  iterations per launch from one reduction; the same iterates)
   ncgp_fp64      the non-incremental CGP form the paper compares with
                  (no pressure in the momentum equation, P = Phi_f; chi = 0)
+  ndchol_mixed   FP64 iterative refinement around FP32 solves with the
+                 factor (FP32 storage and accumulation), previous increment
+  learned_mixed_ndchol  the same from the guarded learned guess
 and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
@@ -126,7 +129,9 @@ def rel(a, b):
 
 
 # oracle configuration (mass mode, coarse solver, scheme) matching each form
-FORM_MODES = {"lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
+FORM_MODES = {"ndchol_mixed": ("consistent", "exact", "incremental"),
+              "learned_mixed_ndchol": ("consistent", "exact", "incremental"),
+              "lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
               "lumped_fp64": ("lumped", "pcg", "incremental"),
               "ndchol_fp64": ("consistent", "exact", "incremental"),
               "ndchol_lumped_fp64": ("lumped", "exact", "incremental"),
@@ -403,9 +408,11 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=3)
     ap.add_argument("--learned-eval", type=int, default=1000)
     ap.add_argument("--timed-kernel", default="mass_spmv", choices=sorted(KERNELS))
-    ap.add_argument("--train-runs", type=int, default=3)
-    ap.add_argument("--train-steps", type=int, default=40)
-    ap.add_argument("--train-epochs", type=int, default=4)
+    # the timed workload's network: 10 phase-shifted runs x 200 steps = 2000
+    # training pairs, as the cavity's
+    ap.add_argument("--train-runs", type=int, default=10)
+    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parity-steps", type=int, default=10,
                     help="steps of the trajectory prefix compared with the oracle, every "
@@ -417,7 +424,8 @@ def main():
     ap.add_argument("--config-steps", type=int, default=30)
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
-                            "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64")
+                            "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64,ndchol_mixed,"
+                            "learned_mixed_ndchol")
     ap.add_argument("--main-form", default="s4_fp64",
                     help="the form whose throughput is `value` (if it runs; else plain_fp64)")
     ap.add_argument("--no-learned", action="store_true",
@@ -470,6 +478,14 @@ def main():
     g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="fp64", **kw)
     gm = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="mixed", **kw)
     solvers = {"plain_fp64": g, "learned_mixed": gm, "learned_fp64": g}
+    # FP64 refinement around FP32 solves with the factor of K_c (the mixed
+    # form whose inner solve is not latency bound by its iteration count)
+    gmf = None
+    if learned_forms or "ndchol_mixed" in forms:
+        gmf = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, precision="mixed", precond="ndchol",
+                  **kw)
+        solvers["ndchol_mixed"] = gmf
+        solvers["learned_mixed_ndchol"] = gmf
     for form, mass, pre in (("lumped_p_fp64", "lumped_p", "jacobi"),
                             ("lumped_fp64", "lumped", "jacobi"),
                             ("ndchol_fp64", "consistent", "ndchol"),
@@ -503,7 +519,8 @@ def main():
             f"{t_collect:.1f} s); losses {[round(x, 4) for x in losses]}")
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
               "lumped_p_fp64": None, "lumped_fp64": None, "ndchol_fp64": None,
-              "ndchol_lumped_fp64": None, "ncgp_fp64": None, "s4_fp64": None}
+              "ndchol_lumped_fp64": None, "ncgp_fp64": None, "s4_fp64": None,
+              "ndchol_mixed": None, "learned_mixed_ndchol": theta}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]
@@ -582,11 +599,15 @@ def main():
     # solving the same right-hand side to the same FP64 tolerance
     ttt = {}
     if learned_forms:
-        _, tt5 = learned.evaluate(g, gm, theta, w, steps=nsteps, warm=args.warmup)
+        extras = [("mixed_factor", gmf, False), ("learned_mixed_factor", gmf, True)]
+        if "ndchol_fp64" in solvers:
+            extras.insert(0, ("plain_factor", solvers["ndchol_fp64"], False))
+        _, tt5 = learned.evaluate(g, gm, theta, w, steps=nsteps, warm=args.warmup,
+                                  extras=extras)
         tt5["training"] = {"pairs": n_samples, "epochs": args.train_epochs, "s": t_train,
                            "final_loss": losses[-1]}
         ttt[w.name] = tt5
-    del g, gm, solvers, finals, uD
+    del g, gm, gmf, solvers, finals, uD
     torch.cuda.empty_cache()
 
     # the learned guess on its own workload: cavity, trained on other lid speeds
@@ -597,6 +618,10 @@ def main():
                   max_iter=wl.max_iter)
         gl = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="fp64", **kl)
         glm = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="mixed", **kl)
+        glf = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="fp64", precond="ndchol",
+                  **kl)
+        glmf = CGP(wl.coarse_mesh(), wl.levels, wl.dt, wl.nu, precision="mixed",
+                   precond="ndchol", **kl)
         t0 = time.perf_counter()
         runs = learned.plain_runs(gl, learned.variants(wl, args.learned_runs, seed=0),
                                   args.learned_steps)
@@ -608,7 +633,10 @@ def main():
         pairs = sum(len(r.b) for r in runs)
         del runs
         _, ttl = learned.evaluate(gl, glm, theta_l, wl.with_(lid_speed=1.0),
-                                  steps=args.learned_eval, warm=10)
+                                  steps=args.learned_eval, warm=10,
+                                  extras=[("plain_factor", glf, False),
+                                          ("mixed_factor", glmf, False),
+                                          ("learned_mixed_factor", glmf, True)])
         ttl["training"] = {"pairs": pairs, "epochs": args.learned_epochs,
                            "collect_s": t1 - t0, "s": t2 - t1, "final_loss": losses_l[-1]}
         ttl["config"] = {"fine_nodes": gl.nf, "coarse_nodes": gl.nc, "levels": wl.levels,
@@ -623,7 +651,7 @@ def main():
                                                   "max_res_plain", "max_res_learned", "accepted")}
         ttt[wl.name] = ttl
         log(f"[bench] {wl.name}: {json.dumps(ttl)}")
-        del gl, glm, gls
+        del gl, glm, gls, glf, glmf
 
     calib = None
     if args.pcg_calibration_iters > 0:

@@ -70,7 +70,9 @@ extern "C" {
 /* coarse-solve preconditioner (the paper preconditions its Krylov solves
  * with ILU(0), Sect. 2.3; the choice of coarse solver is open) */
 #define CGP_PRECOND_JACOBI 0 /* diagonal: single-reduction PCG, FP64 or mixed   */
-#define CGP_PRECOND_NDCHOL 1 /* nested-dissection Cholesky factor of K_c (FP64) */
+#define CGP_PRECOND_NDCHOL 1 /* nested-dissection Cholesky factor of K_c: FP64
+                                PCG, or with CGP_MIXED FP64 iterative refinement
+                                whose corrections are FP32 factor solves        */
 #define CGP_PRECOND_JACOBI_S4 2 /* diagonal, s-step form (FP64): the iterates of
                                   Jacobi-PCG, four iterations per launch from
                                   one Gram-matrix reduction (Chebyshev basis of
@@ -140,7 +142,11 @@ typedef struct cgp_problem {
                             of K_c (phi = 0 nodes removed; without natural
                             nodes the last coarse node N_c - 1 is pinned, as
                             K_c is singular), computed once on the host in
-                            cgp_assemble; requires precision = CGP_FP64      */
+                            cgp_assemble; with precision = CGP_MIXED the
+                            factor is stored in FP32 and the solve is FP64
+                            iterative refinement around FP32 factor solves
+                            (FP32 storage and accumulation; the residual,
+                            its norm and the iterate in FP64)                */
   int32_t scheme;         /* CGP_SCHEME_INCREMENTAL or CGP_SCHEME_NONINCREMENTAL */
 } cgp_problem;
 
@@ -254,7 +260,11 @@ int cgp_restrict(cgp_ctx* ctx, const double* u_tilde, double* b_c, void* stream)
  * form (same iterates up to rounding, same test after every iteration);
  * CGP_PRECOND_NDCHOL runs FP64 PCG whose
  * preconditioner is the factor (one iteration reaches rounding level; the
- * FP64 residual is tested before the first and after every iteration).  For the pure Neumann problem the lumped-mass mean of
+ * FP64 residual is tested before the first and after every iteration), or,
+ * with CGP_MIXED, FP64 refinement steps x += F32^-1 (b - K x), F32 the
+ * factor in FP32 (each removes all but about kappa(K_c) eps_32 of the error;
+ * the FP64 residual is tested before every correction; stats->iters and
+ * outer_iters count the corrections, capped by max_outer).  For the pure Neumann problem the lumped-mass mean of
  * the result is removed.  b_c, phi_c device [N_c].  stats may be NULL (then
  * no synchronisation beyond the convergence polling). */
 int cgp_pcg_solve(cgp_ctx* ctx, const double* b_c, double* phi_c, cgp_solve_stats* stats,

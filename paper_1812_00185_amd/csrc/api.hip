@@ -163,7 +163,9 @@ struct cgp_ctx {
   // nested-dissection factor preconditioner (CGP_PRECOND_NDCHOL): host
   // structure, device view, and the PCG vectors z, p (alternating) and q
   cgp::NdFactor nd;
-  cgp::NdDev ndd{};
+  cgp::NdDev ndd{};     // FP64 factor (precision CGP_FP64)
+  cgp::NdDev32 ndd32{}; // FP32 factor (CGP_MIXED: the solve inside the refinement)
+  float* nd_z32 = nullptr;
   double* nd_z = nullptr;
   double* nd_p[2] = {nullptr, nullptr};
   double* nd_q = nullptr;
@@ -278,15 +280,34 @@ size_t carve(cgp_ctx* c, void* base) {
     d.gidx = w.take<int32_t>(f.gidx.size());
     d.fwd = w.take<cgp::NdItem>(f.fwd.size());
     d.bwd = w.take<cgp::NdItem>(f.bwd.size());
-    d.G = w.take<double>((size_t)f.g_entries);
-    d.GT = w.take<double>((size_t)f.g_entries);
-    d.Y = w.take<double>(f.nfac);
-    d.X = w.take<double>(f.nfac);
-    d.U = w.take<double>(f.n_upd);
-    c->nd_z = w.take<double>(nc);
-    c->nd_p[0] = w.take<double>(nc);
-    c->nd_p[1] = w.take<double>(nc);
-    c->nd_q = w.take<double>(nc);
+    if (c->prob.precision == CGP_FP64) {
+      d.G = w.take<double>((size_t)f.g_entries);
+      d.GT = w.take<double>((size_t)f.g_entries);
+      d.Y = w.take<double>(f.nfac);
+      d.X = w.take<double>(f.nfac);
+      d.U = w.take<double>(f.n_upd);
+      c->nd_z = w.take<double>(nc);
+      c->nd_p[0] = w.take<double>(nc);
+      c->nd_p[1] = w.take<double>(nc);
+      c->nd_q = w.take<double>(nc);
+    } else {
+      // the same structure with FP32 values
+      cgp::NdDev32& e = c->ndd32;
+      e.nfac = d.nfac;
+      e.perm = d.perm;
+      e.sn = d.sn;
+      e.rows = d.rows;
+      e.gptr = d.gptr;
+      e.gidx = d.gidx;
+      e.fwd = d.fwd;
+      e.bwd = d.bwd;
+      e.G = w.take<float>((size_t)f.g_entries);
+      e.GT = w.take<float>((size_t)f.g_entries);
+      e.Y = w.take<float>(f.nfac);
+      e.X = w.take<float>(f.nfac);
+      e.U = w.take<float>(f.n_upd);
+      c->nd_z32 = w.take<float>(nc);
+    }
   }
   if (c->prob.coarse_precond == CGP_PRECOND_JACOBI_S4) {
     const cgp::CaPlan& pl = c->ca;
@@ -560,11 +581,62 @@ int jacobi_pcg64(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hi
   return stats_status(out, 1, P.max_iter, st);
 }
 
+// Mixed precision with the factor: FP64 iterative refinement whose
+// correction is the FP32 factor solve, x += L^-T L^-1 (float) r, r = b - K x
+// in FP64 (each correction removes all but about kappa eps_32 of the error).
+// The FP64 residual is tested before every correction.  Corrections are
+// queued two at a time between host polls; a correction whose test found the
+// solve done returns at once.
+int run_pcg_nd_mixed(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st,
+                     hipStream_t s) {
+  const cgp_problem& P = c->prob;
+  Scal* const chk = c->scal + 4;
+  int queued = 0, rc = CGP_OK;
+  Scal last{};
+  const int cap = std::min(P.max_outer, P.max_iter);
+  for (;;) {
+    const int burst = queued == 0 ? 2 : 1;
+    for (int k = 0; k < burst && queued < cap; ++k, ++queued) {
+      cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
+      cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, chk, queued, s);
+      cgp::launch_nd_solve<float>(c->ndd32, c->nd, c->cb32, c->nd_z32, s, chk);
+      cgp::launch_axpy_f32(c->nd_z32, x, c->nc, s, chk);
+    }
+    cgp::launch_residual64(c->C, c->Kc, b, x, c->cr, c->cb32, c->part, c->nb_c, s);
+    cgp::launch_reduce_check(c->part, c->nb_c, P.pcg_tol, chk, queued, s);
+    cgp::launch_mirror(chk, c->pinned, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    last = c->pinned[0];
+    if (last.status == 2) {
+      rc = fail(CGP_ERR_NAN, "mixed-precision refinement produced NaN/Inf");
+      break;
+    }
+    if (last.done_stamp) break;
+    if (queued >= cap) {
+      rc = fail(CGP_NOT_CONVERGED, "refinement limit reached");
+      break;
+    }
+  }
+  // a check that finds the solve done stores (its index + 1); the
+  // corrections before it were applied
+  const int applied = last.done_stamp ? last.done_stamp - 1 : queued;
+  if (st) {
+    st->iters = applied;
+    st->outer_iters = applied;
+    st->converged = rc == CGP_OK;
+    st->rel_res = last.rel;
+  }
+  return rc;
+}
+
 int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
   int rc = CGP_OK;
   if (c->h.n_nat_c) cgp::launch_zero_masked(x, c->nat_c, c->nc, s);
-  if (P.coarse_precond == CGP_PRECOND_NDCHOL) {
+  if (P.coarse_precond == CGP_PRECOND_NDCHOL && P.precision == CGP_MIXED) {
+    rc = run_pcg_nd_mixed(c, b, x, st, s);
+    if (rc == CGP_ERR_HIP) return rc;
+  } else if (P.coarse_precond == CGP_PRECOND_NDCHOL) {
     rc = run_pcg_nd(c, b, x, st, s);
   } else if (P.coarse_precond == CGP_PRECOND_JACOBI_S4) {
     // one launch per kCaS iterations (launch 1 tests the guess); the scalars
@@ -752,8 +824,6 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
     return fail(CGP_ERR_INVALID, "unknown scheme");
   if (prob->scheme == CGP_SCHEME_NONINCREMENTAL && prob->chi != 0)
     return fail(CGP_ERR_INVALID, "the non-incremental scheme has no rotational form (chi = 0)");
-  if (prob->coarse_precond == CGP_PRECOND_NDCHOL && prob->precision != CGP_FP64)
-    return fail(CGP_ERR_INVALID, "CGP_PRECOND_NDCHOL requires precision CGP_FP64");
   if (prob->coarse_precond == CGP_PRECOND_JACOBI_S4 && prob->precision != CGP_FP64)
     return fail(CGP_ERR_INVALID, "CGP_PRECOND_JACOBI_S4 requires precision CGP_FP64");
   cgp::Mesh cm;
@@ -966,12 +1036,23 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     HIPCHK(up((void*)d.gidx, f.gidx.data(), sizeof(int32_t) * f.gidx.size()));
     HIPCHK(up((void*)d.fwd, f.fwd.data(), sizeof(cgp::NdItem) * f.fwd.size()));
     HIPCHK(up((void*)d.bwd, f.bwd.data(), sizeof(cgp::NdItem) * f.bwd.size()));
-    HIPCHK(up((void*)d.G, f.G.data(), sizeof(double) * f.G.size()));
-    HIPCHK(up((void*)d.GT, f.GT.data(), sizeof(double) * f.GT.size()));
-    // z is written at the factored unknowns only: zero once
-    cgp::launch_fill(c->nd_z, 0.0, c->nc, s);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
+    if (c->prob.precision == CGP_FP64) {
+      HIPCHK(up((void*)d.G, f.G.data(), sizeof(double) * f.G.size()));
+      HIPCHK(up((void*)d.GT, f.GT.data(), sizeof(double) * f.GT.size()));
+      // z is written at the factored unknowns only: zero once
+      cgp::launch_fill(c->nd_z, 0.0, c->nc, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    } else {
+      // the FP64 factor rounded to FP32 for the solve inside the refinement
+      const cgp::NdDev32& e = c->ndd32;
+      std::vector<float> g32(f.G.begin(), f.G.end()), gt32(f.GT.begin(), f.GT.end());
+      HIPCHK(up((void*)e.G, g32.data(), sizeof(float) * g32.size()));
+      HIPCHK(up((void*)e.GT, gt32.data(), sizeof(float) * gt32.size()));
+      cgp::launch_fill32(c->nd_z32, 0.0f, c->nc, s);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    }
     std::vector<double>().swap(f.G);
     std::vector<double>().swap(f.GT);
   }

@@ -151,7 +151,10 @@ void launch_final_update(int32_t n, const double* ut, const double* du, const do
 // ---------------------------------------------------------------- small vector ops
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
 void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s);
-void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s);
+// x += d; with `skip`, nothing once that record's solve is done
+void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s,
+                     const Scal* skip = nullptr);
+void launch_fill32(float* x, float v, int64_t n, hipStream_t s);
 // n <= 5 scalar records into host-mapped pinned memory
 void launch_mirror(const Scal* src, Scal* host_dst, int n, hipStream_t s);
 void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,

@@ -1178,10 +1178,20 @@ __global__ void k_zero_masked(double* __restrict__ x, const uint8_t* __restrict_
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (nat[i]) x[i] = 0.0;
 }
-__global__ void k_axpy_f32(const float* __restrict__ d, double* __restrict__ x, int64_t n) {
+// x += d (FP32 correction into the FP64 iterate); returns at once when
+// `skip` is given and its solve is done
+__global__ void k_axpy_f32(const float* __restrict__ d, double* __restrict__ x, int64_t n,
+                           const Scal* skip) {
+  if (skip && skip->done_stamp) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     x[i] += (double)d[i];
+}
+
+__global__ void k_fill32(float* __restrict__ x, float v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
 }
 
 // r = b - K x in FP64 (and its FP32 copy), partials (r, r) and (b, b)
@@ -1466,8 +1476,11 @@ void launch_zero_masked(double* x, const uint8_t* nat, int32_t n, hipStream_t s)
 void launch_mirror(const Scal* src, Scal* host_dst, int n, hipStream_t s) {
   k_mirror<<<1, 64, 0, s>>>(src, host_dst, n);
 }
-void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s) {
-  k_axpy_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(d, x, n);
+void launch_axpy_f32(const float* d, double* x, int64_t n, hipStream_t s, const Scal* skip) {
+  k_axpy_f32<<<grid_for(n, kBlock), kBlock, 0, s>>>(d, x, n, skip);
+}
+void launch_fill32(float* x, float v, int64_t n, hipStream_t s) {
+  k_fill32<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, v, n);
 }
 void launch_residual64(const DLevel& C, const double* Kval, const double* b, const double* x,
                        double* r, float* r32, double* part, int nb, hipStream_t s) {

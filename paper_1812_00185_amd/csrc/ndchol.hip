@@ -18,10 +18,11 @@ constexpr int kNdWaves = 4;  // waves per item, each over a quarter of the reduc
 constexpr int kNdBlock = kNdWave * kNdWaves;
 static_assert(kNdItemRows == kNdWave, "one output row (column) per lane");
 
-// sum over [a, b) of g[k * ld] * x[k], 8 loads in flight
-__device__ __forceinline__ double dot_strided(const double* __restrict__ g, int64_t ld,
-                                              const double* x, int a, int b) {
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+// sum over [a, b) of g[k * ld] * x[k], 8 loads in flight (accumulated in T)
+template <typename T>
+__device__ __forceinline__ T dot_strided(const T* __restrict__ g, int64_t ld, const T* x, int a,
+                                         int b) {
+  T acc[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   int k = a;
   for (; k + 8 <= b; k += 8) {
 #pragma unroll
@@ -32,11 +33,12 @@ __device__ __forceinline__ double dot_strided(const double* __restrict__ g, int6
 }
 
 // the kNdWaves partial sums of each lane, added in wave order by wave 0
-__device__ __forceinline__ double combine(double part, double (&sh)[kNdWaves][kNdWave]) {
+template <typename T>
+__device__ __forceinline__ T combine(T part, T (&sh)[kNdWaves][kNdWave]) {
   const int lane = threadIdx.x % kNdWave, wv = threadIdx.x / kNdWave;
   sh[wv][lane] = part;
   __syncthreads();
-  double t = 0.0;
+  T t = T(0);
   if (wv == 0) {
 #pragma unroll
     for (int q = 0; q < kNdWaves; ++q) t += sh[q][lane];
@@ -49,17 +51,19 @@ __device__ __forceinline__ bool nd_skip(const Scal* flag) {
 }
 
 // forward: y_C and u of one item; f_C = r on C plus the children's updates
+template <typename T>
 __global__ void __launch_bounds__(kNdBlock)
-k_nd_forward(NdDev d, const NdItem* __restrict__ items, const double* __restrict__ r,
+k_nd_forward(NdDevT<T> d, const NdItem* __restrict__ items, const T* __restrict__ r,
              const Scal* flag) {
-  extern __shared__ double fc[];
-  __shared__ double part[kNdWaves][kNdWave];
+  extern __shared__ __align__(16) unsigned char fc_raw[];
+  T* fc = reinterpret_cast<T*>(fc_raw);
+  __shared__ T part[kNdWaves][kNdWave];
   if (nd_skip(flag)) return;
   const NdItem it = items[blockIdx.x];
   const NdSuper S = d.sn[it.sn];
   const int fs = S.w + S.m;
   for (int j = threadIdx.x; j < S.w; j += kNdBlock) {
-    double v = r[d.perm[S.c0 + j]];
+    T v = r[d.perm[S.c0 + j]];
     for (int q = d.gptr[S.gpos + j]; q < d.gptr[S.gpos + j + 1]; ++q) v += d.U[d.gidx[q]];
     fc[j] = v;
   }
@@ -71,23 +75,25 @@ k_nd_forward(NdDev d, const NdItem* __restrict__ items, const double* __restrict
   const int jmax = it.hi <= S.w ? it.hi : S.w;
   const int chunk = (jmax + kNdWaves - 1) / kNdWaves;
   const int a = min(jmax, wv * chunk), b = min(jmax, a + chunk);
-  const double acc = combine(dot_strided(d.G + S.goff + oc, fs, fc, a, b), part);
+  const T acc = combine<T>(dot_strided<T>(d.G + S.goff + oc, fs, fc, a, b), part);
   if (wv != 0 || o >= it.hi) return;
   if (o < S.w) {
     d.Y[S.c0 + o] = acc;
   } else {
-    double fr = 0.0;
+    T fr = T(0);
     for (int q = d.gptr[S.gpos + o]; q < d.gptr[S.gpos + o + 1]; ++q) fr += d.U[d.gidx[q]];
     d.U[S.uoff + o - S.w] = fr - acc;
   }
 }
 
 // backward: x_C = G^T [y_C ; -x_R] for one item's columns
+template <typename T>
 __global__ void __launch_bounds__(kNdBlock)
-k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z,
+k_nd_backward(NdDevT<T> d, const NdItem* __restrict__ items, T* __restrict__ z,
               const Scal* flag) {
-  extern __shared__ double v[];
-  __shared__ double part[kNdWaves][kNdWave];
+  extern __shared__ __align__(16) unsigned char v_raw[];
+  T* v = reinterpret_cast<T*>(v_raw);
+  __shared__ T part[kNdWaves][kNdWave];
   if (nd_skip(flag)) return;
   const NdItem it = items[blockIdx.x];
   const NdSuper S = d.sn[it.sn];
@@ -102,7 +108,7 @@ k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z,
   const int len = fs - it.lo;
   const int chunk = (len + kNdWaves - 1) / kNdWaves;
   const int a = it.lo + min(len, wv * chunk), b = it.lo + min(len, (wv + 1) * chunk);
-  const double acc = combine(dot_strided(d.GT + S.goff + ic, S.w, v, a, b), part);
+  const T acc = combine<T>(dot_strided<T>(d.GT + S.goff + ic, S.w, v, a, b), part);
   if (wv != 0 || i >= it.hi) return;
   d.X[S.c0 + i] = acc;
   z[d.perm[S.c0 + i]] = acc;
@@ -110,20 +116,26 @@ k_nd_backward(NdDev d, const NdItem* __restrict__ items, double* __restrict__ z,
 
 }  // namespace
 
-void launch_nd_solve(const NdDev& d, const NdFactor& f, const double* r, double* z,
-                     hipStream_t s, const Scal* skip_if_done) {
+template <typename T>
+void launch_nd_solve(const NdDevT<T>& d, const NdFactor& f, const T* r, T* z, hipStream_t s,
+                     const Scal* skip_if_done) {
   for (int L = 0; L < f.height; ++L) {
     const int a = f.fwd_lvl[L], b = f.fwd_lvl[L + 1];
     int lds = 1;
     for (int k = a; k < b; ++k) lds = std::max(lds, f.sn[f.fwd[k].sn].w);
-    k_nd_forward<<<b - a, kNdBlock, sizeof(double) * lds, s>>>(d, d.fwd + a, r, skip_if_done);
+    k_nd_forward<T><<<b - a, kNdBlock, sizeof(T) * lds, s>>>(d, d.fwd + a, r, skip_if_done);
   }
   for (int q = 0; q < f.height; ++q) {
     const int a = f.bwd_lvl[q], b = f.bwd_lvl[q + 1];
     int lds = 1;
     for (int k = a; k < b; ++k) lds = std::max(lds, f.sn[f.bwd[k].sn].w + f.sn[f.bwd[k].sn].m);
-    k_nd_backward<<<b - a, kNdBlock, sizeof(double) * lds, s>>>(d, d.bwd + a, z, skip_if_done);
+    k_nd_backward<T><<<b - a, kNdBlock, sizeof(T) * lds, s>>>(d, d.bwd + a, z, skip_if_done);
   }
 }
+
+template void launch_nd_solve<double>(const NdDevT<double>&, const NdFactor&, const double*,
+                                      double*, hipStream_t, const Scal*);
+template void launch_nd_solve<float>(const NdDevT<float>&, const NdFactor&, const float*,
+                                     float*, hipStream_t, const Scal*);
 
 }  // namespace cgp

@@ -91,8 +91,12 @@ void nd_solve_host(const NdFactor& f, const double* r, double* z);
 
 namespace cgp {
 
-// Device copy of a factor (arrays in the caller's workspace).
-struct NdDev {
+// Device copy of a factor (arrays in the caller's workspace), with the
+// factor entries, front vectors and results of type T: double for the FP64
+// coarse solve, float for the FP32 solve inside the mixed-precision
+// refinement (FP32 storage and FP32 accumulation).
+template <typename T>
+struct NdDevT {
   int32_t nfac;
   const int32_t* perm;
   const NdSuper* sn;
@@ -101,12 +105,14 @@ struct NdDev {
   const int32_t* gidx;
   const NdItem* fwd;
   const NdItem* bwd;
-  const double* G;
-  const double* GT;
-  double* Y;  // [nfac] forward result
-  double* X;  // [nfac] backward result (ND order)
-  double* U;  // [n_upd] update vectors
+  const T* G;
+  const T* GT;
+  T* Y;  // [nfac] forward result
+  T* X;  // [nfac] backward result (ND order)
+  T* U;  // [n_upd] update vectors
 };
+using NdDev = NdDevT<double>;
+using NdDev32 = NdDevT<float>;
 
 struct Scal;
 
@@ -114,7 +120,8 @@ struct Scal;
 // (leaves first), then one backward launch per level (root first).  Entries
 // of z at skipped nodes are not written.  With skip_if_done != nullptr every
 // launch returns at once when that record's done_stamp is set.
-void launch_nd_solve(const NdDev& d, const NdFactor& f, const double* r, double* z,
-                     hipStream_t s, const Scal* skip_if_done = nullptr);
+template <typename T>
+void launch_nd_solve(const NdDevT<T>& d, const NdFactor& f, const T* r, T* z, hipStream_t s,
+                     const Scal* skip_if_done = nullptr);
 
 }  // namespace cgp

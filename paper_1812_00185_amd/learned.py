@@ -107,15 +107,19 @@ def train(g: CGP, runs, epochs=8, lr=1e-3, seed=0, log=None, skip=4):
     return theta, losses
 
 
-def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
+def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10, extras=()):
     """Time to tolerance of the coarse solve along a fresh run, four ways on
     the same right-hand side and to the same FP64 tolerance: plain FP64 PCG
     from the previous increment (solver g); the guarded quadratic
     extrapolation 3 phi^n - 3 phi^{n-1} + phi^{n-2} with FP64 PCG (a
     network-free point of comparison); the guarded learned guess with FP64
     PCG (g); and the guarded learned guess with mixed-precision refinement
-    (solver gm, same mesh).  The run advances with the plain solution.
-    Returns per-step records and means over the steps after `warm`."""
+    (solver gm, same mesh).  `extras`: further (name, solver, use_net)
+    solvers on the same mesh, each solving the same right-hand side from the
+    guarded learned guess (use_net) or from the previous increment, reported
+    as iters_<name> and ms_<name>.  The run advances with the plain
+    solution.  Returns per-step records and means over the steps after
+    `warm`."""
     import torch
 
     xyd = g.fine_xy[g.dirichlet_nodes]
@@ -153,8 +157,19 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
         (st_q, chose_q), ms_q = timed(extrap_solve)
         (phi_b, chose, st_b), ms_b = timed(lambda: learned_solve(g))
         (phi_c, _, st_c), ms_c = timed(lambda: learned_solve(gm))
+        extra_rec = {}
+        for name, solver, use_net in extras:
+            if use_net:
+                (_, _, st_e), ms_e = timed(lambda: learned_solve(solver))
+            else:
+                phi_e = hist[0].clone()
+                st_e, ms_e = timed(lambda: solver.pcg_solve(b, phi_e))
+            extra_rec[f"iters_{name}"] = st_e["iters"]
+            extra_rec[f"ms_{name}"] = ms_e
+            extra_rec[f"res_{name}"] = st_e["rel_res"]
         na = torch.linalg.norm(phi_a)
-        rec.append(dict(iters_plain=st_a["iters"], iters_extrap=st_q["iters"], ms_extrap=ms_q,
+        rec.append(dict(**extra_rec, iters_plain=st_a["iters"], iters_extrap=st_q["iters"],
+                        ms_extrap=ms_q,
                         iters_learned=st_b["iters"],
                         iters_learned_mixed=st_c["iters"], outer=st_c["outer_iters"],
                         ms_plain=ms_a, ms_learned=ms_b, ms_learned_mixed=ms_c,
@@ -170,8 +185,10 @@ def evaluate(g: CGP, gm: CGP, theta, workload, steps, seed=1, warm=10):
     tail = rec[warm:] if len(rec) > warm else rec
     keys = ("iters_plain", "iters_extrap", "iters_learned", "iters_learned_mixed", "ms_plain",
             "ms_extrap", "ms_learned", "ms_learned_mixed", "accepted", "accepted_extrap")
+    keys = keys + tuple(f"{p}_{name}" for name, _, _ in extras for p in ("iters", "ms"))
     summary = {k: float(np.mean([r[k] for r in tail])) for k in keys}
     summary["steps"] = len(tail)
-    for k in ("res_plain", "res_learned", "res_learned_mixed", "diff", "diff_mixed"):
+    for k in ("res_plain", "res_learned", "res_learned_mixed", "diff", "diff_mixed") + tuple(
+            f"res_{name}" for name, _, _ in extras):
         summary["max_" + k] = float(max(r[k] for r in tail))
     return rec, summary

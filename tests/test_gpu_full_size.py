@@ -92,6 +92,18 @@ def test_taylor_green_2049_k3_ndchol_two_steps():
         assert du <= 1e-10 and dp <= 1e-10
 
 
+def test_taylor_green_2049_k3_ndchol_mixed_two_steps():
+    """The mixed-precision form with the factor: FP64 refinement around FP32
+    factor solves on the 257 x 257 coarse system, against the FP64 oracle's
+    exact coarse solve: the FP64 true residual within the tolerance and the
+    fields within the mixed bar, 1e-6."""
+    w = get_workload("tg2049_k3_mixed").with_(precond="ndchol")
+    for du, dp, st in run(w, 2):
+        assert st["poisson"]["converged"] and st["poisson"]["rel_res"] <= w.pcg_tol
+        assert st["poisson"]["outer_iters"] <= 5
+        assert du <= 1e-6 and dp <= 1e-6
+
+
 def test_taylor_green_2049_k3_sstep_one_step():
     """The plain FP64 step with the coarse Jacobi-PCG in s-step form (four
     iterations per launch from one reduction), against the oracle's

@@ -123,3 +123,64 @@ def test_step_trajectories(name, wf, steps):
         worst = max(worst, rel(sg.U.cpu().numpy(), so.U), rel(sg.P.cpu().numpy(), so.P))
     print(f"[result] {name}: worst relative L2 over {steps} steps {worst:.3e}", flush=True)
     assert worst <= TOL64
+
+
+# ----------------------------------------------------------------- mixed precision
+def make_mixed(w):
+    w = w.with_(precond="ndchol", precision=1)
+    print(f"\n[case] {w.name} coarse_n={w.coarse_n} k={w.levels} chi={w.chi} ndchol mixed",
+          flush=True)
+    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi, restrict=w.restrict,
+            pcg_tol=w.pcg_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter,
+            mass=w.mass, precond="ndchol", precision="mixed")
+    return w, g, build_oracle(w.with_(precision=0))
+
+
+@pytest.mark.parametrize("name,wf", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_mixed_refinement_with_fp32_factor(name, wf):
+    """FP64 refinement around FP32 factor solves: the FP64 true residual
+    (recomputed from the oracle's K_c) meets the tolerance; the solution is
+    within kappa x tol of the exact coarse solve (checked against 1e-6); a
+    handful of corrections suffice (each removes all but ~kappa eps_32)."""
+    w, g, o = make_mixed(wf().with_(pcg_tol=1e-8))
+    f = o.phi_free
+    for seed, guess in ((1, "zero"), (2, "random")):
+        b = compatible_rhs(o, seed)
+        x0 = np.zeros(o.nc) if guess == "zero" else np.random.default_rng(seed + 10).standard_normal(o.nc)
+        ref, _ = o.poisson(b, x0)
+        phi = g.to_device(x0)
+        st = g.pcg_solve(g.to_device(b), phi)
+        torch.cuda.synchronize()
+        x = phi.cpu().numpy()
+        true = np.linalg.norm(b[f] - o.Kc_ff @ x[f]) / np.linalg.norm(b[f])
+        d = rel(x, ref)
+        print(f"[result] {name} {guess}: true rel residual {true:.3e}, vs exact {d:.3e}, "
+              f"stats {st}", flush=True)
+        assert st["converged"] and 1 <= st["outer_iters"] <= 5
+        assert true <= w.pcg_tol and st["rel_res"] <= w.pcg_tol
+        assert d <= 1e-6
+        assert np.all(x[o.nat_c] == 0.0)
+
+
+@pytest.mark.parametrize("name,wf,steps", [
+    ("cavity_k1_chi1", lambda: cavity(33, 1, chi=1), 10),
+    ("channel_k1_chi1", lambda: channel(1, 0.05, chi=1), 8),
+])
+def test_mixed_step_trajectories(name, wf, steps):
+    """Mixed-precision steps with the FP32 factor end to end against the FP64
+    oracle (exact coarse solve): within the mixed path's bar, 1e-6."""
+    w, g, o = make_mixed(wf().with_(pcg_tol=1e-8))
+    Um, U0, P0 = w.initial_fields(o.fine_xy)
+    so, sg = o.initial_state(Um, U0, P0), g.new_state(Um, U0, P0)
+    xyd = o.fine_xy[o.dir]
+    worst = 0.0
+    for n in range(steps):
+        t = (n + 1) * w.dt
+        uD = w.dirichlet_values(xyd, t)
+        so = o.step(so, uD).state
+        st = g.step(sg, g.to_device(uD), stats=True)
+        assert st["poisson"]["converged"] and st["poisson"]["rel_res"] <= w.pcg_tol
+        worst = max(worst, rel(sg.U.cpu().numpy(), so.U), rel(sg.P.cpu().numpy(), so.P))
+    print(f"[result] {name}: mixed (FP32 factor) vs FP64 oracle, worst over {steps} steps "
+          f"{worst:.3e}", flush=True)
+    assert worst <= 1e-6

@@ -112,8 +112,12 @@ def test_context_reports_factor_structure(N):
     g = CGP(unit_square(17), 1, 1e-3, 1e-2, device="cpu")
     assert g.ndchol["n_factored"] == 0
     g.close()
+    # the mixed-precision form keeps the same factor structure (FP32 values)
+    g = CGP(unit_square(17), 1, 1e-3, 1e-2, precision="mixed", precond="ndchol", device="cpu")
+    assert g.ndchol["n_factored"] == 17 * 17 - 1
+    g.close()
     with pytest.raises(N.CGPError, match="requires precision"):
-        CGP(unit_square(9), 1, 1e-3, 1e-2, precision="mixed", precond="ndchol", device="cpu")
+        CGP(unit_square(9), 1, 1e-3, 1e-2, precision="mixed", precond="jacobi_s4", device="cpu")
 
 
 # ---------------------------------------------------------------- oracle pins
