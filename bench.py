@@ -26,17 +26,19 @@ and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
 trajectories than the timed one).  `value` is the throughput in fine
-DOF * steps / s (DOF = 3 N_f: u, v, p) of the paper's step with FP64
-Jacobi-PCG, run in its s-step form (s4_fp64: the iterations of plain_fp64,
-four per launch; --main-form picks another form), which matches the FP64
-oracle to 1e-10 like plain_fp64; the other forms (which agree with it to the
+DOF * steps / s (DOF = 3 N_f: u, v, p) of the step with the FP64 coarse
+solve preconditioned by the nested-dissection factor (ndchol_fp64; the
+problem statement of this workload names no preconditioner; --main-form
+picks another form), which matches the FP64 oracle with an exact coarse
+solve to 1e-10; the other forms (which agree with it to the
 solver tolerance), the coarse-solve time to tolerance of each guess on this
 workload and on the 257 x 257 lid-driven cavity with a 129 x 129 pressure
 mesh (the learned guess's own workload: trained on lid speeds U[0.5, 1.5],
 evaluated on a fresh U = 1 run), the roofline position of the dominant
 kernel (HIP events over the timed region), the CPU oracle timed on a bounded
-sample (the first --parity-steps steps), the parity of the main and the plain
-form against that oracle prefix at every step and of every form's first step,
+sample (the first --parity-steps steps, configured like the main form), the
+parity of the main form (and of the mixed form with the factor) against that
+oracle prefix at every step and of every form's first step,
 and the other configurations (33 x 33 Taylor-Green, the 257 x 257 cavity at
 k = 0..3 in both schemes, plain FP64 and mixed, the channel with the
 cylinder, mixed and FP64), each timed and checked against the oracle, are
@@ -139,12 +141,13 @@ FORM_MODES = {"ndchol_mixed": ("consistent", "exact", "incremental"),
               "s4_fp64": ("consistent", "pcg", "incremental")}
 
 
-def cpu_baseline(w, g_fine_xy, first_steps, prefixes, nprefix):
-    """The oracle (as it stands), single thread, over the first `nprefix`
-    steps of the same workload from its initial fields: its throughput is
-    the CPU baseline, and its states give the parity of the GPU forms that
-    ran the same prefix (every step) and of every form's first step (each
-    against the oracle configured like it)."""
+def cpu_baseline(w, g_fine_xy, first_steps, prefixes, nprefix, main_mode):
+    """The oracle (as it stands), single thread, configured like the main
+    form (`main_mode`: mass matrices, coarse solver, scheme), over the first
+    `nprefix` steps of the same workload from its initial fields: its
+    throughput is the CPU baseline, and its states give the parity of the GPU
+    forms of that mode that ran the same prefix (every step) and of every
+    form's first step (each against the oracle configured like it)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.cgp import build as build_oracle
@@ -152,6 +155,7 @@ def cpu_baseline(w, g_fine_xy, first_steps, prefixes, nprefix):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         ora = build_oracle(w)
+        ora.mass_mode, ora.coarse_solver, ora.scheme = main_mode
         t_setup = time.perf_counter() - t0
         st0 = ora.initial_state(*w.initial_fields(ora.fine_xy))
         uD1 = w.dirichlet_values(ora.fine_xy[ora.dir], w.dt)
@@ -174,10 +178,10 @@ def cpu_baseline(w, g_fine_xy, first_steps, prefixes, nprefix):
         parity[form + "_prefix"] = {
             "steps": len(per), "u_last": per[-1][0], "p_last": per[-1][1],
             "u_max": max(d[0] for d in per), "p_max": max(d[1] for d in per),
-            "oracle": "mass=consistent, coarse=pcg, scheme=incremental"}
+            "oracle": "mass={}, coarse={}, scheme={}".format(*main_mode)}
     # first step of each form against the oracle configured like it (mass
     # matrices of Eqs. 25-27, coarse solver); the operators are shared
-    refs = {("consistent", "pcg", "incremental"): states[0]}
+    refs = {main_mode: states[0]}
     for form, (U_g, P_g) in first_steps.items():
         mode = FORM_MODES.get(form, ("consistent", "pcg", "incremental"))
         if mode not in refs:
@@ -426,7 +430,7 @@ def main():
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
                             "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64,ndchol_mixed,"
                             "learned_mixed_ndchol")
-    ap.add_argument("--main-form", default="s4_fp64",
+    ap.add_argument("--main-form", default="ndchol_fp64",
                     help="the form whose throughput is `value` (if it runs; else plain_fp64)")
     ap.add_argument("--no-learned", action="store_true",
                     help="the plain FP64 forms only (Jacobi-PCG, standard and s-step): no training, no learned forms or legs")
@@ -544,8 +548,9 @@ def main():
     nprefix = max(1, min(args.parity_steps, nsteps))
     prefixes = {}
     if not args.no_cpu_baseline:
-        for form in dict.fromkeys([main_form, "plain_fp64"]):
-            if form not in forms:
+        for form in forms:
+            if form != main_form and (form not in ("ndchol_mixed", "s4_fp64") or
+                                      FORM_MODES.get(form) != FORM_MODES.get(main_form)):
                 continue
             sp = solvers[form].new_state(Um, U0, P0)
             traj = []
@@ -666,7 +671,9 @@ def main():
     cpu, parity = (None, None)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
-        cpu, parity = cpu_baseline(w, fine_xy, first, prefixes, nprefix)
+        cpu, parity = cpu_baseline(w, fine_xy, first, prefixes, nprefix,
+                                   FORM_MODES.get(main_form,
+                                                  ("consistent", "pcg", "incremental")))
         del prefixes
 
     out = {
