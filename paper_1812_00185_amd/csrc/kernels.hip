@@ -126,15 +126,24 @@ struct TileStage {
 // Loads the nonzeros of rows [r0, r1) into LDS (coalesced); returns the first
 // nonzero index s0.  Brackets the stage with barriers so a block can loop over
 // tiles.
-template <typename T>
+// kStream: the matrix is streamed once per launch (the fine momentum matrix,
+// hundreds of MB): its values and column indices are loaded non-temporally
+// so that the L2 keeps the gathered vector; the coarse matrices, re-read by
+// every iteration from cache, load normally.
+template <typename T, bool kStream = false>
 __device__ __forceinline__ int stage_tile(TileStage<T>& st, const DLevel& L, const T* __restrict__ val,
                                           int r0, int r1) {
   const int s0 = L.rowptr[r0], s1 = L.rowptr[r1];
   __syncthreads();
 #pragma unroll 4
   for (int k = threadIdx.x; k < s1 - s0; k += kBlock) {
-    st.val[k] = val[s0 + k];
-    st.col[k] = L.col[s0 + k];
+    if constexpr (kStream) {
+      st.val[k] = __builtin_nontemporal_load(val + s0 + k);
+      st.col[k] = __builtin_nontemporal_load(L.col + s0 + k);
+    } else {
+      st.val[k] = val[s0 + k];
+      st.col[k] = L.col[s0 + k];
+    }
   }
   __syncthreads();
   return s0;
@@ -416,7 +425,7 @@ k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double
   double rr[2] = {0, 0}, bb[2] = {0, 0};
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int s0 = stage_tile<double, true>(st, L, A, r0, r1);
     const int row = r0 + threadIdx.x;
     if (row < r1) {
       double ax[2];
@@ -500,7 +509,7 @@ k_bicg_b2(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
   double dot[2] = {0, 0};
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int s0 = stage_tile<double, true>(st, L, A, r0, r1);
     const int row = r0 + threadIdx.x;
     if (row < r1) {
       double av[2];
@@ -585,7 +594,7 @@ k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
   double ts[2] = {0, 0}, tt[2] = {0, 0};
   for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
     const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = stage_tile(st, L, A, r0, r1);
+    const int s0 = stage_tile<double, true>(st, L, A, r0, r1);
     const int row = r0 + threadIdx.x;
     if (row < r1) {
       double at[2];

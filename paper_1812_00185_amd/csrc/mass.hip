@@ -37,6 +37,8 @@ namespace {
 // inside the block's range are read from LDS, the others gathered from x_k.
 // b and the iterates must be 16-byte aligned (the workspace pieces are
 // 256-byte aligned).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+
 template <int NR, int M>
 __global__ void __launch_bounds__(kBlock)
 k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __restrict__ xk,
@@ -55,9 +57,13 @@ k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __rest
 #pragma unroll
   for (int q = threadIdx.x; q < kPieces; q += kBlock) {
     if (v0 + 2 * q + 1 < vend) {
-      sb[q] = b2[q];
+      // b and x_{k-1} are read once per launch: non-temporal, so that the L2
+      // keeps x_k, which neighbouring blocks gather
+      const nt_d2 bv = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(b2) + q);
+      sb[q] = make_double2(bv.x, bv.y);
       if (!first) {
-        sm[q] = m2[q];
+        const nt_d2 mv = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(m2) + q);
+        sm[q] = make_double2(mv.x, mv.y);
         sx[q] = x2[q];
       }
     } else if (v0 + 2 * q < vend) {
@@ -110,7 +116,11 @@ k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __rest
 #pragma unroll
   for (int q = threadIdx.x; q < kPieces; q += kBlock) {
     if (v0 + 2 * q + 1 < vend) {
-      o2[q] = sm[q];
+      const double2 ov = sm[q];
+      nt_d2 o;
+      o.x = ov.x;
+      o.y = ov.y;
+      __builtin_nontemporal_store(o, reinterpret_cast<nt_d2*>(o2) + q);
       if (first) k2[q] = make_double2(0.0, 0.0);
     } else if (v0 + 2 * q < vend) {
       xnew[v0 + 2 * q] = smw[2 * q];
