@@ -386,8 +386,11 @@ int cgp_intermediates(cgp_ctx* ctx, const double** u_tilde, const double** b_c,
 /* Measurement hook.  While enabled, every launch of the selected kernel on
  * this context is bracketed by a pair of HIP events recorded on the stream
  * the kernel runs on.  kernel_id: 0 off, CGP_K_MASS_SPMV (one Chebyshev step
- * of the fused mass-matrix solves: velocity correction and, for chi = 1, the
- * rotational pressure update), CGP_K_MOM_SPMV (momentum BiCGSTAB product
+ * of the fused mass-matrix solves -- velocity correction and, for chi = 1, the
+ * rotational pressure update -- after the first, over all lattice nodes or,
+ * with lattice size 8, over the coarse-edge and vertex nodes),
+ * CGP_K_MASS_PAIR (lattice size 8: two Chebyshev steps on the interior
+ * nodes of the coarse triangles), CGP_K_MOM_SPMV (momentum BiCGSTAB product
  * v = A p^, 2 right-hand sides), CGP_K_COARSE_SPMV (coarse PCG product
  * kernel), CGP_K_MOM_ASSEMBLE (momentum matrix and right-hand side).
  * Enabling resets the accumulated time.  cgp_timing_read synchronises the
@@ -397,6 +400,7 @@ int cgp_intermediates(cgp_ctx* ctx, const double** u_tilde, const double** b_c,
 #define CGP_K_MOM_SPMV 2
 #define CGP_K_COARSE_SPMV 3
 #define CGP_K_MOM_ASSEMBLE 4
+#define CGP_K_MASS_PAIR 5
 int cgp_timing_enable(cgp_ctx* ctx, int kernel_id);
 int cgp_timing_read(cgp_ctx* ctx, double* total_ms, int64_t* launches);
 
@@ -429,6 +433,24 @@ int cgp_query_ndchol(const cgp_ctx* ctx, cgp_ndchol_info* out);
  * numbering, columns in range).  Errors: CGP_ERR_INVALID. */
 int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, const double* x, double* y, double* diag);
+
+/* Host-only check of the paired Chebyshev steps of the mass solves on a
+ * context with lattice size 8 (k = 3): runs, on the host and with every
+ * index checked, the launch sequence of one pair of steps -- a step on the
+ * coarse-edge and vertex nodes, the two-step kernel on the interior nodes of
+ * the coarse triangles, a step on the edge and vertex nodes -- and returns
+ * x_{k+1} in x1 and x_{k+2} in x2, where
+ *   x_{j+1} = x_j + ca (x_j - x_{j-1}) + cb D^-1 (b - M x_j),
+ * coef = (ca, cb) of the first step, then of the second; velocity components
+ * (0, 1) are 0 at Dirichlet nodes.  b, xm (x_{k-1}), xk, x1, x2: host
+ * [N_f][nr], fine numbering, nr 2 or 3; rowptr, col, mval as for
+ * cgp_lattice_mass_apply_host.  A value the sequence leaves unwritten comes
+ * back as NaN.  Errors: CGP_ERR_INVALID (arguments, another lattice size, an
+ * index out of range). */
+int cgp_lattice_cheb_pair_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
+                               const double* mval, int32_t nr, const double* b,
+                               const double* xm, const double* xk, const double* coef,
+                               double* x1, double* x2);
 
 /* Host-only: orders, factors and applies the nested-dissection factor of a
  * symmetric positive definite CSR matrix restricted to the rows/columns with

@@ -23,6 +23,7 @@ CGP_K_MASS_SPMV = 1
 CGP_K_MOM_SPMV = 2
 CGP_K_COARSE_SPMV = 3
 CGP_K_MOM_ASSEMBLE = 4
+CGP_K_MASS_PAIR = 5
 CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
@@ -131,6 +132,8 @@ SIGNATURES = [
     ("cgp_timing_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("cgp_query_ndchol", C.c_int, [C.c_void_p, C.POINTER(NdcholInfo)]),
     ("cgp_lattice_mass_apply_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, _dp, _dp, _dp]),
+    ("cgp_lattice_cheb_pair_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, C.c_int32, _dp, _dp, _dp,
+                                             _dp, _dp, _dp]),
     ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,
                                         C.POINTER(C.c_uint8), _dp, _dp, C.POINTER(NdcholInfo)]),
     ("cgp_ca_plan_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _ip, _ip, _ip]),

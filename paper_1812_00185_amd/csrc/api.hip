@@ -10,12 +10,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "capcg.hpp"
 #include "cgp.h"
+#include "cheb2.hpp"
 #include "device.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
@@ -130,6 +132,7 @@ struct cgp_ctx {
   double *ut = nullptr, *rhs = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr,
          *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
   double* phi_f = nullptr;
+  int32_t* vpos = nullptr;              // lattice vertex rows: CSR positions
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
   int cheb_iters = 0;
@@ -221,6 +224,10 @@ size_t carve(cgp_ctx* c, void* base) {
     d.af = w.take<double>(L.af.size());
     d.ldir = w.take<uint8_t>(L.ldir.size());
     d.lat_of = w.take<int32_t>(L.lat_of.size());
+    d.vw = L.vw;
+    d.vcol = w.take<int32_t>(L.vcol.size());
+    d.vval = w.take<double>(L.vcol.size());
+    c->vpos = w.take<int32_t>(L.vpos.size());
   }
   c->mrhs = w.take<double>(3 * nf);
   for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
@@ -336,9 +343,6 @@ size_t carve(cgp_ctx* c, void* base) {
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
   c->latd.tri_v = c->tri_c;
-  c->latd.rowptr = rp_f;
-  c->latd.col = col_f;
-  c->latd.M = c->Mval;
   c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
   return w.off + 256;
 }
@@ -758,7 +762,10 @@ int run_pcg(cgp_ctx* c, const double* b, double* x, cgp_solve_stats* st, hipStre
   return rc;
 }
 
-hipEvent_t* cheb_timer(void* c) { return timer(static_cast<cgp_ctx*>(c), CGP_K_MASS_SPMV); }
+hipEvent_t* cheb_timer(void* c, int which) {
+  return timer(static_cast<cgp_ctx*>(c),
+               which == cgp::kChebTimedPair ? CGP_K_MASS_PAIR : CGP_K_MASS_SPMV);
+}
 
 int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
                 double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s) {
@@ -784,7 +791,7 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   }
   if (nr == 0) return CGP_OK;  // the kernel wrote U and P
   const double* du = cgp::launch_cheb(c->latd, c->nf, c->mrhs, nr, c->mx, c->cheb_iters, s,
-                                      c->timed_id == CGP_K_MASS_SPMV ? cheb_timer : nullptr, c);
+                                      (c->timed_id == CGP_K_MASS_SPMV || c->timed_id == CGP_K_MASS_PAIR) ? cheb_timer : nullptr, c);
   if (!du) return fail(CGP_ERR_INVALID, "mass solve: misaligned vectors or unsupported lattice size");
   // with the lumped pressure update the kernel above wrote P already
   cgp::launch_final_update(c->nf, ut, du, p_in, phi_f, nr, cheb_p || !chi, u_out, p_out,
@@ -987,6 +994,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     HIPCHK(up((void*)d.af, L.af.data(), 8 * L.af.size()));
     HIPCHK(up((void*)d.ldir, L.ldir.data(), L.ldir.size()));
     HIPCHK(up((void*)d.lat_of, L.lat_of.data(), 4 * L.lat_of.size()));
+    HIPCHK(up((void*)d.vcol, L.vcol.data(), 4 * L.vcol.size()));
+    HIPCHK(up((void*)c->vpos, L.vpos.data(), 4 * L.vpos.size()));
   }
   c->pinned = static_cast<Scal*>(host);
   std::memset(c->pinned, 0, kHostBytes);
@@ -995,6 +1004,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     if (!c->ev[k]) HIPCHK(hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c->scal, 0, sizeof(Scal) * 8, s));
   cgp::launch_mass_assemble(c->F, c->Mval, s);
+  cgp::launch_vertex_rows((int64_t)c->lat.vpos.size(), c->vpos, c->Mval,
+                          const_cast<double*>(c->latd.vval), s);
   cgp::launch_coarse_assemble(c->C, c->nat_c, c->Kc, c->Kc32, c->Dxc, c->Dyc, c->invdKc,
                               c->invdKc32, c->lumped_c, s);
   cgp::launch_make_ell(c->C, c->Kc, c->invdKc, c->ell_w, c->ell_col, c->ell_val, c->ell_sval,
@@ -1145,17 +1156,107 @@ int cgp_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   return rc;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The values of the lattice's coarse-vertex rows from a host CSR matrix in
+// mesh numbering (rows 0 .. nV-1): every entry of those rows must be one of
+// the table's columns and every table column an entry.
+bool host_vertex_rows(const cgp::Lattice& L, int32_t n, const int32_t* rowptr, const int32_t* col,
+                      const double* mval, std::vector<double>& vval) {
+  vval.assign(L.vcol.size(), 0.0);
+  std::vector<uint8_t> hit(L.vcol.size(), 0);
+  for (int32_t v = 0; v < L.nV; ++v)
+    for (int32_t s = rowptr[v]; s < rowptr[v + 1]; ++s) {
+      if (col[s] < 0 || col[s] >= n) return false;
+      const int32_t lc = L.lat_of[col[s]];
+      int32_t k = 0;
+      while (k < L.vw && !(L.vcol[(size_t)k * L.nV + v] == lc && L.vpos[(size_t)k * L.nV + v] >= 0 &&
+                           !hit[(size_t)k * L.nV + v]))
+        ++k;
+      if (k == L.vw) return false;
+      hit[(size_t)k * L.nV + v] = 1;
+      vval[(size_t)k * L.nV + v] = mval[s];
+    }
+  for (size_t k = 0; k < hit.size(); ++k)
+    if (L.vpos[k] >= 0 && !hit[k]) return false;
+  return true;
+}
+
+// One Chebyshev step over the lattice nodes [l0, l1) as the single-step
+// kernel computes it: out = x + ca (x - xm) + cb D^-1 (b - M x).
+template <int NR>
+bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, const double* b,
+                      const double* xm, const double* x, double ca, double cb, double* out) {
+  bool ok = true;
+  for (int32_t l = l0; l < l1; ++l) {
+    double y[NR], dg;
+    cgp::lat_apply<NR, cgp::kCh2M>(v, l,
+                                   [&](int32_t k, int d) {
+                                     if (k < 0 || k >= n) {
+                                       ok = false;
+                                       return 0.0;
+                                     }
+                                     return x[(int64_t)k * NR + d];
+                                   },
+                                   y, dg);
+    const bool masked = v.ldir[l] != 0;
+    const double di = 1.0 / dg;
+    for (int d = 0; d < NR; ++d) {
+      const double xl = x[(int64_t)l * NR + d];
+      out[(int64_t)l * NR + d] =
+          (d < 2 && masked) ? 0.0 : xl + ca * (xl - xm[(int64_t)l * NR + d]) + cb * di * (b[(int64_t)l * NR + d] - y[d]);
+    }
+  }
+  return ok;
+}
+
+// The launch sequence of a pair of steps on the host: single step over
+// [EB & ~1, n), the interior kernel block by block (each phase for every
+// thread before the next), single step again.  Lattice-ordered vectors.
+template <int NR>
+bool cheb_pair_host(const cgp::LatDev& v, int32_t n, const double* b, const double* xm,
+                    const double* xk, const double* cf, double* x1, double* x2) {
+  using namespace cgp;
+  const int32_t lb = v.EB & ~1;
+  bool ok = cheb_single_host<NR>(v, n, lb, n, b, xm, xk, cf[0], cf[1], x1);
+  ch2_fault = false;
+  const Cheb2Args A{n, b, xm, xk, x1, x2, cf[0], cf[1], cf[2], cf[3]};
+  auto cp2 = [](const double* src, double* dst) {
+    dst[0] = src[0];
+    dst[1] = src[1];
+  };
+  auto S = std::make_unique<Cheb2Shared<NR>>();
+  const int nblk = (v.nT + kCh2Tris - 1) / kCh2Tris;
+  for (int blk = 0; blk < nblk; ++blk) {
+    // a slot read before it is written shows up as NaN in the results
+    std::fill_n(reinterpret_cast<double*>(S.get()), sizeof(Cheb2Shared<NR>) / sizeof(double),
+                std::nan(""));
+    for (int t = 0; t < kCh2Threads; ++t) ch2_stage<NR>(v, A, blk, t, *S, cp2, cp2);
+    for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, *S);
+    for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, *S);
+    for (int t = 0; t < kCh2Threads; ++t) ch2_write<NR>(v, A, blk, t, *S, cp2);
+  }
+  ok = ok && !ch2_fault;
+  ok = ok && cheb_single_host<NR>(v, n, lb, n, b, xk, x1, cf[2], cf[3], x2);
+  return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
 int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, const double* x, double* y, double* diag) {
   if (!c || !rowptr || !col || !mval || !x || !y || !diag) return fail(CGP_ERR_INVALID, "null argument");
   const cgp::Lattice& L = c->lat;
   cgp::LatDev v = L.host_view();
-  v.rowptr = rowptr;
-  v.col = col;
-  v.M = mval;
   const int32_t n = c->nf;
-  for (int32_t e = 0; e < rowptr[c->nc]; ++e)
-    if (col[e] < 0 || col[e] >= n) return fail(CGP_ERR_INVALID, "column index out of range");
+  std::vector<double> vval;
+  if (!host_vertex_rows(L, n, rowptr, col, mval, vval))
+    return fail(CGP_ERR_INVALID, "vertex rows: column out of range or entries differ");
+  v.vval = vval.data();
   std::vector<double> xl(n);
   std::vector<int32_t> node(n);
   for (int32_t i = 0; i < n; ++i) {
@@ -1184,6 +1285,42 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const i
   if (!known) return fail(CGP_ERR_INVALID, "unsupported lattice size");
   if (!in_range) return fail(CGP_ERR_INVALID, "lattice stencil index out of range");
   if (!diag_ok) return fail(CGP_ERR_INVALID, "lattice diagonals disagree");
+  return CGP_OK;
+}
+
+int cgp_lattice_cheb_pair_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
+                               const double* mval, int32_t nr, const double* b,
+                               const double* xm, const double* xk, const double* coef,
+                               double* x1, double* x2) {
+  if (!c || !rowptr || !col || !mval || !b || !xm || !xk || !coef || !x1 || !x2)
+    return fail(CGP_ERR_INVALID, "null argument");
+  if (nr != 2 && nr != 3) return fail(CGP_ERR_INVALID, "nr must be 2 or 3");
+  const cgp::Lattice& L = c->lat;
+  if (L.m != cgp::kCh2M) return fail(CGP_ERR_INVALID, "the two-step kernel needs lattice size 8");
+  cgp::LatDev v = L.host_view();
+  const int32_t n = c->nf;
+  std::vector<double> vval;
+  if (!host_vertex_rows(L, n, rowptr, col, mval, vval))
+    return fail(CGP_ERR_INVALID, "vertex rows: column out of range or entries differ");
+  v.vval = vval.data();
+  const size_t len = (size_t)n * nr;
+  std::vector<double> bl(len), ml(len), kl(len), o1(len, std::nan("")), o2(len, std::nan(""));
+  for (int32_t i = 0; i < n; ++i)
+    for (int d = 0; d < nr; ++d) {
+      const size_t f = (size_t)i * nr + d, t = (size_t)L.lat_of[i] * nr + d;
+      bl[t] = b[f];
+      ml[t] = xm[f];
+      kl[t] = xk[f];
+    }
+  const bool ok = nr == 3 ? cheb_pair_host<3>(v, n, bl.data(), ml.data(), kl.data(), coef, o1.data(), o2.data())
+                          : cheb_pair_host<2>(v, n, bl.data(), ml.data(), kl.data(), coef, o1.data(), o2.data());
+  if (!ok) return fail(CGP_ERR_INVALID, "two-step kernel: index out of range");
+  for (int32_t i = 0; i < n; ++i)
+    for (int d = 0; d < nr; ++d) {
+      const size_t f = (size_t)i * nr + d, t = (size_t)L.lat_of[i] * nr + d;
+      x1[f] = o1[t];
+      x2[f] = o2[t];
+    }
   return CGP_OK;
 }
 
@@ -1460,7 +1597,7 @@ int cgp_intermediates(cgp_ctx* c, const double** ut, const double** bc, const do
 
 int cgp_timing_enable(cgp_ctx* c, int kernel_id) {
   if (!c) return fail(CGP_ERR_INVALID, "null context");
-  if (kernel_id < 0 || kernel_id > CGP_K_MOM_ASSEMBLE) return fail(CGP_ERR_INVALID, "unknown kernel id");
+  if (kernel_id < 0 || kernel_id > CGP_K_MASS_PAIR) return fail(CGP_ERR_INVALID, "unknown kernel id");
   c->timed_id = kernel_id;
   c->tev_used = 0;
   return CGP_OK;

@@ -50,6 +50,9 @@ inline int stamp(int it, int phase) { return it * 8 + phase; }
 
 // ---------------------------------------------------------------- assembly
 void launch_mass_assemble(const DLevel& L, double* Mval, hipStream_t s);
+// vval[k] = Mval[vpos[k]], 0 where vpos[k] < 0 (k < n)
+void launch_vertex_rows(int64_t n, const int32_t* vpos, const double* Mval, double* vval,
+                        hipStream_t s);
 void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
                             double* Dxval, double* Dyval, double* invd, float* invd32,
                             double* lumped, hipStream_t s);
@@ -111,11 +114,14 @@ int cheb_iterations(double tol);
 // lattice layout (velocity components 0 at Dirichlet nodes); returns the
 // buffer (one of x[0..2]) holding the result, or nullptr (nothing launched)
 // when b or an iterate is not 16-byte aligned or the lattice size is not one
-// of 1, 2, 4, 8.  `timer(tctx)`, when given, supplies an event pair per
-// product launch.
+// of 1, 2, 4, 8.  `timer(tctx, which)`, when given, supplies an event pair per
+// launch of a single step after the first (which = kChebTimedSingle) and per
+// launch of the interior two-step kernel (kChebTimedPair), or nullptr.
+constexpr int kChebTimedSingle = 0;
+constexpr int kChebTimedPair = 1;
 double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
-                    double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
-                    void* tctx);
+                    double* const x[3], int iters, hipStream_t s,
+                    hipEvent_t* (*timer)(void*, int), void* tctx);
 
 // ---------------------------------------------------------------- restriction / prolongation
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,

@@ -1351,6 +1351,21 @@ void launch_mass_assemble(const DLevel& L, double* Mval, hipStream_t s) {
   k_mass_assemble<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L, Mval);
 }
 
+namespace {
+// vval[k] = Mval[vpos[k]] (0 where vpos is -1): the coarse-vertex rows of the
+// lattice mass operator from the assembled CSR values
+__global__ void k_vertex_rows(int64_t n, const int32_t* __restrict__ vpos,
+                              const double* __restrict__ Mval, double* __restrict__ vval) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) vval[i] = vpos[i] >= 0 ? Mval[vpos[i]] : 0.0;
+}
+}  // namespace
+
+void launch_vertex_rows(int64_t n, const int32_t* vpos, const double* Mval, double* vval,
+                        hipStream_t s) {
+  if (n > 0) k_vertex_rows<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, vpos, Mval, vval);
+}
+
 void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
                             double* Dxval, double* Dyval, double* invd, float* invd32,
                             double* lumped, hipStream_t s) {

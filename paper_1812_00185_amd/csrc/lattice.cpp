@@ -24,6 +24,8 @@ LatDev Lattice::host_view() const {
   d.af = af.data();
   d.ldir = ldir.data();
   d.lat_of = lat_of.data();
+  d.vw = vw;
+  d.vcol = vcol.data();
   return d;
 }
 
@@ -96,6 +98,28 @@ std::string build_lattice(const Hierarchy& h, Lattice& L) {
     if (h.dir_index[i] >= 0) L.ldir[L.lat_of[i]] = 1;
   for (int32_t l = 0; l < L.EB; ++l)
     if (L.ldir[l]) return "lattice: Dirichlet node inside a coarse triangle";
+  // coarse-vertex rows (mesh nodes 0 .. nV-1): diagonal first, then the rest
+  // of the CSR row in order
+  const Graph& g = h.gf;
+  L.vw = 1;
+  for (int32_t v = 0; v < L.nV; ++v) L.vw = std::max(L.vw, g.rowptr[v + 1] - g.rowptr[v]);
+  L.vcol.assign((size_t)L.vw * L.nV, 0);
+  L.vpos.assign((size_t)L.vw * L.nV, -1);
+  for (int32_t v = 0; v < L.nV; ++v) {
+    int32_t k = 1;
+    bool diag = false;
+    for (int32_t s = 0; s < L.vw; ++s) L.vcol[(size_t)s * L.nV + v] = L.VB + v;
+    for (int32_t s = g.rowptr[v]; s < g.rowptr[v + 1]; ++s) {
+      const int32_t c = g.col[s];
+      if (c < 0 || c >= (int32_t)N) return "lattice: vertex row column out of range";
+      const int32_t slot = c == v && !diag ? 0 : k++;
+      if (c == v) diag = true;
+      if (slot >= L.vw) return "lattice: vertex row without its diagonal";
+      L.vcol[(size_t)slot * L.nV + v] = L.lat_of[c];
+      L.vpos[(size_t)slot * L.nV + v] = s;
+    }
+    if (!diag) return "lattice: vertex row without its diagonal";
+  }
   return "";
 }
 

@@ -14,7 +14,8 @@
 //   node inside a coarse edge between T1 and T2 (fine areas A1, A2; A2 = 0 on
 //     the boundary): two neighbours along the edge with M = (A1 + A2) / 12,
 //     two neighbours inside each T_j with M = 2 A_j / 12, M_ii = (A1 + A2)/2;
-//   coarse vertex: any valence; its row of the assembled CSR matrix.
+//   coarse vertex: any valence; its row of the assembled matrix, kept as a
+//     fixed-width table with lattice column indices (the diagonal first).
 // Vectors in this layout hold, in order: the interior nodes of every coarse
 // triangle (triangle-major, rows a = 1 .. m-2 of b = 1 .. m-1-a), the m - 1
 // inner nodes of every coarse edge (from its lower-numbered end), the coarse
@@ -45,9 +46,12 @@ struct LatDev {
   const double* af;       // [nT] fine triangle area |T| / 4^k
   const uint8_t* ldir;    // [N] velocity-Dirichlet flag per lattice node
   const int32_t* lat_of;  // [N] mesh node -> lattice node
-  const int32_t* rowptr;  // fine CSR (mesh numbering), rows of the coarse vertices
-  const int32_t* col;
-  const double* M;        // assembled fine mass matrix (vertex rows)
+  // rows of the coarse vertices of the assembled mass matrix, column major
+  // [vw][nV]: entry k of vertex v at [k * nV + v]; slot 0 the diagonal, then
+  // the other entries in CSR order; short rows padded with (VB + v, 0)
+  int32_t vw;
+  const int32_t* vcol;    // lattice column indices
+  const double* vval;     // values
 };
 
 // first lattice index of interior row a (1 <= a <= m-2) within a triangle
@@ -227,17 +231,26 @@ CGP_HD inline void lat_apply(const LatDev& L, int32_t l, X x, double (&y)[NR], d
       y[d] = diag * x(l, d) + (asum / 12.0) * (x(prev, d) + x(next, d)) + acc[d];
     return;
   }
-  const int32_t v = l - L.VB;
-  diag = 0.0;
+  // coarse vertex: its table row, four entries' loads issued at a time
+  const int32_t v = l - L.VB, nV = L.nV;
+  diag = L.vval[v];
 #pragma unroll
   for (int d = 0; d < NR; ++d) y[d] = 0.0;
-  for (int32_t s = L.rowptr[v]; s < L.rowptr[v + 1]; ++s) {
-    const double mv = L.M[s];
-    const int32_t c = L.col[s];
-    if (c == v) diag = mv;
-    const int32_t lc = L.lat_of[c];
+  for (int32_t k0 = 0; k0 < L.vw; k0 += 4) {
+    int32_t lc[4];
+    double mv[4];
 #pragma unroll
-    for (int d = 0; d < NR; ++d) y[d] += mv * x(lc, d);
+    for (int q = 0; q < 4; ++q) {
+      const bool in = k0 + q < L.vw;
+      lc[q] = in ? L.vcol[(int64_t)(k0 + q) * nV + v] : l;
+      mv[q] = in ? L.vval[(int64_t)(k0 + q) * nV + v] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (k0 + q >= L.vw) break;
+#pragma unroll
+      for (int d = 0; d < NR; ++d) y[d] += mv[q] * x(lc[q], d);
+    }
   }
 }
 
@@ -253,10 +266,7 @@ CGP_HD inline double lat_diag(const LatDev& L, int32_t l) {
     }
     return 0.5 * asum;
   }
-  const int32_t v = l - L.VB;
-  for (int32_t s = L.rowptr[v]; s < L.rowptr[v + 1]; ++s)
-    if (L.col[s] == v) return L.M[s];
-  return 0.0;
+  return L.vval[l - L.VB];
 }
 
 // calls f(Lat<M>{}) for the compile-time lattice size M equal to m; returns
@@ -284,13 +294,18 @@ struct Lattice {
   std::vector<int32_t> tri_v, tri_e, edge_v, edge_t, lat_of;
   std::vector<double> af;
   std::vector<uint8_t> ldir;
-  // view with host pointers (CSR and M left empty)
+  // coarse-vertex rows of the mass matrix (see LatDev): width, lattice
+  // columns, and the position of each entry in the fine CSR arrays (-1 for
+  // padding), from which the values are gathered once M is assembled
+  int32_t vw = 0;
+  std::vector<int32_t> vcol, vpos;
+  // view with host pointers (vval left empty)
   LatDev host_view() const;
 };
 
 // Numbers the coarse edges (first encounter over triangles and local edges),
 // maps every fine node to its lattice node and checks that the map is a
-// permutation.  Returns "" on success.
+// permutation; builds the coarse-vertex rows.  Returns "" on success.
 std::string build_lattice(const Hierarchy& h, Lattice& L);
 
 }  // namespace cgp

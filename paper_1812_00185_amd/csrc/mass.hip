@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "cheb2.hpp"
 #include "device.hpp"
 #include "lattice.hpp"
 
@@ -36,18 +37,22 @@ namespace {
 // 169 us per launch against 127 us staged, 2049^2 k = 3, NR = 3); neighbours
 // inside the block's range are read from LDS, the others gathered from x_k.
 // b and the iterates must be 16-byte aligned (the workspace pieces are
-// 256-byte aligned).
+// 256-byte aligned).  The launch covers the nodes [lbase, n), lbase even (so
+// that every block range starts 16-byte aligned), with (n - lbase) / kBlock
+// blocks rounded up.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 
 template <int NR, int M>
 __global__ void __launch_bounds__(kBlock)
-k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __restrict__ xk,
-               const double* __restrict__ xkm, double* __restrict__ xnew, double ca, double cb,
-               int first) {
+k_cheb_lattice(LatDev L, int32_t n, int32_t lbase, const double* __restrict__ b,
+               double* __restrict__ xk, const double* __restrict__ xkm, double* __restrict__ xnew,
+               double ca, double cb, int first) {
   constexpr int kVals = kBlock * NR;  // doubles per block
   constexpr int kPieces = kVals / 2;  // 16-byte pieces per block
   __shared__ double2 sb[kPieces], sm[kPieces], sx[kPieces];
-  const int32_t l0 = blockIdx.x * kBlock;
+  // blocks in reverse order: the coarse-vertex rows (at the end of the
+  // layout; short rows of dependent gathers) start first instead of trailing
+  const int32_t l0 = lbase + (int32_t)(gridDim.x - 1 - blockIdx.x) * kBlock;
   const int32_t l = l0 + threadIdx.x;
   const int64_t v0 = (int64_t)l0 * NR;  // first double of the block
   const int64_t vend = (int64_t)n * NR;  // doubles in the vector
@@ -89,13 +94,11 @@ k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __rest
     } else {
       double y[NR], diag;
       // neighbours inside the block's range come from LDS
-      lat_apply<NR, M>(
-          L, l,
-          [&](int32_t i, int d) {
-            const uint32_t r = (uint32_t)(i - l0);
-            return r < (uint32_t)kBlock ? sxd[r * NR + d] : xk[(int64_t)i * NR + d];
-          },
-          y, diag);
+      auto xv = [&](int32_t i, int d) {
+        const uint32_t r = (uint32_t)(i - l0);
+        return r < (uint32_t)kBlock ? sxd[r * NR + d] : xk[(int64_t)i * NR + d];
+      };
+      lat_apply<NR, M>(L, l, xv, y, diag);
       const double di = 1.0 / diag;
 #pragma unroll
       for (int d = 0; d < NR; ++d) {
@@ -129,6 +132,36 @@ k_cheb_lattice(LatDev L, int32_t n, const double* __restrict__ b, double* __rest
   }
 }
 
+// Two Chebyshev steps on the interior nodes of kCh2Tris coarse triangles per
+// block (lattice size 8; the phases and their data flow are in cheb2.hpp).
+// 36 KB of LDS per block for NR = 3.
+template <int NR>
+__global__ void __launch_bounds__(kCh2Threads) k_cheb_pair(LatDev L, Cheb2Args A) {
+  __shared__ __align__(16) Cheb2Shared<NR> S;
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  auto ld2 = [](const double* src, double* dst) {
+    *reinterpret_cast<double2*>(dst) = *reinterpret_cast<const double2*>(src);
+  };
+  auto ldnt2 = [](const double* src, double* dst) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src));
+    *reinterpret_cast<double2*>(dst) = make_double2(v.x, v.y);
+  };
+  auto stnt2 = [](const double* src, double* dst) {
+    const double2 v = *reinterpret_cast<const double2*>(src);
+    nt_d2 o;
+    o.x = v.x;
+    o.y = v.y;
+    __builtin_nontemporal_store(o, reinterpret_cast<nt_d2*>(dst));
+  };
+  ch2_stage<NR>(L, A, blk, tid, S, ld2, ldnt2);
+  __syncthreads();
+  ch2_step1<NR>(L, A, blk, tid, S);
+  __syncthreads();
+  ch2_step2<NR>(L, A, blk, tid, S);
+  __syncthreads();
+  ch2_write<NR>(L, A, blk, tid, S, stnt2);
+}
+
 }  // namespace
 
 int cheb_iterations(double tol) {
@@ -140,36 +173,74 @@ int cheb_iterations(double tol) {
 }
 
 double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
-                    double* const x[3], int iters, hipStream_t s, hipEvent_t* (*timer)(void*),
-                    void* tctx) {
+                    double* const x[3], int iters, hipStream_t s,
+                    hipEvent_t* (*timer)(void*, int), void* tctx) {
   // the kernel moves its block ranges as 16-byte pieces
   const uintptr_t align = (uintptr_t)b | (uintptr_t)x[0] | (uintptr_t)x[1] | (uintptr_t)x[2];
   if ((align & 15) != 0 || !lat_dispatch(L.m, [](auto) {})) return nullptr;
   const double lo = 0.5, hi = 2.0;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  const int g = (n + kBlock - 1) / kBlock;
+  // step k: (ca_k, cb_k) of the three-term recurrence
   double rho = 1.0 / sigma;
-  for (int k = 0; k < iters; ++k) {
-    double ca = 0.0, cb = 1.0 / theta;
+  auto coef = [&](int k, double& ca, double& cb) {
+    ca = 0.0;
+    cb = 1.0 / theta;
     if (k > 0) {
       const double rn = 1.0 / (2.0 * sigma - rho);
       ca = rn * rho;
       cb = 2.0 * rn / delta;
       rho = rn;
     }
+  };
+  // single step k over the nodes [lbase, n); x_k in x[k % 3], x_{k-1} in
+  // x[(k + 2) % 3], x_{k+1} into x[(k + 1) % 3]
+  auto single = [&](int k, int32_t lbase, double ca, double cb) {
+    const int g = (n - lbase + kBlock - 1) / kBlock;
+    if (g <= 0) return;
     double* xk = x[k % 3];
     const double* xkm = x[(k + 2) % 3];
     double* xn = x[(k + 1) % 3];
-    hipEvent_t* ev = (timer && k > 0) ? timer(tctx) : nullptr;
+    hipEvent_t* ev = (timer && k > 0) ? timer(tctx, kChebTimedSingle) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
     lat_dispatch(L.m, [&](auto lat) {
       constexpr int M = decltype(lat)::kM;
       if (nr == 3)
-        k_cheb_lattice<3, M><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
+        k_cheb_lattice<3, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
       else
-        k_cheb_lattice<2, M><<<g, kBlock, 0, s>>>(L, n, b, xk, xkm, xn, ca, cb, k == 0);
+        k_cheb_lattice<2, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
     });
     if (ev) (void)hipEventRecord(ev[1], s);
+  };
+  // steps in pairs on lattice size 8: edge and vertex nodes (from the even
+  // node at or below EB), the interior two steps at once, edge and vertex
+  // nodes again
+  const bool pairs = L.m == kCh2M && L.nT > 0 && L.EB == L.nT * kCh2NI;
+  const int32_t lb = L.EB & ~1;
+  const int gp = (L.nT + kCh2Tris - 1) / kCh2Tris;
+  double ca, cb;
+  coef(0, ca, cb);
+  single(0, 0, ca, cb);
+  for (int k = 1; k < iters;) {
+    coef(k, ca, cb);
+    if (!pairs || k + 1 >= iters) {
+      single(k, 0, ca, cb);
+      k += 1;
+      continue;
+    }
+    double ca2, cb2;
+    coef(k + 1, ca2, cb2);
+    single(k, lb, ca, cb);
+    const Cheb2Args A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
+                      ca, cb, ca2, cb2};
+    hipEvent_t* ev = timer ? timer(tctx, kChebTimedPair) : nullptr;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (nr == 3)
+      k_cheb_pair<3><<<gp, kCh2Threads, 0, s>>>(L, A);
+    else
+      k_cheb_pair<2><<<gp, kCh2Threads, 0, s>>>(L, A);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    single(k + 1, lb, ca2, cb2);
+    k += 2;
   }
   return x[iters % 3];
 }
