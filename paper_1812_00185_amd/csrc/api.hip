@@ -1228,14 +1228,15 @@ bool cheb_pair_host(const cgp::LatDev& v, int32_t n, const double* b, const doub
     dst[1] = src[1];
   };
   auto S = std::make_unique<Cheb2Shared<NR>>();
+  static constexpr Ch2NbTable nbt = ch2_make_nb_table();
   const int nblk = (v.nT + kCh2Tris - 1) / kCh2Tris;
   for (int blk = 0; blk < nblk; ++blk) {
     // a slot read before it is written shows up as NaN in the results
     std::fill_n(reinterpret_cast<double*>(S.get()), sizeof(Cheb2Shared<NR>) / sizeof(double),
                 std::nan(""));
     for (int t = 0; t < kCh2Threads; ++t) ch2_stage<NR>(v, A, blk, t, *S, cp2, cp2);
-    for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, *S);
-    for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, *S);
+    for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, nbt.w, *S);
+    for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, nbt.w, *S);
     for (int t = 0; t < kCh2Threads; ++t) ch2_write<NR>(v, A, blk, t, *S, cp2);
   }
   ok = ok && !ch2_fault;

@@ -72,15 +72,48 @@ CGP_HD inline int ch2_ntri(const LatDev& L, int blk) {
 }
 
 // workspace slot of point (a, b) of the block's triangle g: interior points
-// in the layout's row order, edge points at (3 g + j) (m - 1) + p - 1 (local
+// in the layout's order, edge points at (3 g + j) (m - 1) + p - 1 (local
 // edge j, p steps from v_j); -1 for a vertex
 CGP_HD inline int ch2_slot(int g, int a, int b) {
   constexpr int M = kCh2M;
-  if (a >= 1 && b >= 1 && a + b <= M - 1) return g * kCh2NI + lat_rowoff(M, a) + (b - 1);
+  if (a >= 1 && b >= 1 && a + b <= M - 1) return g * kCh2NI + lat_islot(M, a, b);
   if (b == 0 && a >= 1 && a <= M - 1) return kCh2Own + (g * 3 + 0) * (M - 1) + (a - 1);
   if (a + b == M && b >= 1 && b <= M - 1) return kCh2Own + (g * 3 + 1) * (M - 1) + (b - 1);
   if (a == 0 && b >= 1 && b <= M - 1) return kCh2Own + (g * 3 + 2) * (M - 1) + (M - b - 1);
   return -1;
+}
+
+// Neighbour table of the interior stencil: for each interior position r of a
+// triangle (lat_islot order), the six neighbours in lat_apply's order --
+// (a, b-1), (a, b+1), (a+1, b), (a+1, b-1), (a-1, b), (a-1, b+1) -- as 8-bit
+// codes packed in one word: an interior position (< kCh2NI), or 32 + 7 j +
+// p - 1 for the point p steps from v_j on local edge j.  Slot in a block's
+// workspace for triangle g: g kCh2NI + code, plus kCh2Own - 32 for an edge
+// code (the edge slots of triangle g start at kCh2Own + 3 (m - 1) g, and
+// 3 (m - 1) = kCh2NI for m = 8).
+struct Ch2NbTable {
+  uint64_t w[kCh2NI];
+};
+
+constexpr int ch2_code(int a, int b) {
+  constexpr int M = kCh2M;
+  if (a >= 1 && b >= 1 && a + b <= M - 1) return lat_islot(M, a, b);
+  if (b == 0) return 32 + 0 * (M - 1) + (a - 1);
+  if (a + b == M) return 32 + 1 * (M - 1) + (b - 1);
+  return 32 + 2 * (M - 1) + (M - b - 1);
+}
+
+constexpr Ch2NbTable ch2_make_nb_table() {
+  Ch2NbTable t{};
+  for (int a = 1; a <= kCh2M - 2; ++a)
+    for (int b = 1; a + b <= kCh2M - 1; ++b) {
+      const int pts[6][2] = {{a, b - 1}, {a, b + 1},     {a + 1, b},
+                             {a + 1, b - 1}, {a - 1, b}, {a - 1, b + 1}};
+      uint64_t w = 0;
+      for (int q = 0; q < 6; ++q) w |= (uint64_t)ch2_code(pts[q][0], pts[q][1]) << (8 * q);
+      t.w[lat_islot(kCh2M, a, b)] = w;
+    }
+  return t;
 }
 
 // point (a, b) of the block's triangle g held in edge-node slot h
@@ -131,24 +164,34 @@ CGP_HD inline void ch2_stage(const LatDev& L, const Cheb2Args& A, int blk, int t
 // One Chebyshev step on the block's interior nodes: reads x (current
 // iterate, every slot), xm (previous, interior) and bb; writes out
 // (interior).  out may be xm: a thread reads its node's xm before writing
-// it, and no other thread reads that value.
+// it, and no other thread reads that value.  nbt: the neighbour table.
 template <int NR>
-CGP_HD inline void ch2_step(const LatDev& L, int blk, int tid, const double* x, const double* xm,
-                            const double* bb, double ca, double cb, double* out) {
+CGP_HD inline void ch2_step(const LatDev& L, int blk, int tid, const uint64_t* nbt,
+                            const double* x, const double* xm, const double* bb, double ca,
+                            double cb, double* out) {
   const int ntri = ch2_ntri(L, blk);
   for (int t = tid; t < ntri * kCh2NI; t += kCh2Threads) {
     const int g = t / kCh2NI;
-    int32_t Tq, a, b;
-    Ch2Lat::interior((int32_t)(t - g * kCh2NI), Tq, a, b);  // point within its triangle
+    const int r = t - g * kCh2NI;
     const int32_t T = blk * kCh2Tris + g;
     const double At = L.af[T];
-    // lat_apply's neighbour order: (a, b-1), (a, b+1), (a+1, b), (a+1, b-1),
-    // (a-1, b), (a-1, b+1)
-    const int nb[6] = {ch2_slot(g, a, b - 1),     ch2_slot(g, a, b + 1), ch2_slot(g, a + 1, b),
-                       ch2_slot(g, a + 1, b - 1), ch2_slot(g, a - 1, b), ch2_slot(g, a - 1, b + 1)};
+    const uint64_t w = nbt[r];
+    int nb[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) CH2_CHECK(nb[q] >= 0 && nb[q] < kCh2All);
-    CH2_CHECK(ch2_slot(g, a, b) == t);
+    for (int q = 0; q < 6; ++q) {
+      const int code = (int)((w >> (8 * q)) & 0xff);
+      nb[q] = g * kCh2NI + code + (code >= 32 ? kCh2Own - 32 : 0);
+    }
+#ifndef __HIP_DEVICE_COMPILE__
+    {  // host emulation: the table agrees with the points' slots
+      int32_t Tq, a, b;
+      Ch2Lat::interior((int32_t)r, Tq, a, b);
+      const int ref[6] = {ch2_slot(g, a, b - 1),     ch2_slot(g, a, b + 1), ch2_slot(g, a + 1, b),
+                          ch2_slot(g, a + 1, b - 1), ch2_slot(g, a - 1, b), ch2_slot(g, a - 1, b + 1)};
+      for (int q = 0; q < 6; ++q) CH2_CHECK(nb[q] == ref[q] && nb[q] >= 0 && nb[q] < kCh2All);
+      CH2_CHECK(ch2_slot(g, a, b) == t);
+    }
+#endif
     const bool masked = L.ldir[(int64_t)blk * kCh2Own + t] != 0;
     const double di = 1.0 / At;
 #pragma unroll
@@ -165,13 +208,13 @@ CGP_HD inline void ch2_step(const LatDev& L, int blk, int tid, const double* x, 
 // Phases 2 and 3: x_{k+1} into S.x1, then x_{k+2} over S.xm.
 template <int NR>
 CGP_HD inline void ch2_step1(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             Cheb2Shared<NR>& S) {
-  ch2_step<NR>(L, blk, tid, S.xk, S.xm, S.b, A.ca1, A.cb1, S.x1);
+                             const uint64_t* nbt, Cheb2Shared<NR>& S) {
+  ch2_step<NR>(L, blk, tid, nbt, S.xk, S.xm, S.b, A.ca1, A.cb1, S.x1);
 }
 template <int NR>
 CGP_HD inline void ch2_step2(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             Cheb2Shared<NR>& S) {
-  ch2_step<NR>(L, blk, tid, S.x1, S.xk, S.b, A.ca2, A.cb2, S.xm);
+                             const uint64_t* nbt, Cheb2Shared<NR>& S) {
+  ch2_step<NR>(L, blk, tid, nbt, S.x1, S.xk, S.b, A.ca2, A.cb2, S.xm);
 }
 
 // Phase 4: the interior ranges of x_{k+1} and x_{k+2} out as 16-byte pieces

@@ -17,9 +17,9 @@
 //   coarse vertex: any valence; its row of the assembled matrix, kept as a
 //     fixed-width table with lattice column indices (the diagonal first).
 // Vectors in this layout hold, in order: the interior nodes of every coarse
-// triangle (triangle-major, rows a = 1 .. m-2 of b = 1 .. m-1-a), the m - 1
-// inner nodes of every coarse edge (from its lower-numbered end), the coarse
-// vertices.
+// triangle (triangle-major; see lat_islot for the order within a triangle),
+// the m - 1 inner nodes of every coarse edge (from its lower-numbered end),
+// the coarse vertices.
 #pragma once
 
 #include <cstdint>
@@ -55,14 +55,30 @@ struct LatDev {
 };
 
 // first lattice index of interior row a (1 <= a <= m-2) within a triangle
-CGP_HD inline int32_t lat_rowoff(int32_t m, int32_t a) {
+CGP_HD constexpr int32_t lat_rowoff(int32_t m, int32_t a) {
   return (a - 1) * (m - 1) - ((a - 1) * a) / 2;
+}
+
+// position of the interior point (a, b) (a, b >= 1, a + b <= m - 1) in its
+// triangle's interior range.  m <= 4: rows a = 1 .. m-2 of b = 1 .. m-1-a.
+// m = 8: first the 15 points next to the edges, as one ring -- edge 0's
+// first row (b = 1, a = 1..6), edge 1's (a + b = 7, b = 2..6), edge 2's
+// (a = 1, b = 5..2) -- then the 6 inner points by rows, so that the values an
+// edge node's stencil reads inside a triangle (that triangle's first row
+// along the edge) lie in one run of 6 consecutive nodes (for edge 2, two
+// runs: positions 10..14 and 0).
+CGP_HD constexpr int32_t lat_islot(int32_t m, int32_t a, int32_t b) {
+  if (m != 8) return lat_rowoff(m, a) + (b - 1);
+  if (b == 1) return a - 1;
+  if (a + b == 7) return 4 + b;
+  if (a == 1) return 16 - b;
+  return 15 + (a - 2) * 3 - ((a - 2) * (a - 3)) / 2 + (b - 2);
 }
 
 // lattice index of point (a, b) of coarse triangle T (0 <= a, b; a + b <= m)
 CGP_HD inline int32_t lat_index(const LatDev& L, int32_t T, int32_t a, int32_t b) {
   const int32_t m = L.m;
-  if (a >= 1 && b >= 1 && a + b <= m - 1) return T * L.nI + lat_rowoff(m, a) + (b - 1);
+  if (a >= 1 && b >= 1 && a + b <= m - 1) return T * L.nI + lat_islot(m, a, b);
   if (a == 0 && b == 0) return L.VB + L.tri_v[3 * T];
   if (b == 0 && a == m) return L.VB + L.tri_v[3 * T + 1];
   if (a == 0 && b == m) return L.VB + L.tri_v[3 * T + 2];
@@ -113,8 +129,7 @@ struct Lat {
 
   // lattice index of point (a, b) of T (0 <= a, b; a + b <= M)
   CGP_HD static int32_t index(const LatDev& L, int32_t T, const LatTri& t, int32_t a, int32_t b) {
-    if (a >= 1 && b >= 1 && a + b <= M - 1)
-      return T * NI + ((a - 1) * (M - 1) - ((a - 1) * a) / 2) + (b - 1);
+    if (a >= 1 && b >= 1 && a + b <= M - 1) return T * NI + lat_islot(M, a, b);
     if (b == 0) return a == 0 ? L.VB + t.tv[0] : (a == M ? L.VB + t.tv[1] : edge_pt(L, t.te[0], a));
     if (a + b == M) return b == M ? L.VB + t.tv[2] : edge_pt(L, t.te[1], b);
     return edge_pt(L, t.te[2], M - b);  // a == 0, 0 < b < M
@@ -126,6 +141,17 @@ struct Lat {
   // known point of an edge of T, never a vertex: one select each.
   CGP_HD static void interior_nbrs(const LatDev& L, int32_t l, int32_t a, int32_t b,
                                    const LatTri& t, int32_t (&nb)[7]) {
+    if constexpr (M == 8) {  // ring order: each neighbour from its point
+      const int32_t T = l / NI;
+      nb[0] = l;
+      nb[1] = index(L, T, t, a + 1, b);
+      nb[2] = index(L, T, t, a, b + 1);
+      nb[3] = index(L, T, t, a - 1, b);
+      nb[4] = index(L, T, t, a, b - 1);
+      nb[5] = index(L, T, t, a + 1, b - 1);
+      nb[6] = index(L, T, t, a - 1, b + 1);
+      return;
+    }
     const int32_t up = M - 1 - a, dn = M - a;  // row offsets to rows a + 1 and a - 1
     const bool in_hi = a + b + 1 <= M - 1;
     nb[0] = l;
@@ -142,6 +168,28 @@ struct Lat {
     constexpr int32_t D = NI > 0 ? NI : 1;
     T = l / D;
     int32_t r = l - T * D;
+    if constexpr (M == 8) {  // inverse of lat_islot
+      if (r < 6) {
+        a = r + 1;
+        b = 1;
+      } else if (r < 11) {
+        b = r - 4;
+        a = 7 - b;
+      } else if (r < 15) {
+        a = 1;
+        b = 16 - r;
+      } else if (r < 18) {
+        a = 2;
+        b = r - 13;
+      } else if (r < 20) {
+        a = 3;
+        b = r - 16;
+      } else {
+        a = 4;
+        b = 2;
+      }
+      return;
+    }
     a = 1;
 #pragma unroll
     for (int32_t k = 1; k <= M - 3; ++k) {

@@ -132,6 +132,9 @@ k_cheb_lattice(LatDev L, int32_t n, int32_t lbase, const double* __restrict__ b,
   }
 }
 
+// neighbour table of the interior stencil (cheb2.hpp), in constant memory
+__constant__ Ch2NbTable kCh2NbDev = ch2_make_nb_table();
+
 // Two Chebyshev steps on the interior nodes of kCh2Tris coarse triangles per
 // block (lattice size 8; the phases and their data flow are in cheb2.hpp).
 // 36 KB of LDS per block for NR = 3.
@@ -155,9 +158,9 @@ __global__ void __launch_bounds__(kCh2Threads) k_cheb_pair(LatDev L, Cheb2Args A
   };
   ch2_stage<NR>(L, A, blk, tid, S, ld2, ldnt2);
   __syncthreads();
-  ch2_step1<NR>(L, A, blk, tid, S);
+  ch2_step1<NR>(L, A, blk, tid, kCh2NbDev.w, S);
   __syncthreads();
-  ch2_step2<NR>(L, A, blk, tid, S);
+  ch2_step2<NR>(L, A, blk, tid, kCh2NbDev.w, S);
   __syncthreads();
   ch2_write<NR>(L, A, blk, tid, S, stnt2);
 }
