@@ -352,28 +352,52 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
     double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-    for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
-      const int j = L.col[s];
-      const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
-      const double2 pj = L.xy[j];
+    // Every gather of a slot (node j and both side vertices) is issued before
+    // any arithmetic -- a missing side reads node j instead and its terms are
+    // skipped -- so a slot waits for two memory round trips (the column and
+    // sides, then the node data) instead of one per side.
+    struct Slot {
+      int j;
+      int2 sd;
+      double2 pj, wj, rj, pk[2], wk[2];
+      double Pj, tj[2];
+    };
+    const int2* side2 = reinterpret_cast<const int2*>(L.side);
+    auto load = [&](int s, Slot& d) {
+      d.j = L.col[s];
+      d.sd = side2[s];
+      const int j = d.j;
+      const int k0 = d.sd.x >= 0 ? d.sd.x : j, k1 = d.sd.y >= 0 ? d.sd.y : j;
+      d.pj = L.xy[j];
+      d.wj = W[j];
+      d.rj = R[j];
+      d.Pj = p ? p[j] : 0.0;
+      d.pk[0] = L.xy[k0];
+      d.wk[0] = W[k0];
+      d.pk[1] = L.xy[k1];
+      d.wk[1] = W[k1];
       if constexpr (kTrac) {
-        if (sd.x < 0 || sd.y < 0) {  // boundary edge: natural on a free row
+        d.tj[0] = tn[j];
+        d.tj[1] = tn[n + j];
+      }
+    };
+    auto add = [&](int s, const Slot& d) {
+      const double2 pj = d.pj;
+      if constexpr (kTrac) {
+        if (d.sd.x < 0 || d.sd.y < 0) {  // boundary edge: natural on a free row
           const double l = sqrt((pj.x - pi.x) * (pj.x - pi.x) + (pj.y - pi.y) * (pj.y - pi.y));
-          acc[7] += l * (2.0 * tn[i] + tn[j]) * (1.0 / 6.0);
-          acc[8] += l * (2.0 * tn[n + i] + tn[n + j]) * (1.0 / 6.0);
+          acc[7] += l * (2.0 * tn[i] + d.tj[0]) * (1.0 / 6.0);
+          acc[8] += l * (2.0 * tn[n + i] + d.tj[1]) * (1.0 / 6.0);
         }
       }
-      const double2 wj = W[j], rj = R[j];
-      const double wjx = wj.x, wjy = wj.y;
-      const double Pj = p ? p[j] : 0.0;
+      const double wjx = d.wj.x, wjy = d.wj.y;
+      const double Pj = d.Pj;
       double m = 0.0, kk = 0.0, nn = 0.0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int k = q == 0 ? sd.x : sd.y;
-        if (k < 0) continue;
-        const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
-        const double2 wk = W[k];
-        const double wkx = wk.x, wky = wk.y;
+        if ((q == 0 ? d.sd.x : d.sd.y) < 0) continue;
+        const SideGeo g = side_geo(pi, pj, d.pk[q], q == 0 ? 1.0 : -1.0);
+        const double wkx = d.wk[q].x, wky = d.wk[q].y;
         m += g.area * (1.0 / 12.0);
         kk += (g.bi * g.bj + g.ci * g.cj) / (4.0 * g.area);
         nn += ((2.0 * wix + wjx + wkx) * g.bj + (2.0 * wiy + wjy + wky) * g.cj) * (1.0 / 24.0);
@@ -384,8 +408,13 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       acc[0] += m;
       acc[1] += kk;
       acc[2] += nn;
-      acc[3] += m * rj.x;
-      acc[4] += m * rj.y;
+      acc[3] += m * d.rj.x;
+      acc[4] += m * d.rj.y;
+    };
+    for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
+      Slot a;
+      load(s, a);
+      add(s, a);
     }
     group_sum<NA>(acc);
     if (lane == 0) {
@@ -1059,22 +1088,45 @@ k_correct_rhs(DLevel L, const int32_t* __restrict__ dir_index, const double* __r
     const double phii = phi[i];
     const double ui = ut[i], vi = ut[n + i];
     double acc[3] = {0.0, 0.0, 0.0};  // gx, gy, div
-    for (int s = beg + 1 + lane; s < end; s += kRowLanes) {
+    // as in the momentum assembly: every gather of a lane's two slots is
+    // issued before any arithmetic (a missing side reads node j instead)
+    struct Slot {
+      int2 sd;
+      double2 pj, pk[2];
+      double phj, uj, vj;
+    };
+    const int2* side2 = reinterpret_cast<const int2*>(L.side);
+    auto load = [&](int s, Slot& d) {
       const int j = L.col[s];
-      const int2 sd = reinterpret_cast<const int2*>(L.side)[s];
-      const double2 pj = L.xy[j];
-      const double ph = phi[j] + 0.5 * phii;
-      const double uj = chi ? ut[j] : 0.0, vj = chi ? ut[n + j] : 0.0;
+      d.sd = side2[s];
+      const int k0 = d.sd.x >= 0 ? d.sd.x : j, k1 = d.sd.y >= 0 ? d.sd.y : j;
+      d.pj = L.xy[j];
+      d.phj = phi[j];
+      d.uj = chi ? ut[j] : 0.0;
+      d.vj = chi ? ut[n + j] : 0.0;
+      d.pk[0] = L.xy[k0];
+      d.pk[1] = L.xy[k1];
+    };
+    auto add = [&](const Slot& d) {
+      const double ph = d.phj + 0.5 * phii;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const int k = q == 0 ? sd.x : sd.y;
-        if (k < 0) continue;
-        const SideGeo g = side_geo(pi, pj, L.xy[k], q == 0 ? 1.0 : -1.0);
+        if ((q == 0 ? d.sd.x : d.sd.y) < 0) continue;
+        const SideGeo g = side_geo(pi, d.pj, d.pk[q], q == 0 ? 1.0 : -1.0);
         acc[0] += g.bi * ph;
         acc[1] += g.ci * ph;
         if (chi)
-          acc[2] += (g.bj * uj + g.cj * vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
+          acc[2] += (g.bj * d.uj + g.cj * d.vj) * (1.0 / 6.0) + (g.bi * ui + g.ci * vi) * (1.0 / 12.0);
       }
+    };
+    for (int s0 = beg + 1 + lane; s0 < end; s0 += 2 * kRowLanes) {
+      const int s1 = s0 + kRowLanes;
+      const bool two = s1 < end;
+      Slot a, b;
+      load(s0, a);
+      load(two ? s1 : s0, b);
+      add(a);
+      if (two) add(b);
     }
     group_sum<3>(acc);
     if (lane == 0) {
