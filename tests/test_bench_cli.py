@@ -34,12 +34,23 @@ def test_algorithmic_bytes_at_2049():
     # 257^2 pressure mesh: 131,072 triangles, 197,120 edges, 66,049 vertices
     nf, zf, t, e, v = 4198401, 29372417, 131072, 197120, 66049
     mass = bench.KERNELS["mass_spmv"][1]
-    assert mass(nf, zf, 3, t, e, v) == 422221941
+    # lattice size 8: the step over the coarse-edge and vertex nodes, from the
+    # even node at or below the 21 t interior nodes
+    r = nf - 21 * t
+    assert r == 7 * e + v and (21 * t) % 2 == 0
+    assert mass(nf, zf, 3, t, e, v, 3) == (96 * r + r + 360 * t + 16 * e + 32 * t
+                                           + 12 * (2 * e + v)) == 200308845
+    # other lattice sizes: the step over every node
+    assert mass(nf, zf, 3, t, e, v, 2) == 422221941
+    pair = bench.KERNELS["mass_pair"][1]
+    assert pair(nf, zf, 3, t, e, v, 3) == 21 * t * 121 + 7 * e * 48 + 32 * t == 403480576
+    # the interior and edge ranges cover the vector
+    assert 21 * t + 7 * e + v == nf
     mom = bench.KERNELS["mom_spmv"][1]
-    assert mom(nf, zf, 3, t, e, v) == 12 * zf + 4 * (nf + 1) + 48 * nf == 570785860
+    assert mom(nf, zf, 3, t, e, v, 3) == 12 * zf + 4 * (nf + 1) + 48 * nf == 570785860
     pcg = bench.KERNELS["coarse_spmv"][1]
     # the fine-scale calibration: the 2049^2 square as the Poisson mesh
-    assert pcg(nf, zf, 0, 0, 0, 0) == 738721900
+    assert pcg(nf, zf, 0, 0, 0, 0, 0) == 738721900
 
 
 def test_counter_records_are_read_or_declined():
