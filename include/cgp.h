@@ -434,6 +434,18 @@ int cgp_query_ndchol(const cgp_ctx* ctx, cgp_ndchol_info* out);
 int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, const double* x, double* y, double* diag);
 
+/* Host-only check of the right-hand sides of the consistent-mass solves as
+ * the library forms them on the lattice layout (fine geometry from the coarse
+ * triangles): for host phi_f [N_f] and u_tilde [2][N_f] (fine numbering),
+ * rhs [N_f][3] receives -(2/3) dt (G phi_f)_i (0 on velocity-Dirichlet rows)
+ * in its first two entries and, for chi = 1, -nu (D U~)_i in the third (0
+ * for chi = 0), with G = -D^T and (D U)_i the integral of psi_i div U_h
+ * (Eqs. 25-26).  With phi_c [N_c] (not NULL) phi_f is taken to be its
+ * prolongation (Eq. 24), the form cgp_project_step uses, and phi_f is not
+ * read (may be NULL).  Every index is checked.  Errors: CGP_ERR_INVALID. */
+int cgp_lattice_correct_rhs_host(const cgp_ctx* ctx, const double* phi_f, const double* phi_c,
+                                 const double* u_tilde, double* rhs);
+
 /* Host-only check of the paired Chebyshev steps of the mass solves on a
  * context with lattice size 8 (k = 3): runs, on the host and with every
  * index checked, the launch sequence of one pair of steps -- a step on the

@@ -18,6 +18,7 @@
 #include "capcg.hpp"
 #include "cgp.h"
 #include "cheb2.hpp"
+#include "corrlat.hpp"
 #include "device.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
@@ -133,6 +134,8 @@ struct cgp_ctx {
          *v = nullptr, *phat = nullptr, *shat = nullptr, *t = nullptr;
   double* phi_f = nullptr;
   int32_t* vpos = nullptr;              // lattice vertex rows: CSR positions
+  int32_t* node_of = nullptr;           // [N_f] lattice node -> mesh node
+  double* corr_v4 = nullptr;            // [N_f][4] correction inputs in lattice order
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
   int cheb_iters = 0;
@@ -228,6 +231,8 @@ size_t carve(cgp_ctx* c, void* base) {
     d.vcol = w.take<int32_t>(L.vcol.size());
     d.vval = w.take<double>(L.vcol.size());
     c->vpos = w.take<int32_t>(L.vpos.size());
+    c->node_of = w.take<int32_t>(L.node_of.size());
+    c->corr_v4 = w.take<double>(4 * L.node_of.size());
   }
   c->mrhs = w.take<double>(3 * nf);
   for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
@@ -767,8 +772,10 @@ hipEvent_t* cheb_timer(void* c, int which) {
                which == cgp::kChebTimedPair ? CGP_K_MASS_PAIR : CGP_K_MASS_SPMV);
 }
 
+// phi_c: the coarse increment phi_f was prolonged from (Eq. 24), or nullptr
 int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double* p_in,
-                double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s) {
+                double* u_out, double* p_out, cgp_solve_stats* st, hipStream_t s,
+                const double* phi_c = nullptr) {
   const cgp_problem& P = c->prob;
   const int chi = P.chi;
   const int mode = P.mass_mode;
@@ -779,8 +786,16 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   const bool cheb_u = mode != CGP_MASS_LUMPED;
   const bool cheb_p = chi && mode == CGP_MASS_CONSISTENT;
   const int nr = cheb_u ? (cheb_p ? 3 : 2) : 0;
-  cgp::launch_correct_rhs(c->F, c->dir_index, c->Mval, P.dt, P.nu, chi, mode, phi_f, ut, p_in,
-                          c->mrhs, u_out, p_out, c->latd.lat_of, s);
+  if (mode == CGP_MASS_CONSISTENT) {
+    // right-hand sides on the lattice layout, geometry from the coarse mesh
+    const cgp::CorrLatArgs A{c->nf,      reinterpret_cast<const double*>(c->C.xy), c->cn_ptr,
+                             c->cn_tri, c->corr_v4, phi_c, P.dt, P.nu, chi};
+    if (!cgp::launch_correct_rhs_lattice(c->latd, c->node_of, phi_f, ut, A, c->mrhs, s))
+      return fail(CGP_ERR_INVALID, "correction right-hand side: misaligned buffer or unsupported lattice size");
+  } else {
+    cgp::launch_correct_rhs(c->F, c->dir_index, c->Mval, P.dt, P.nu, chi, mode, phi_f, ut, p_in,
+                            c->mrhs, u_out, p_out, c->latd.lat_of, s);
+  }
   if (st) {
     // a-priori bound of the Chebyshev iteration on [1/2, 2]; lumped: exact
     const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
@@ -996,6 +1011,7 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     HIPCHK(up((void*)d.lat_of, L.lat_of.data(), 4 * L.lat_of.size()));
     HIPCHK(up((void*)d.vcol, L.vcol.data(), 4 * L.vcol.size()));
     HIPCHK(up((void*)c->vpos, L.vpos.data(), 4 * L.vpos.size()));
+    HIPCHK(up((void*)c->node_of, L.node_of.data(), 4 * L.node_of.size()));
   }
   c->pinned = static_cast<Scal*>(host);
   std::memset(c->pinned, 0, kHostBytes);
@@ -1325,6 +1341,35 @@ int cgp_lattice_cheb_pair_host(const cgp_ctx* c, const int32_t* rowptr, const in
   return CGP_OK;
 }
 
+int cgp_lattice_correct_rhs_host(const cgp_ctx* c, const double* phi_f, const double* phi_c,
+                                 const double* u_tilde, double* rhs) {
+  if (!c || (!phi_f && !phi_c) || !u_tilde || !rhs) return fail(CGP_ERR_INVALID, "null argument");
+  const cgp::Lattice& L = c->lat;
+  const cgp::LatDev v = L.host_view();
+  const int32_t n = c->nf;
+  std::vector<double> v4(4 * (size_t)n);
+  cgp::corr_fault = false;
+  for (int32_t l = 0; l < n; ++l)
+    cgp::corr_gather(n, L.node_of.data(), phi_c ? nullptr : phi_f, u_tilde, l, v4.data());
+  const cgp::CorrLatArgs A{n,         c->h.coarse.xy.data(), c->h.cn_ptr.data(), c->h.cn_tri.data(),
+                           v4.data(), phi_c, c->prob.dt, c->prob.nu, c->prob.chi};
+  const bool known = cgp::lat_dispatch(v.m, [&](auto lat) {
+    constexpr int M = decltype(lat)::kM;
+    for (int32_t l = 0; l < n; ++l) {
+      double out[3];
+      if (phi_c)
+        cgp::corr_node<M, true>(v, A, l, out);
+      else
+        cgp::corr_node<M, false>(v, A, l, out);
+      const int32_t i = L.node_of[l];
+      for (int d = 0; d < 3; ++d) rhs[3 * (int64_t)i + d] = out[d];
+    }
+  });
+  if (!known) return fail(CGP_ERR_INVALID, "unsupported lattice size");
+  if (cgp::corr_fault) return fail(CGP_ERR_INVALID, "correction stencil index out of range");
+  return CGP_OK;
+}
+
 int cgp_query_ndchol(const cgp_ctx* c, cgp_ndchol_info* out) {
   if (!c || !out) return fail(CGP_ERR_INVALID, "null argument");
   const cgp::NdFactor& f = c->nd;
@@ -1438,7 +1483,8 @@ int project_step(cgp_ctx* c, cgp_state* S, const double* u_dir, const double* f,
   if (rc < 0) return rc;
   cgp::launch_prolong(c->nf, c->pcode, c->tri_c, c->prob.levels, phi_new, c->phi_f, s);
   cgp_solve_stats cs[3];
-  rc = worst(rc, run_correct(c, c->ut, c->phi_f, noninc ? nullptr : S->p, S->u_prev, S->p, cs, s));
+  rc = worst(rc, run_correct(c, c->ut, c->phi_f, noninc ? nullptr : S->p, S->u_prev, S->p, cs, s,
+                             phi_new));
   if (rc < 0) return rc;
   T->mass[0] = cs[0];
   T->mass[1] = cs[1];

@@ -148,6 +148,14 @@ void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double*
                         double dt, double nu, int chi, int mass_mode, const double* phi_f,
                         const double* ut, const double* p_in, double* rhs, double* u_out,
                         double* p_out, const int32_t* lat_of, hipStream_t s);
+// the same right-hand sides for mass mode CGP_MASS_CONSISTENT on the lattice
+// layout (corrlat.hpp): first A.v4 ([n][4] from phi_f and U~, or [n][2] from
+// U~ when A.phi_c is given, phi_f then being its prolongation) through
+// node_of, then rhs [n][2 + chi]; rhs and A.v4 16-byte aligned; false
+// (nothing launched) for a misaligned buffer or an unsupported lattice size
+bool launch_correct_rhs_lattice(const LatDev& L, const int32_t* node_of, const double* phi,
+                                const double* ut, const struct CorrLatArgs& A, double* rhs,
+                                hipStream_t s);
 // U = U~ + dU from the solved increments du [n][nr]; P = P + phi (+ du[2]
 // when nr = 3) unless write_p is false
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,

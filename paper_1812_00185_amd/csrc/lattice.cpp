@@ -93,6 +93,8 @@ std::string build_lattice(const Hierarchy& h, Lattice& L) {
     seen[l] = 1;
     L.lat_of[i] = l;
   }
+  L.node_of.assign(N, 0);
+  for (int32_t i = 0; i < (int32_t)N; ++i) L.node_of[L.lat_of[i]] = i;
   L.ldir.assign(N, 0);
   for (int32_t i = 0; i < (int32_t)N; ++i)
     if (h.dir_index[i] >= 0) L.ldir[L.lat_of[i]] = 1;

@@ -347,6 +347,7 @@ struct Lattice {
   // padding), from which the values are gathered once M is assembled
   int32_t vw = 0;
   std::vector<int32_t> vcol, vpos;
+  std::vector<int32_t> node_of;  // [N] lattice node -> mesh node (inverse of lat_of)
   // view with host pointers (vval left empty)
   LatDev host_view() const;
 };

@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "cheb2.hpp"
+#include "corrlat.hpp"
 #include "device.hpp"
 #include "lattice.hpp"
 
@@ -165,7 +166,67 @@ __global__ void __launch_bounds__(kCh2Threads) k_cheb_pair(LatDev L, Cheb2Args A
   ch2_write<NR>(L, A, blk, tid, S, stnt2);
 }
 
+// Right-hand sides of the consistent-mass solves on the lattice layout (one
+// thread per lattice node; the stencils are in corrlat.hpp): rhs [n][NR],
+// NR = 2 + chi, written through LDS as 16-byte pieces of the block's range.
+template <int NR, int M, bool kPc>
+__global__ void __launch_bounds__(kBlock) k_correct_rhs_lat(LatDev L, CorrLatArgs A,
+                                                            double* __restrict__ rhs) {
+  constexpr int kPieces = kBlock * NR / 2;
+  __shared__ double2 so[kPieces];
+  double* sod = reinterpret_cast<double*>(so);
+  const int32_t n = A.n;
+  const int32_t l0 = blockIdx.x * kBlock;
+  const int32_t l = l0 + threadIdx.x;
+  if (l < n) {
+    double out[3];
+    corr_node<M, kPc>(L, A, l, out);
+#pragma unroll
+    for (int d = 0; d < NR; ++d) sod[threadIdx.x * NR + d] = out[d];
+  }
+  __syncthreads();
+  const int64_t v0 = (int64_t)l0 * NR, vend = (int64_t)n * NR;
+  double2* o2 = reinterpret_cast<double2*>(rhs + v0);
+  for (int q = threadIdx.x; q < kPieces; q += kBlock) {
+    if (v0 + 2 * q + 1 < vend)
+      o2[q] = so[q];
+    else if (v0 + 2 * q < vend)
+      rhs[v0 + 2 * q] = sod[2 * q];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_corr_gather(int32_t n, const int32_t* __restrict__ node_of, const double* __restrict__ phi,
+              const double* __restrict__ ut, double* __restrict__ v4) {
+  const int32_t l = blockIdx.x * kBlock + threadIdx.x;
+  if (l < n) corr_gather(n, node_of, phi, ut, l, v4);
+}
+
 }  // namespace
+
+bool launch_correct_rhs_lattice(const LatDev& L, const int32_t* node_of, const double* phi,
+                                const double* ut, const CorrLatArgs& A, double* rhs,
+                                hipStream_t s) {
+  if (((uintptr_t)rhs & 15) != 0 || ((uintptr_t)A.v4 & 15) != 0) return false;
+  const int g = (A.n + kBlock - 1) / kBlock;
+  if (!lat_dispatch(L.m, [](auto) {})) return false;
+  // with phi_c the copy holds U~ only
+  k_corr_gather<<<g, kBlock, 0, s>>>(A.n, node_of, A.phi_c ? nullptr : phi, ut,
+                                     const_cast<double*>(A.v4));
+  return lat_dispatch(L.m, [&](auto lat) {
+    constexpr int M = decltype(lat)::kM;
+    if (A.phi_c) {
+      if (A.chi)
+        k_correct_rhs_lat<3, M, true><<<g, kBlock, 0, s>>>(L, A, rhs);
+      else
+        k_correct_rhs_lat<2, M, true><<<g, kBlock, 0, s>>>(L, A, rhs);
+    } else if (A.chi) {
+      k_correct_rhs_lat<3, M, false><<<g, kBlock, 0, s>>>(L, A, rhs);
+    } else {
+      k_correct_rhs_lat<2, M, false><<<g, kBlock, 0, s>>>(L, A, rhs);
+    }
+  });
+}
 
 int cheb_iterations(double tol) {
   // error reduction 2 ((sqrt(k)-1)/(sqrt(k)+1))^m with k = 4 (interval [1/2, 2]),

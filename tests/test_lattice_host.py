@@ -161,3 +161,58 @@ def test_cheb_pair_host_rejects_other_lattice_sizes(N):
         assert rc != 0 and b"lattice size 8" in g.lib.cgp_last_error()
     finally:
         g.close()
+
+
+# ------------------------------------------------ correction right-hand sides
+
+RHS_CASES = [
+    ("square_k1_natural", lambda: unit_square(9, tags={"left": NATURAL}), 1, 1),
+    ("square_k2", lambda: unit_square(17), 2, 0),
+    ("square_k3", lambda: unit_square(9), 3, 1),
+    ("square_k3_natural", lambda: unit_square(9, tags={"left": NATURAL}), 3, 1),
+    ("disc_k3", lambda: disc(30, 80, seed=1), 3, 1),
+    ("channel_k2", lambda: channel_cylinder(0.08), 2, 1),
+    ("square_k0", lambda: unit_square(9), 0, 1),
+]
+
+
+@pytest.mark.parametrize("name,meshf,k,chi", RHS_CASES, ids=[c[0] for c in RHS_CASES])
+def test_lattice_correction_rhs_matches_assembled(N, name, meshf, k, chi):
+    """The right-hand sides of Eqs. 25-26 as the library forms them on the
+    lattice layout (geometry from the coarse triangles, interior stencils
+    from coefficient differences, edge and vertex nodes triangle by
+    triangle) against the oracle's assembled G = -D^T and D on the fine mesh,
+    for arbitrary (not prolonged) phi_f and U~, natural boundaries
+    included."""
+    from paper_1812_00185_amd.solver import CGP
+
+    mesh = meshf()
+    dt, nu = 1e-3, 1e-2
+    g = CGP(mesh, k, dt, nu, chi=chi, device="cpu")
+    try:
+        F = Operators(Hierarchy(mesh, k).fine)
+        rng = np.random.default_rng(k + 11 * chi + len(name))
+        phi = rng.standard_normal(g.nf)
+        ut = rng.standard_normal((2, g.nf))
+        dp = C.POINTER(C.c_double)
+        hier = Hierarchy(mesh, k)
+        phic = rng.standard_normal(g.nc)
+        # arbitrary phi_f; then phi_f = P phi_c given as phi_c (the step's form)
+        for label, pf, pc in (("phi_f", phi, None), ("phi_c", hier.prolong(phic), phic)):
+            rhs = np.empty((g.nf, 3))
+            rc = g.lib.cgp_lattice_correct_rhs_host(
+                g.ctx, pf.ctypes.data_as(dp) if pc is None else None,
+                None if pc is None else pc.ctypes.data_as(dp),
+                np.ascontiguousarray(ut).ctypes.data_as(dp), rhs.ctypes.data_as(dp))
+            assert rc == 0, g.lib.cgp_last_error()
+            ref_u = -(2.0 / 3.0) * dt * F.grad(pf)
+            ref_u[:, g.dirichlet_nodes] = 0.0
+            ref_p = -nu * F.div(ut) if chi else np.zeros(g.nf)
+            eu = np.abs(rhs[:, :2].T - ref_u).max() / np.abs(ref_u).max()
+            ep = np.abs(rhs[:, 2] - ref_p).max() / max(np.abs(ref_p).max(), 1e-300)
+            print(f"[corr rhs] {name} ({label}): N_f={g.nf} velocity {eu:.1e} pressure {ep:.1e}")
+            assert eu < 1e-13
+            assert (ep < 1e-13) if chi else np.all(rhs[:, 2] == 0.0)
+            assert np.all(rhs[g.dirichlet_nodes, :2] == 0.0)
+    finally:
+        g.close()
