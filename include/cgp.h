@@ -434,6 +434,21 @@ int cgp_query_ndchol(const cgp_ctx* ctx, cgp_ndchol_info* out);
 int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, const double* x, double* y, double* diag);
 
+/* Host-only check of the momentum rows (Eq. 21) that the library assembles
+ * on the lattice layout: for host u_prev, u [2][N_f], p [N_f] (may be NULL:
+ * no pressure term), u_dir [2][n_dirichlet], f [2][N_f] and t_nat [2][N_f]
+ * (may be NULL), fills the rows of the fine nodes other than the coarse
+ * vertices: aval [nnz_fine] of A = 3/2 M + dt nu K + dt N(2 U^n - U^{n-1})
+ * (identity on Dirichlet rows), rhs [2][N_f] and x0 [2][N_f], every other
+ * entry NaN; rowptr [N_f + 1] and col [nnz_fine] receive the library's fine
+ * CSR structure (diagonal first in each row, then the columns in increasing
+ * order).  Errors: CGP_ERR_INVALID (arguments, or a context whose fine rows
+ * do not all have the lattice form). */
+int cgp_lattice_momentum_host(const cgp_ctx* ctx, const double* u_prev, const double* u,
+                              const double* p, const double* u_dir, const double* f,
+                              const double* t_nat, int32_t* rowptr, int32_t* col, double* aval,
+                              double* rhs, double* x0);
+
 /* Host-only check of the right-hand sides of the consistent-mass solves as
  * the library forms them on the lattice layout (fine geometry from the coarse
  * triangles): for host phi_f [N_f] and u_tilde [2][N_f] (fine numbering),

@@ -19,6 +19,7 @@
 #include "cgp.h"
 #include "cheb2.hpp"
 #include "corrlat.hpp"
+#include "momlat.hpp"
 #include "device.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
@@ -136,6 +137,12 @@ struct cgp_ctx {
   int32_t* vpos = nullptr;              // lattice vertex rows: CSR positions
   int32_t* node_of = nullptr;           // [N_f] lattice node -> mesh node
   double* corr_v4 = nullptr;            // [N_f][4] correction inputs in lattice order
+  uint8_t* mslot = nullptr;             // [N_f][8] lattice momentum rows: CSR offsets
+  cgp::MomRow* mrow = nullptr;          // [N_f] their neighbour and triangle records
+  cgp::MomTri* mtri = nullptr;          // [nT] coarse-triangle coefficients
+  std::vector<cgp::MomRow> mrow_h;      // host copies (set-up)
+  std::vector<cgp::MomTri> mtri_h;
+  cgp::MomLattice mlat{};               // their launch description
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
   int cheb_iters = 0;
@@ -233,6 +240,9 @@ size_t carve(cgp_ctx* c, void* base) {
     c->vpos = w.take<int32_t>(L.vpos.size());
     c->node_of = w.take<int32_t>(L.node_of.size());
     c->corr_v4 = w.take<double>(4 * L.node_of.size());
+    c->mslot = w.take<uint8_t>(L.mslot.size());
+    c->mrow = w.take<cgp::MomRow>(c->mrow_h.size());
+    c->mtri = w.take<cgp::MomTri>(c->mtri_h.size());
   }
   c->mrhs = w.take<double>(3 * nf);
   for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
@@ -348,6 +358,7 @@ size_t carve(cgp_ctx* c, void* base) {
 
   c->F = DLevel{c->nf, (int32_t)nnzf, rp_f, col_f, side_f, xy_f, tile_f, c->h.gf.ntiles()};
   c->latd.tri_v = c->tri_c;
+  c->mlat = cgp::MomLattice{c->mslot, c->mrow, c->mtri, c->lat.nV};
   c->C = DLevel{c->nc, (int32_t)nnzc, rp_c, col_c, side_c, xy_c, tile_c, c->h.gc.ntiles()};
   return w.off + 256;
 }
@@ -465,7 +476,8 @@ int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
   const cgp_problem& P = c->prob;
   cgp::launch_momentum_assemble(c->F, c->dir_index, P.dt, P.nu, u_prev, u, p, u_dir, c->ndir,
                                 f, t_nat, c->Aval, c->invdA, c->rhs, ut,
-                                c->phat, c->shat, s, timer(c, CGP_K_MOM_ASSEMBLE));
+                                c->phat, c->shat, s, timer(c, CGP_K_MOM_ASSEMBLE),
+                                c->lat.mom_ok ? &c->mlat : nullptr);
   cgp::BicgVecs V{ut, c->r, c->rhat, c->p, c->v, c->phat, c->shat, c->t, c->rhs, c->invdA};
   cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
   Scal out[2];
@@ -873,6 +885,21 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   }
   try {
     err = cgp::build_lattice(c->h, c->lat);
+    if (err.empty()) cgp::build_mom_slots(c->h, c->lat);
+    if (err.empty() && c->lat.mom_ok) {
+      // row records (mesh numbering) and coarse-triangle coefficients
+      const cgp::Lattice& L = c->lat;
+      const cgp::LatDev v = L.host_view();
+      c->mrow_h.assign(L.lat_of.size(), cgp::MomRow{{-1, -1, -1, -1, -1, -1}, {-1, -1}});
+      c->mtri_h.resize(L.nT);
+      cgp::lat_dispatch(v.m, [&](auto lat) {
+        constexpr int M = decltype(lat)::kM;
+        for (int32_t i = L.nV; i < (int32_t)L.lat_of.size(); ++i)
+          c->mrow_h[i] = cgp::mom_row_record<M>(v, L.node_of.data(), L.lat_of[i]);
+        for (int32_t T = 0; T < L.nT; ++T)
+          c->mtri_h[T] = cgp::mom_tri_coef<M>(v, c->h.coarse.xy.data(), T);
+      });
+    }
   } catch (const std::exception& e) {
     err = std::string("lattice set-up failed: ") + e.what();
   }
@@ -1012,6 +1039,9 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     HIPCHK(up((void*)d.vcol, L.vcol.data(), 4 * L.vcol.size()));
     HIPCHK(up((void*)c->vpos, L.vpos.data(), 4 * L.vpos.size()));
     HIPCHK(up((void*)c->node_of, L.node_of.data(), 4 * L.node_of.size()));
+    HIPCHK(up((void*)c->mslot, L.mslot.data(), L.mslot.size()));
+    HIPCHK(up((void*)c->mrow, c->mrow_h.data(), sizeof(cgp::MomRow) * c->mrow_h.size()));
+    HIPCHK(up((void*)c->mtri, c->mtri_h.data(), sizeof(cgp::MomTri) * c->mtri_h.size()));
   }
   c->pinned = static_cast<Scal*>(host);
   std::memset(c->pinned, 0, kHostBytes);
@@ -1367,6 +1397,50 @@ int cgp_lattice_correct_rhs_host(const cgp_ctx* c, const double* phi_f, const do
   });
   if (!known) return fail(CGP_ERR_INVALID, "unsupported lattice size");
   if (cgp::corr_fault) return fail(CGP_ERR_INVALID, "correction stencil index out of range");
+  return CGP_OK;
+}
+
+int cgp_lattice_momentum_host(const cgp_ctx* c, const double* u_prev, const double* u,
+                              const double* p, const double* u_dir, const double* f,
+                              const double* t_nat, int32_t* rowptr, int32_t* col, double* aval,
+                              double* rhs, double* x0) {
+  if (!c || !u_prev || !u || !u_dir || !rowptr || !col || !aval || !rhs || !x0)
+    return fail(CGP_ERR_INVALID, "null argument");
+  const cgp::Lattice& L = c->lat;
+  if (!L.mom_ok) return fail(CGP_ERR_INVALID, "no lattice form of the momentum rows on this context");
+  const cgp::Graph& g = c->h.gf;
+  const int32_t n = c->nf;
+  const size_t nnz = g.col.size();
+  std::copy(g.rowptr.begin(), g.rowptr.end(), rowptr);
+  std::copy(g.col.begin(), g.col.end(), col);
+  const double nan = std::nan("");
+  std::fill_n(aval, nnz, nan);
+  std::fill_n(rhs, 2 * (size_t)n, nan);
+  std::fill_n(x0, 2 * (size_t)n, nan);
+  std::vector<double> invd(n, nan);
+  // the fields of the assembly pre-pass
+  const double dt = c->prob.dt;
+  std::vector<double2> W(n), R(n);
+  for (int32_t i = 0; i < n; ++i) {
+    const double ux = u[i], uy = u[n + i], px = u_prev[i], py = u_prev[n + i];
+    double rx = 2.0 * ux - 0.5 * px, ry = 2.0 * uy - 0.5 * py;
+    if (f) {
+      rx += dt * f[i];
+      ry += dt * f[n + i];
+    }
+    W[i] = make_double2(2.0 * ux - px, 2.0 * uy - py);
+    R[i] = make_double2(rx, ry);
+  }
+  const cgp::MomLatArgs A{n, L.nV, g.rowptr.data(), L.mslot.data(), c->mrow_h.data(),
+                          c->mtri_h.data(), c->h.dir_index.data(), W.data(), R.data(), p, u_dir,
+                          c->ndir, t_nat, dt, dt * c->prob.nu, aval, invd.data(), rhs, x0};
+  auto put = [&](int32_t s, double val) { aval[s] = val; };
+  for (int32_t i = L.nV; i < n; ++i) {
+    if (t_nat)
+      cgp::mom_row<true>(A, i, put);
+    else
+      cgp::mom_row<false>(A, i, put);
+  }
   return CGP_OK;
 }
 

@@ -56,12 +56,23 @@ void launch_vertex_rows(int64_t n, const int32_t* vpos, const double* Mval, doub
 void launch_coarse_assemble(const DLevel& L, const uint8_t* nat, double* Kval, float* Kval32,
                             double* Dxval, double* Dyval, double* invd, float* invd32,
                             double* lumped, hipStream_t s);
+// Lattice form of the momentum rows (momlat.hpp): rows from row0 on (the
+// rows of the coarse vertices come first in mesh numbering).
+struct MomRow;
+struct MomTri;
+struct MomLattice {
+  const uint8_t* slot;      // [N][8]
+  const MomRow* rows;       // [N]
+  const MomTri* tris;       // [nT]
+  int32_t row0;
+};
+// ml == nullptr: every row side-based
 void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double dt, double nu,
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
                               const double* t_nat, double* Aval, double* invdA, double* rhs,
                               double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
-                              hipEvent_t* ev = nullptr);
+                              hipEvent_t* ev = nullptr, const MomLattice* ml = nullptr);
 
 // ---------------------------------------------------------------- BiCGSTAB (2 rhs)
 struct BicgVecs {

@@ -24,6 +24,7 @@
 
 #include "cgp.h"
 #include "device.hpp"
+#include "momlat.hpp"
 #include "mesh.hpp"
 #include "mpnn.hpp"
 
@@ -313,19 +314,20 @@ __global__ void k_momentum_fields(int32_t n32, const double* __restrict__ up,
 // row every boundary slot (i, j) (an edge with one side missing) is a
 // natural edge, since a node on a Dirichlet edge is a Dirichlet row; on an
 // edge of length l the P1 boundary mass gives l (2 t_i + t_j) / 6.
+// Rows [0, row_end).
 template <bool kTrac>
 __global__ void __launch_bounds__(kBlock)
-k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
-                    const double2* __restrict__ W, const double2* __restrict__ R,
+k_momentum_assemble(DLevel L, int32_t row_end, const int32_t* __restrict__ dir_index, double dt,
+                    double dtnu, const double2* __restrict__ W, const double2* __restrict__ R,
                     const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
                     const double* __restrict__ tn, double* __restrict__ A,
                     double* __restrict__ invdA, double* __restrict__ rhs,
                     double* __restrict__ x0) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
-  for (int base = blockIdx.x * rpb; base < n; base += gridDim.x * rpb) {
+  for (int base = blockIdx.x * rpb; base < row_end; base += gridDim.x * rpb) {
     const int i = base + threadIdx.x / kRowLanes;
-    if (i >= n) continue;  // uniform within the lane group
+    if (i >= row_end) continue;  // uniform within the lane group
     const int beg = L.rowptr[i], end = L.rowptr[i + 1];
     const int di = dir_index[i];
     if (di >= 0) {  // Dirichlet row: identity, right-hand side = boundary value
@@ -435,6 +437,24 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
       x0[n + i] = wiy;
     }
   }
+}
+
+// The rows of the lattice's interior and coarse-edge nodes, [A.row0, A.n),
+// one thread per row (momlat.hpp).
+// A block's rows hold at most 7 entries each (checked at set-up), so its
+// contiguous range of matrix values is staged in LDS and written out with
+// consecutive lanes on consecutive values.
+template <bool kTrac>
+__global__ void __launch_bounds__(kBlock) k_momentum_lat(MomLatArgs A) {
+  constexpr int kMaxVals = kBlock * 7;
+  __shared__ double sa[kMaxVals];
+  const int32_t r0 = A.row0 + blockIdx.x * kBlock;
+  const int32_t r1 = r0 + kBlock < A.n ? r0 + kBlock : A.n;
+  const int32_t base = A.rowptr[r0], top = A.rowptr[r1];
+  const int32_t i = r0 + threadIdx.x;
+  if (i < r1) mom_row<kTrac>(A, i, [&](int32_t s, double v) { sa[s - base] = v; });
+  __syncthreads();
+  for (int32_t q = threadIdx.x; q < top - base; q += kBlock) A.A[base + q] = sa[q];
 }
 
 // ------------------------------------------------------------------ BiCGSTAB
@@ -1430,17 +1450,32 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const double* u_dir, int32_t n_dir, const double* f,
                               const double* t_nat, double* Aval, double* invdA, double* rhs,
                               double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
-                              hipEvent_t* ev) {
+                              hipEvent_t* ev, const MomLattice* ml) {
   double2* W = reinterpret_cast<double2*>(scratch_w);
   double2* R = reinterpret_cast<double2*>(scratch_r);
+  // rows [0, row_end) side-based; the rest on the lattice
+  const int32_t row_end = ml ? ml->row0 : L.n;
   if (ev) (void)hipEventRecord(ev[0], s);
   k_momentum_fields<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L.n, u_prev, u, f, dt, W, R);
-  if (t_nat)
-    k_momentum_assemble<true><<<row_group_grid(L.n), kBlock, 0, s>>>(
-        L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
-  else
-    k_momentum_assemble<false><<<row_group_grid(L.n), kBlock, 0, s>>>(
-        L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs, x0);
+  if (row_end > 0) {
+    if (t_nat)
+      k_momentum_assemble<true><<<row_group_grid(row_end), kBlock, 0, s>>>(
+          L, row_end, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
+    else
+      k_momentum_assemble<false><<<row_group_grid(row_end), kBlock, 0, s>>>(
+          L, row_end, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs,
+          x0);
+  }
+  if (ml && row_end < L.n) {
+    const MomLatArgs A{L.n, row_end, L.rowptr, ml->slot, ml->rows, ml->tris, dir_index, W, R,
+                       p,   u_dir,   n_dir,    t_nat,    dt,       dt * nu,  Aval,      invdA,
+                       rhs, x0};
+    const int g = (int)((L.n - row_end + kBlock - 1) / kBlock);
+    if (t_nat)
+      k_momentum_lat<true><<<g, kBlock, 0, s>>>(A);
+    else
+      k_momentum_lat<false><<<g, kBlock, 0, s>>>(A);
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 

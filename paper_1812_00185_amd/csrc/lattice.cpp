@@ -5,6 +5,7 @@
 #include <unordered_map>
 
 #include "mesh.hpp"
+#include "momlat.hpp"
 
 namespace cgp {
 
@@ -123,6 +124,53 @@ std::string build_lattice(const Hierarchy& h, Lattice& L) {
     if (!diag) return "lattice: vertex row without its diagonal";
   }
   return "";
+}
+
+void build_mom_slots(const Hierarchy& h, Lattice& L) {
+  const Graph& g = h.gf;
+  const int32_t N = (int32_t)L.lat_of.size();
+  L.mslot.assign(8 * (size_t)N, kNoSlot);
+  L.mom_ok = false;
+  const LatDev v = L.host_view();
+  bool ok = true;
+  const bool known = lat_dispatch(v.m, [&](auto lat) {
+    constexpr int M = decltype(lat)::kM;
+    for (int32_t i = L.nV; i < N && ok; ++i) {
+      const int32_t l = L.lat_of[i];
+      if (l >= L.VB) {
+        ok = false;
+        break;
+      }
+      int32_t pt[6];
+      mom_dirs<M>(v, l, pt);
+      const int32_t beg = g.rowptr[i], end = g.rowptr[i + 1];
+      if (end - beg > 7 || g.col[beg] != i) {  // the kernel stages 7 values per row
+        ok = false;
+        break;
+      }
+      std::vector<uint8_t> hit(end - beg, 0);
+      int present = 0;
+      for (int d = 0; d < 6; ++d) {
+        if (pt[d] < 0) continue;
+        if (pt[d] >= N) {
+          ok = false;
+          break;
+        }
+        ++present;
+        const int32_t j = L.node_of[pt[d]];
+        int32_t s = beg + 1;
+        while (s < end && g.col[s] != j) ++s;
+        if (s == end || hit[s - beg]) {
+          ok = false;
+          break;
+        }
+        hit[s - beg] = 1;
+        L.mslot[8 * (size_t)i + d] = (uint8_t)(s - beg);
+      }
+      if (ok && present != end - beg - 1) ok = false;
+    }
+  });
+  L.mom_ok = known && ok;
 }
 
 }  // namespace cgp

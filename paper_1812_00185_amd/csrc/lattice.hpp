@@ -348,6 +348,12 @@ struct Lattice {
   int32_t vw = 0;
   std::vector<int32_t> vcol, vpos;
   std::vector<int32_t> node_of;  // [N] lattice node -> mesh node (inverse of lat_of)
+  // momentum rows on the lattice (momlat.hpp): per mesh row, the CSR offset
+  // of each of its six direction neighbours ([N][8], 0xff: none; rows of the
+  // coarse vertices unused), and whether every row of an interior or edge
+  // node matched its CSR row exactly
+  std::vector<uint8_t> mslot;
+  bool mom_ok = false;
   // view with host pointers (vval left empty)
   LatDev host_view() const;
 };
@@ -356,5 +362,8 @@ struct Lattice {
 // maps every fine node to its lattice node and checks that the map is a
 // permutation; builds the coarse-vertex rows.  Returns "" on success.
 std::string build_lattice(const Hierarchy& h, Lattice& L);
+
+// Fills L.mslot and L.mom_ok from the fine CSR graph of h.
+void build_mom_slots(const Hierarchy& h, Lattice& L);
 
 }  // namespace cgp

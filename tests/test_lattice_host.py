@@ -216,3 +216,81 @@ def test_lattice_correction_rhs_matches_assembled(N, name, meshf, k, chi):
             assert np.all(rhs[g.dirichlet_nodes, :2] == 0.0)
     finally:
         g.close()
+
+
+# ------------------------------------------------------------ momentum rows
+
+MOM_CASES = [
+    ("square_k1", lambda: unit_square(9), 1, False),
+    ("square_k3", lambda: unit_square(9), 3, False),
+    ("square_k3_traction", lambda: unit_square(9, tags={"left": NATURAL}), 3, True),
+    ("disc_k2", lambda: disc(30, 120, seed=2), 2, False),
+    ("disc_k3", lambda: disc(30, 80, seed=1), 3, False),
+    ("channel_k2_traction", lambda: channel_cylinder(0.08), 2, True),
+]
+
+
+@pytest.mark.parametrize("name,meshf,k,trac", MOM_CASES, ids=[c[0] for c in MOM_CASES])
+def test_lattice_momentum_rows_match_assembled(N, name, meshf, k, trac):
+    """The momentum rows of Eq. 21 as the library assembles them on the
+    lattice layout (fine-triangle coefficients from the coarse triangles, no
+    coordinate, side or column index read) against the oracle's assembled
+    matrix, right-hand side and initial guess, on every row of a fine node
+    other than the coarse vertices (those keep the side-based assembly):
+    random fields, pressure, forcing, Dirichlet values and, on natural
+    boundaries, traction."""
+    from oracle.cgp import OracleCGP
+    from paper_1812_00185_amd.solver import CGP
+
+    mesh = meshf()
+    dt, nu = 1e-3, 1e-2
+    g = CGP(mesh, k, dt, nu, chi=1, device="cpu")
+    o = OracleCGP(mesh, k, dt, nu, 1)
+    try:
+        n = g.nf
+        assert np.array_equal(o.dir, g.dirichlet_nodes)
+        rng = np.random.default_rng(k + len(name))
+        Up, U, F = (rng.standard_normal((2, n)) for _ in range(3))
+        P = rng.standard_normal(n)
+        uD = rng.standard_normal((2, o.dir.size))
+        T = rng.standard_normal((2, n)) if trac else None
+        A, rhs_o, w = o.momentum_system(Up, U, P, uD, F, T)
+        A = A.tocsr()
+        x0_o = w.copy()
+        x0_o[:, o.dir] = uD
+        nnz = int(g.sizes.nnz_fine)
+        rowptr = np.empty(n + 1, np.int32)
+        col = np.empty(nnz, np.int32)
+        aval = np.empty(nnz)
+        rhs = np.empty((2, n))
+        x0 = np.empty((2, n))
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        arr = lambda a: None if a is None else np.ascontiguousarray(a).ctypes.data_as(dp)
+        rc = g.lib.cgp_lattice_momentum_host(
+            g.ctx, arr(Up), arr(U), arr(P), arr(uD), arr(F), arr(T), rowptr.ctypes.data_as(ip),
+            col.ctypes.data_as(ip), aval.ctypes.data_as(dp), rhs.ctypes.data_as(dp),
+            x0.ctypes.data_as(dp))
+        assert rc == 0, g.lib.cgp_last_error()
+        rows = np.arange(g.nc, n)
+        assert rows.size > 0
+        lo, hi = rowptr[g.nc], rowptr[n]
+        ri = np.repeat(np.arange(n), np.diff(rowptr))[lo:hi]
+        ref = np.asarray(A[ri, col[lo:hi]]).ravel()
+        assert np.array_equal(x0[:, rows], x0_o[:, rows])
+        # Dirichlet rows (identity, boundary values) exactly; free rows to
+        # rounding, scaled by the free rows' own magnitudes
+        dirrow = np.zeros(n, bool)
+        dirrow[o.dir] = True
+        fr = ~dirrow[ri]
+        assert np.array_equal(aval[lo:hi][~fr], ref[~fr])
+        rf = rows[~dirrow[rows]]
+        assert np.array_equal(rhs[:, rows[dirrow[rows]]], rhs_o[:, rows[dirrow[rows]]])
+        ea = np.abs(aval[lo:hi][fr] - ref[fr]).max() / np.abs(ref[fr]).max()
+        er = np.abs(rhs[:, rf] - rhs_o[:, rf]).max() / np.abs(rhs_o[:, rf]).max()
+        print(f"[mom rows] {name}: N_f={n}, free rows {rf.size}: A {ea:.1e} rhs {er:.1e}")
+        assert ea < 1e-13 and er < 1e-13
+        # the coarse-vertex rows are left to the side-based kernel
+        assert np.all(np.isnan(aval[:lo])) and np.all(np.isnan(rhs[:, :g.nc]))
+    finally:
+        g.close()
