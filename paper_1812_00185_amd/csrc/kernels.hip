@@ -314,18 +314,18 @@ __global__ void k_momentum_fields(int32_t n32, const double* __restrict__ up,
 // row every boundary slot (i, j) (an edge with one side missing) is a
 // natural edge, since a node on a Dirichlet edge is a Dirichlet row; on an
 // edge of length l the P1 boundary mass gives l (2 t_i + t_j) / 6.
-// Rows [0, row_end).
+// Rows [0, row_end), by blocks blk, blk + nblk, ... of kBlock / kRowLanes
+// rows each.
 template <bool kTrac>
-__global__ void __launch_bounds__(kBlock)
-k_momentum_assemble(DLevel L, int32_t row_end, const int32_t* __restrict__ dir_index, double dt,
-                    double dtnu, const double2* __restrict__ W, const double2* __restrict__ R,
-                    const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
-                    const double* __restrict__ tn, double* __restrict__ A,
-                    double* __restrict__ invdA, double* __restrict__ rhs,
-                    double* __restrict__ x0) {
+__device__ __forceinline__ void mom_side_rows(
+    const DLevel& L, int32_t row_end, const int32_t* __restrict__ dir_index, double dt,
+    double dtnu, const double2* __restrict__ W, const double2* __restrict__ R,
+    const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
+    const double* __restrict__ tn, double* __restrict__ A, double* __restrict__ invdA,
+    double* __restrict__ rhs, double* __restrict__ x0, int blk, int nblk) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
-  for (int base = blockIdx.x * rpb; base < row_end; base += gridDim.x * rpb) {
+  for (int base = blk * rpb; base < row_end; base += nblk * rpb) {
     const int i = base + threadIdx.x / kRowLanes;
     if (i >= row_end) continue;  // uniform within the lane group
     const int beg = L.rowptr[i], end = L.rowptr[i + 1];
@@ -439,16 +439,36 @@ k_momentum_assemble(DLevel L, int32_t row_end, const int32_t* __restrict__ dir_i
   }
 }
 
+template <bool kTrac>
+__global__ void __launch_bounds__(kBlock)
+k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, double dtnu,
+                    const double2* __restrict__ W, const double2* __restrict__ R,
+                    const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
+                    const double* __restrict__ tn, double* __restrict__ A,
+                    double* __restrict__ invdA, double* __restrict__ rhs,
+                    double* __restrict__ x0) {
+  mom_side_rows<kTrac>(L, L.n, dir_index, dt, dtnu, W, R, p, udir, ndir, tn, A, invdA, rhs, x0,
+                       blockIdx.x, gridDim.x);
+}
+
 // The rows of the lattice's interior and coarse-edge nodes, [A.row0, A.n),
 // one thread per row (momlat.hpp).
 // A block's rows hold at most 7 entries each (checked at set-up), so its
 // contiguous range of matrix values is staged in LDS and written out with
 // consecutive lanes on consecutive values.
+// Blocks [0, nbv) take the rows of the coarse vertices [0, A.row0) side-based
+// (one group of kBlock / kRowLanes rows each), the others the lattice rows,
+// so that the two kinds of work overlap.
 template <bool kTrac>
-__global__ void __launch_bounds__(kBlock) k_momentum_lat(MomLatArgs A) {
+__global__ void __launch_bounds__(kBlock) k_momentum_lat(DLevel L, MomLatArgs A, int nbv) {
+  if ((int)blockIdx.x < nbv) {
+    mom_side_rows<kTrac>(L, A.row0, A.dir_index, A.dt, A.dtnu, A.W, A.R, A.p, A.udir, A.ndir,
+                         A.tn, A.A, A.invdA, A.rhs, A.x0, blockIdx.x, nbv);
+    return;
+  }
   constexpr int kMaxVals = kBlock * 7;
   __shared__ double sa[kMaxVals];
-  const int32_t r0 = A.row0 + blockIdx.x * kBlock;
+  const int32_t r0 = A.row0 + (blockIdx.x - nbv) * kBlock;
   const int32_t r1 = r0 + kBlock < A.n ? r0 + kBlock : A.n;
   const int32_t base = A.rowptr[r0], top = A.rowptr[r1];
   const int32_t i = r0 + threadIdx.x;
@@ -1453,28 +1473,28 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               hipEvent_t* ev, const MomLattice* ml) {
   double2* W = reinterpret_cast<double2*>(scratch_w);
   double2* R = reinterpret_cast<double2*>(scratch_r);
-  // rows [0, row_end) side-based; the rest on the lattice
-  const int32_t row_end = ml ? ml->row0 : L.n;
   if (ev) (void)hipEventRecord(ev[0], s);
   k_momentum_fields<<<grid_for(L.n, kBlock), kBlock, 0, s>>>(L.n, u_prev, u, f, dt, W, R);
-  if (row_end > 0) {
+  if (!ml || ml->row0 >= L.n) {  // every row side-based
     if (t_nat)
-      k_momentum_assemble<true><<<row_group_grid(row_end), kBlock, 0, s>>>(
-          L, row_end, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
+      k_momentum_assemble<true><<<row_group_grid(L.n), kBlock, 0, s>>>(
+          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
     else
-      k_momentum_assemble<false><<<row_group_grid(row_end), kBlock, 0, s>>>(
-          L, row_end, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs,
-          x0);
-  }
-  if (ml && row_end < L.n) {
-    const MomLatArgs A{L.n, row_end, L.rowptr, ml->slot, ml->rows, ml->tris, dir_index, W, R,
-                       p,   u_dir,   n_dir,    t_nat,    dt,       dt * nu,  Aval,      invdA,
+      k_momentum_assemble<false><<<row_group_grid(L.n), kBlock, 0, s>>>(
+          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs, x0);
+  } else {
+    // the coarse-vertex rows [0, row0) side-based, the rest on the lattice,
+    // in one launch
+    const int32_t row0 = ml->row0;
+    const MomLatArgs A{L.n, row0, L.rowptr, ml->slot, ml->rows, ml->tris, dir_index, W, R,
+                       p,   u_dir, n_dir,   t_nat,    dt,       dt * nu,  Aval,      invdA,
                        rhs, x0};
-    const int g = (int)((L.n - row_end + kBlock - 1) / kBlock);
+    const int nbv = (row0 + kBlock / kRowLanes - 1) / (kBlock / kRowLanes);
+    const int g = nbv + (int)((L.n - row0 + kBlock - 1) / kBlock);
     if (t_nat)
-      k_momentum_lat<true><<<g, kBlock, 0, s>>>(A);
+      k_momentum_lat<true><<<g, kBlock, 0, s>>>(L, A, nbv);
     else
-      k_momentum_lat<false><<<g, kBlock, 0, s>>>(A);
+      k_momentum_lat<false><<<g, kBlock, 0, s>>>(L, A, nbv);
   }
   if (ev) (void)hipEventRecord(ev[1], s);
 }

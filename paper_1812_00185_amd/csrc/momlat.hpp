@@ -299,16 +299,15 @@ CGP_HDI void mom_row(const MomLatArgs& A, int32_t i, Put put) {
     return;
   }
   const MomRow rr = A.rows[i];
-  double2 wd[6], rd[6];
+  double2 wd[6];
   double pd[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int32_t j = rr.nb[d] >= 0 ? rr.nb[d] : i;  // absent: any valid node, unused
     wd[d] = A.W[j];
-    rd[d] = A.R[j];
     pd[d] = A.p ? A.p[j] : 0.0;
   }
-  const double2 wi = A.W[i], ri = A.R[i];
+  const double2 wi = A.W[i];
   const double pi = A.p ? A.p[i] : 0.0;
   MomAcc s;
 #pragma unroll
@@ -351,9 +350,11 @@ CGP_HDI void mom_row(const MomLatArgs& A, int32_t i, Put put) {
     sm += s.m[d];
     sk += s.k[d];
     sn += s.nx[d];
-    rx += s.m[d] * rd[d].x;
-    ry += s.m[d] * rd[d].y;
+    const double2 rj = A.R[rr.nb[d]];  // R only here: fewer live registers
+    rx += s.m[d] * rj.x;
+    ry += s.m[d] * rj.y;
   }
+  const double2 ri = A.R[i];
   const double aii = 1.5 * sm - A.dtnu * sk - A.dt * sn;
   put(beg, aii);
   A.invdA[i] = 1.0 / aii;
