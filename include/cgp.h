@@ -461,23 +461,24 @@ int cgp_lattice_momentum_host(const cgp_ctx* ctx, const double* u_prev, const do
 int cgp_lattice_correct_rhs_host(const cgp_ctx* ctx, const double* phi_f, const double* phi_c,
                                  const double* u_tilde, double* rhs);
 
-/* Host-only check of the paired Chebyshev steps of the mass solves on a
- * context with lattice size 8 (k = 3): runs, on the host and with every
- * index checked, the launch sequence of one pair of steps -- a step on the
- * coarse-edge and vertex nodes, the two-step kernel on the interior nodes of
- * the coarse triangles, a step on the edge and vertex nodes -- and returns
- * x_{k+1} in x1 and x_{k+2} in x2, where
- *   x_{j+1} = x_j + ca (x_j - x_{j-1}) + cb D^-1 (b - M x_j),
- * coef = (ca, cb) of the first step, then of the second; velocity components
- * (0, 1) are 0 at Dirichlet nodes.  b, xm (x_{k-1}), xk, x1, x2: host
- * [N_f][nr], fine numbering, nr 2 or 3; rowptr, col, mval as for
- * cgp_lattice_mass_apply_host.  A value the sequence leaves unwritten comes
- * back as NaN.  Errors: CGP_ERR_INVALID (arguments, another lattice size, an
- * index out of range). */
-int cgp_lattice_cheb_pair_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
-                               const double* mval, int32_t nr, const double* b,
-                               const double* xm, const double* xk, const double* coef,
-                               double* x1, double* x2);
+/* Host-only check of the device mass solves (Eqs. 25-26): a whole solve of
+ * `iters` Chebyshev steps from x_0 = 0,
+ *   x_{j+1} = x_j + ca_j (x_j - x_{j-1}) + cb_j D^-1 (b - M x_j),
+ * (ca_j, cb_j) of the three-term recurrence on [1/2, 2], run launch by launch
+ * as the library runs it on lattice size 8: with pairs != 0 the step pairs
+ * (a step on the coarse-edge and vertex nodes, the two-step kernel on the
+ * interior nodes of the coarse triangles block by block, each phase for
+ * every thread before the next, a step on the edge and vertex nodes), with
+ * pairs == 0 every step on every node; every index checked.  Velocity
+ * components (0, 1) are 0 at Dirichlet nodes.  b, x: host [N_f][nr], fine
+ * numbering, nr 2 or 3; rowptr, col, mval as for
+ * cgp_lattice_mass_apply_host.  The iterates start as NaN, so a value read
+ * before the sequence wrote it comes back as NaN.  Errors: CGP_ERR_INVALID
+ * (arguments, iters outside 1..1000, another lattice size, an index out of
+ * range). */
+int cgp_lattice_cheb_solve_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
+                                const double* mval, int32_t nr, const double* b, int32_t iters,
+                                int32_t pairs, double* x);
 
 /* Host-only: orders, factors and applies the nested-dissection factor of a
  * symmetric positive definite CSR matrix restricted to the rows/columns with

@@ -1258,35 +1258,81 @@ bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, c
   return ok;
 }
 
-// The launch sequence of a pair of steps on the host: single step over
+// A whole mass solve of `iters` Chebyshev steps on the host, launch by
+// launch as launch_cheb runs it: a first step on every node (x_0 = 0), then
+// with pairs (lattice size 8) the step pairs -- a single step over
 // [EB & ~1, n), the interior kernel block by block (each phase for every
-// thread before the next), single step again.  Lattice-ordered vectors.
+// thread before the next), a single step again -- and single steps on every
+// node for the rest; without pairs single steps throughout.  Lattice-ordered
+// vectors; the three iterate buffers start as NaN, so a value read before
+// any launch wrote it shows up in the result.
 template <int NR>
-bool cheb_pair_host(const cgp::LatDev& v, int32_t n, const double* b, const double* xm,
-                    const double* xk, const double* cf, double* x1, double* x2) {
+bool cheb_solve_host(const cgp::LatDev& v, int32_t n, const double* b, int iters, bool pairs,
+                     double* out) {
   using namespace cgp;
-  const int32_t lb = v.EB & ~1;
-  bool ok = cheb_single_host<NR>(v, n, lb, n, b, xm, xk, cf[0], cf[1], x1);
+  const size_t len = (size_t)n * NR;
+  std::vector<double> xs[3];
+  for (auto& x : xs) x.assign(len, std::nan(""));
+  double* x[3] = {xs[0].data(), xs[1].data(), xs[2].data()};
+  // (ca_k, cb_k) of the three-term recurrence on [1/2, 2]
+  std::vector<double> ca(iters), cb(iters);
+  {
+    const double theta = 1.25, delta = 0.75, sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < iters; ++k) {
+      ca[k] = 0.0;
+      cb[k] = 1.0 / theta;
+      if (k > 0) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        ca[k] = rn * rho;
+        cb[k] = 2.0 * rn / delta;
+        rho = rn;
+      }
+    }
+  }
+  for (int32_t l = 0; l < n; ++l) {
+    const double di = 1.0 / lat_diag(v, l);
+    const bool masked = v.ldir[l] != 0;
+    for (int d = 0; d < NR; ++d) {
+      x[1][(int64_t)l * NR + d] = (d < 2 && masked) ? 0.0 : cb[0] * di * b[(int64_t)l * NR + d];
+      x[0][(int64_t)l * NR + d] = 0.0;
+    }
+  }
+  bool ok = true;
   ch2_fault = false;
-  const Cheb2Args A{n, b, xm, xk, x1, x2, cf[0], cf[1], cf[2], cf[3]};
   auto cp2 = [](const double* src, double* dst) {
     dst[0] = src[0];
     dst[1] = src[1];
   };
-  auto S = std::make_unique<Cheb2Shared<NR>>();
   static constexpr Ch2NbTable nbt = ch2_make_nb_table();
+  auto S = std::make_unique<Cheb2Shared<NR>>();
+  const int32_t lb = v.EB & ~1;
   const int nblk = (v.nT + kCh2Tris - 1) / kCh2Tris;
-  for (int blk = 0; blk < nblk; ++blk) {
-    // a slot read before it is written shows up as NaN in the results
-    std::fill_n(reinterpret_cast<double*>(S.get()), sizeof(Cheb2Shared<NR>) / sizeof(double),
-                std::nan(""));
-    for (int t = 0; t < kCh2Threads; ++t) ch2_stage<NR>(v, A, blk, t, *S, cp2, cp2);
-    for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, nbt.w, *S);
-    for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, nbt.w, *S);
-    for (int t = 0; t < kCh2Threads; ++t) ch2_write<NR>(v, A, blk, t, *S, cp2);
+  for (int k = 1; k < iters;) {
+    if (!pairs || k + 1 >= iters) {
+      ok = ok && cheb_single_host<NR>(v, n, 0, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
+                                      x[(k + 1) % 3]);
+      k += 1;
+      continue;
+    }
+    ok = ok && cheb_single_host<NR>(v, n, lb, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
+                                    x[(k + 1) % 3]);
+    const Cheb2Args A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
+                      ca[k], cb[k], ca[k + 1], cb[k + 1]};
+    for (int blk = 0; blk < nblk; ++blk) {
+      std::fill_n(reinterpret_cast<double*>(S.get()), sizeof(Cheb2Shared<NR>) / sizeof(double),
+                  std::nan(""));
+      for (int t = 0; t < kCh2Threads; ++t) ch2_stage<NR>(v, A, blk, t, *S, cp2, cp2);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, nbt.w, *S);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, nbt.w, *S);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_write<NR>(v, A, blk, t, *S, cp2);
+    }
+    ok = ok && cheb_single_host<NR>(v, n, lb, n, b, x[k % 3], x[(k + 1) % 3], ca[k + 1],
+                                    cb[k + 1], x[(k + 2) % 3]);
+    k += 2;
   }
   ok = ok && !ch2_fault;
-  ok = ok && cheb_single_host<NR>(v, n, lb, n, b, xk, x1, cf[2], cf[3], x2);
+  std::copy(x[iters % 3], x[iters % 3] + len, out);
   return ok;
 }
 
@@ -1335,15 +1381,15 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const i
   return CGP_OK;
 }
 
-int cgp_lattice_cheb_pair_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
-                               const double* mval, int32_t nr, const double* b,
-                               const double* xm, const double* xk, const double* coef,
-                               double* x1, double* x2) {
-  if (!c || !rowptr || !col || !mval || !b || !xm || !xk || !coef || !x1 || !x2)
-    return fail(CGP_ERR_INVALID, "null argument");
+int cgp_lattice_cheb_solve_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
+                                const double* mval, int32_t nr, const double* b, int32_t iters,
+                                int32_t pairs, double* x) {
+  if (!c || !rowptr || !col || !mval || !b || !x) return fail(CGP_ERR_INVALID, "null argument");
   if (nr != 2 && nr != 3) return fail(CGP_ERR_INVALID, "nr must be 2 or 3");
+  if (iters < 1 || iters > 1000) return fail(CGP_ERR_INVALID, "iters must be 1..1000");
   const cgp::Lattice& L = c->lat;
-  if (L.m != cgp::kCh2M) return fail(CGP_ERR_INVALID, "the two-step kernel needs lattice size 8");
+  if (pairs && L.m != cgp::kCh2M) return fail(CGP_ERR_INVALID, "step pairs need lattice size 8");
+  if (!pairs && L.m != cgp::kCh2M) return fail(CGP_ERR_INVALID, "the host solve needs lattice size 8");
   cgp::LatDev v = L.host_view();
   const int32_t n = c->nf;
   std::vector<double> vval;
@@ -1351,23 +1397,14 @@ int cgp_lattice_cheb_pair_host(const cgp_ctx* c, const int32_t* rowptr, const in
     return fail(CGP_ERR_INVALID, "vertex rows: column out of range or entries differ");
   v.vval = vval.data();
   const size_t len = (size_t)n * nr;
-  std::vector<double> bl(len), ml(len), kl(len), o1(len, std::nan("")), o2(len, std::nan(""));
+  std::vector<double> bl(len), xl(len);
   for (int32_t i = 0; i < n; ++i)
-    for (int d = 0; d < nr; ++d) {
-      const size_t f = (size_t)i * nr + d, t = (size_t)L.lat_of[i] * nr + d;
-      bl[t] = b[f];
-      ml[t] = xm[f];
-      kl[t] = xk[f];
-    }
-  const bool ok = nr == 3 ? cheb_pair_host<3>(v, n, bl.data(), ml.data(), kl.data(), coef, o1.data(), o2.data())
-                          : cheb_pair_host<2>(v, n, bl.data(), ml.data(), kl.data(), coef, o1.data(), o2.data());
-  if (!ok) return fail(CGP_ERR_INVALID, "two-step kernel: index out of range");
+    for (int d = 0; d < nr; ++d) bl[(size_t)L.lat_of[i] * nr + d] = b[(size_t)i * nr + d];
+  const bool ok = nr == 3 ? cheb_solve_host<3>(v, n, bl.data(), iters, pairs != 0, xl.data())
+                          : cheb_solve_host<2>(v, n, bl.data(), iters, pairs != 0, xl.data());
+  if (!ok) return fail(CGP_ERR_INVALID, "mass solve: index out of range");
   for (int32_t i = 0; i < n; ++i)
-    for (int d = 0; d < nr; ++d) {
-      const size_t f = (size_t)i * nr + d, t = (size_t)L.lat_of[i] * nr + d;
-      x1[f] = o1[t];
-      x2[f] = o2[t];
-    }
+    for (int d = 0; d < nr; ++d) x[(size_t)i * nr + d] = xl[(size_t)L.lat_of[i] * nr + d];
   return CGP_OK;
 }
 

@@ -67,40 +67,45 @@ def test_lattice_mass_apply_matches_assembled(N, name, meshf, k):
 
 # ------------------------------------------------------- paired Chebyshev steps
 
-def _cheb_coefs(k):
-    """(ca, cb) of Chebyshev steps k and k + 1 on the interval [1/2, 2] (the
-    three-term recurrence of the mass solves of Eqs. 25-26)."""
+def _cheb_coefs(iters):
+    """(ca_j, cb_j), j < iters, of the three-term Chebyshev recurrence on the
+    interval [1/2, 2] (the mass solves of Eqs. 25-26)."""
     theta, delta = 1.25, 0.75
     sigma = theta / delta
     rho = 1.0 / sigma
     out = []
-    for j in range(k + 2):
+    for j in range(iters):
         ca, cb = 0.0, 1.0 / theta
         if j > 0:
             rn = 1.0 / (2.0 * sigma - rho)
             ca, cb, rho = rn * rho, 2.0 * rn / delta, rn
         out.append((ca, cb))
-    return out[k] + out[k + 1]
+    return out
 
 
 PAIR_CASES = [
     # (name, coarse mesh, nr); triangle counts not multiples of the 12 per
-    # block, odd and even first edge nodes, natural boundaries, unstructured
+    # block, odd (143 triangles) and even first edge nodes, natural
+    # boundaries, unstructured
     ("square9_nr3", lambda: unit_square(9), 3),
     ("square6_nr2", lambda: unit_square(6, tags={"left": NATURAL}), 2),
     ("disc_nr3", lambda: disc(30, 80, seed=1), 3),
-    ("disc_nr2", lambda: disc(25, 60, seed=4), 2),
+    ("disc_odd_nr2", lambda: disc(25, 60, seed=4), 2),
+    ("disc_odd_nr3", lambda: disc(25, 60, seed=4), 3),
 ]
 
 
 @pytest.mark.parametrize("name,meshf,nr", PAIR_CASES, ids=[c[0] for c in PAIR_CASES])
-def test_cheb_pair_matches_two_single_steps(N, name, meshf, nr):
-    """The launch sequence of a pair of Chebyshev steps (edge and vertex
-    nodes, the two-step interior kernel, edge and vertex nodes), emulated on
-    the host with every index checked, equals two steps
-    x_{j+1} = x_j + ca (x_j - x_{j-1}) + cb D^-1 (b - M x_j) with the oracle's
-    assembled mass matrix (velocity components held at 0 on Dirichlet
-    nodes)."""
+def test_cheb_pairs_match_step_by_step(N, name, meshf, nr):
+    """A whole mass solve as the library launches it on lattice size 8 --
+    step pairs of a step on the coarse-edge and vertex nodes, the two-step
+    kernel on the interior nodes, a step on the edge and vertex nodes --
+    emulated on the host with every index checked and the iterates starting
+    as NaN, equals the step-by-step sequence bit for bit, and both equal the
+    Chebyshev recurrence
+    x_{j+1} = x_j + ca (x_j - x_{j-1}) + cb D^-1 (b - M x_j) with the
+    oracle's assembled mass matrix (velocity components held at 0 on
+    Dirichlet nodes), for odd and even step counts."""
     from paper_1812_00185_amd.solver import CGP
 
     mesh = meshf()
@@ -113,40 +118,43 @@ def test_cheb_pair_matches_two_single_steps(N, name, meshf, nr):
         val = np.ascontiguousarray(M.data, np.float64)
         rng = np.random.default_rng(len(name) + nr)
         n = g.nf
-        b, xm, xk = (rng.standard_normal((n, nr)) for _ in range(3))
-        cf = np.array(_cheb_coefs(5))
-        x1, x2 = np.empty((n, nr)), np.empty((n, nr))
-        dp = C.POINTER(C.c_double)
-        ip = C.POINTER(C.c_int32)
-        rc = g.lib.cgp_lattice_cheb_pair_host(
-            g.ctx, rp.ctypes.data_as(ip), col.ctypes.data_as(ip), val.ctypes.data_as(dp), nr,
-            b.ctypes.data_as(dp), xm.ctypes.data_as(dp), xk.ctypes.data_as(dp),
-            cf.ctypes.data_as(dp), x1.ctypes.data_as(dp), x2.ctypes.data_as(dp))
-        assert rc == 0, g.lib.cgp_last_error()
-        assert np.all(np.isfinite(x1)) and np.all(np.isfinite(x2))
+        b = rng.standard_normal((n, nr))
         di = 1.0 / M.diagonal()
         mask = np.zeros((n, nr), bool)
         mask[g.dirichlet_nodes, :2] = True
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
 
-        def step(x, xp, ca, cb):
-            out = x + ca * (x - xp) + (cb * di)[:, None] * (b - M @ x)
-            out[mask] = 0.0
-            return out
+        def lib_solve(iters, pairs):
+            x = np.empty((n, nr))
+            rc = g.lib.cgp_lattice_cheb_solve_host(
+                g.ctx, rp.ctypes.data_as(ip), col.ctypes.data_as(ip), val.ctypes.data_as(dp),
+                nr, b.ctypes.data_as(dp), iters, pairs, x.ctypes.data_as(dp))
+            assert rc == 0, g.lib.cgp_last_error()
+            return x
 
-        r1 = step(xk, xm, cf[0], cf[1])
-        r2 = step(r1, xk, cf[2], cf[3])
-        e1 = np.abs(x1 - r1).max() / np.abs(r1).max()
-        e2 = np.abs(x2 - r2).max() / np.abs(r2).max()
-        print(f"[cheb pair] {name}: N_f={n} coarse triangles {len(mesh['tri'])} "
-              f"step1 {e1:.1e} step2 {e2:.1e}")
-        # rounding: the stencil sums in another order than the CSR product
-        assert e1 < 1e-13 and e2 < 1e-13
-        assert np.all(x1[mask] == 0.0) and np.all(x2[mask] == 0.0)
+        for iters in (1, 2, 3, 4, 5, 6, 27):
+            cf = _cheb_coefs(iters)
+            xp, x = np.zeros((n, nr)), np.zeros((n, nr))
+            for ca, cb in cf:
+                xn = x + ca * (x - xp) + (cb * di)[:, None] * (b - M @ x)
+                xn[mask] = 0.0
+                xp, x = x, xn
+            got = lib_solve(iters, 1)
+            steps = lib_solve(iters, 0)
+            assert np.all(np.isfinite(got)), f"{iters} steps: a value read before it was written"
+            assert np.array_equal(got, steps), f"{iters} steps: pairs differ from single steps"
+            err = np.abs(got - x).max() / np.abs(x).max()
+            print(f"[cheb pairs] {name}: N_f={n} coarse triangles {len(mesh['tri'])} "
+                  f"{iters} steps {err:.1e}")
+            # rounding: the stencil sums in another order than the CSR product
+            assert err < 1e-13
+            assert np.all(got[mask] == 0.0)
     finally:
         g.close()
 
 
-def test_cheb_pair_host_rejects_other_lattice_sizes(N):
+def test_cheb_solve_host_rejects_other_lattice_sizes(N):
     from paper_1812_00185_amd.solver import CGP
 
     g = CGP(unit_square(9), 2, 1e-3, 1e-2, device="cpu")
@@ -155,9 +163,9 @@ def test_cheb_pair_host_rejects_other_lattice_sizes(N):
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         i = np.zeros(g.nc + 1, np.int32)
-        rc = g.lib.cgp_lattice_cheb_pair_host(
+        rc = g.lib.cgp_lattice_cheb_solve_host(
             g.ctx, i.ctypes.data_as(ip), i.ctypes.data_as(ip), z.ctypes.data_as(dp), 3,
-            *(z.ctypes.data_as(dp) for _ in range(6)))
+            z.ctypes.data_as(dp), 5, 1, z.ctypes.data_as(dp))
         assert rc != 0 and b"lattice size 8" in g.lib.cgp_last_error()
     finally:
         g.close()
