@@ -108,6 +108,7 @@ typedef struct cgp_mesh {
 #define CGP_MASS_CONSISTENT 0
 #define CGP_MASS_LUMPED_P 1
 #define CGP_MASS_LUMPED 2
+#define CGP_MASS_CONSISTENT_MIXED 3
 
 typedef struct cgp_problem {
   cgp_mesh coarse;
@@ -130,9 +131,14 @@ typedef struct cgp_problem {
   int32_t max_outer;     /* mixed: refinement-step cap                       */
   int32_t mass_mode;     /* CGP_MASS_CONSISTENT (Eqs. 25, 26), CGP_MASS_LUMPED_P
                             (rotational pressure update with the lumped mass
-                            matrix, Eq. 27) or CGP_MASS_LUMPED (Eq. 27 and the
+                            matrix, Eq. 27), CGP_MASS_LUMPED (Eq. 27 and the
                             velocity correction with the lumped mass matrix;
-                            no mass solves)                                  */
+                            no mass solves) or CGP_MASS_CONSISTENT_MIXED (the
+                            consistent solves as FP64 iterative refinement:
+                            two Chebyshev solves with float-stored iterates,
+                            each of the step count for sqrt(mass_tol) plus
+                            one, the second on the FP64 residual of the
+                            first; the solution is their FP64 sum)          */
   int32_t coarse_precond; /* CGP_PRECOND_JACOBI, CGP_PRECOND_JACOBI_S4 (the same
                             solver in s-step form; requires precision =
                             CGP_FP64; cgp_create fails with CGP_ERR_INVALID
@@ -298,7 +304,10 @@ int cgp_prolong(cgp_ctx* ctx, const double* phi_c, double* phi_f, void* stream);
  * p_out = p_in + phi_f + dp.  The mass solves run together as Chebyshev
  * iteration on [1/2, 2] (the spectrum of the Jacobi-scaled P1 mass matrix),
  * with the iteration count fixed by mass_tol (27 for 1e-12); stats report
- * that count and its a-priori error bound.  With CGP_SCHEME_NONINCREMENTAL
+ * that count and its a-priori error bound.  With CGP_MASS_CONSISTENT_MIXED
+ * stats report both solves' steps (iters, 2 x 15 for 1e-12), outer_iters 2,
+ * and as rel_res the square of the inner bound plus 8 float ulps (an
+ * estimate: the float storage is not bounded a priori).  With CGP_SCHEME_NONINCREMENTAL
  * p_out = phi_f (p_in not read, may be NULL).  p_out may alias p_in.
  * u_tilde, u_out device [2][N_f]; phi_f, p_in, p_out device [N_f].  stats:
  * [3] (u, v, rotational) or NULL. */
@@ -469,7 +478,10 @@ int cgp_lattice_correct_rhs_host(const cgp_ctx* ctx, const double* phi_f, const 
  * (a step on the coarse-edge and vertex nodes, the two-step kernel on the
  * interior nodes of the coarse triangles block by block, each phase for
  * every thread before the next, a step on the edge and vertex nodes), with
- * pairs == 0 every step on every node; every index checked.  Velocity
+ * pairs == 0 every step on every node; every index checked.  With
+ * mixed != 0 the solve of CGP_MASS_CONSISTENT_MIXED: the sequence above with
+ * float-stored iterates on b's float copy (d1), the FP64 residual
+ * r = b - M d1 stored as float, the same on r (d2), x = d1 + d2.  Velocity
  * components (0, 1) are 0 at Dirichlet nodes.  b, x: host [N_f][nr], fine
  * numbering, nr 2 or 3; rowptr, col, mval as for
  * cgp_lattice_mass_apply_host.  The iterates start as NaN, so a value read
@@ -478,7 +490,7 @@ int cgp_lattice_correct_rhs_host(const cgp_ctx* ctx, const double* phi_f, const 
  * range). */
 int cgp_lattice_cheb_solve_host(const cgp_ctx* ctx, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, int32_t nr, const double* b, int32_t iters,
-                                int32_t pairs, double* x);
+                                int32_t pairs, int32_t mixed, double* x);
 
 /* Host-only: orders, factors and applies the nested-dissection factor of a
  * symmetric positive definite CSR matrix restricted to the rows/columns with

@@ -27,7 +27,7 @@ CGP_K_MASS_PAIR = 5
 CGP_NET_PARAMS = 12993
 CGP_RESTRICT_GALERKIN = 0
 CGP_RESTRICT_INJECT = 1
-CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED = 0, 1, 2
+CGP_MASS_CONSISTENT, CGP_MASS_LUMPED_P, CGP_MASS_LUMPED, CGP_MASS_CONSISTENT_MIXED = 0, 1, 2, 3
 CGP_PRECOND_JACOBI, CGP_PRECOND_NDCHOL, CGP_PRECOND_JACOBI_S4 = 0, 1, 2
 CGP_SCHEME_INCREMENTAL, CGP_SCHEME_NONINCREMENTAL = 0, 1
 
@@ -136,7 +136,7 @@ SIGNATURES = [
     ("cgp_lattice_momentum_host", C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ip,
                                             _dp, _dp, _dp]),
     ("cgp_lattice_cheb_solve_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, C.c_int32, _dp,
-                                              C.c_int32, C.c_int32, _dp]),
+                                              C.c_int32, C.c_int32, C.c_int32, _dp]),
     ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,
                                         C.POINTER(C.c_uint8), _dp, _dp, C.POINTER(NdcholInfo)]),
     ("cgp_ca_plan_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _ip, _ip, _ip]),

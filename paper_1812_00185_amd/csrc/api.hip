@@ -145,6 +145,7 @@ struct cgp_ctx {
   cgp::MomLattice mlat{};               // their launch description
   double* mrhs = nullptr;               // [3][N_f] mass-solve right-hand sides
   double* mx[3] = {nullptr, nullptr, nullptr};  // [3][N_f] Chebyshev iterates
+  float* my[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // mixed form: [5][N_f][3]
   int cheb_iters = 0;
   // lattice layout of the mass solves (host structure and device view)
   cgp::Lattice lat;
@@ -245,7 +246,11 @@ size_t carve(cgp_ctx* c, void* base) {
     c->mtri = w.take<cgp::MomTri>(c->mtri_h.size());
   }
   c->mrhs = w.take<double>(3 * nf);
-  for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
+  if (c->prob.mass_mode == CGP_MASS_CONSISTENT_MIXED) {
+    for (int k = 0; k < 5; ++k) c->my[k] = w.take<float>(3 * nf);
+  } else {
+    for (int k = 0; k < 3; ++k) c->mx[k] = w.take<double>(3 * nf);
+  }
 
   int32_t* rp_c = w.take<int32_t>(nc + 1);
   int32_t* col_c = w.take<int32_t>(nnzc);
@@ -795,28 +800,49 @@ int run_correct(cgp_ctx* c, const double* ut, const double* phi_f, const double*
   // form: M dp = -nu D U~ on all nodes.  Consistent M: one fused Chebyshev
   // solve; lumped M (Eq. 27 for p, and for U in mode LUMPED): a division by
   // the row sum 2 M_ii, fused into the right-hand-side kernel
+  const bool mixed = mode == CGP_MASS_CONSISTENT_MIXED;
+  const bool consistent = mode == CGP_MASS_CONSISTENT || mixed;
   const bool cheb_u = mode != CGP_MASS_LUMPED;
-  const bool cheb_p = chi && mode == CGP_MASS_CONSISTENT;
+  const bool cheb_p = chi && consistent;
   const int nr = cheb_u ? (cheb_p ? 3 : 2) : 0;
-  if (mode == CGP_MASS_CONSISTENT) {
+  if (consistent) {
     // right-hand sides on the lattice layout, geometry from the coarse mesh
     const cgp::CorrLatArgs A{c->nf,      reinterpret_cast<const double*>(c->C.xy), c->cn_ptr,
                              c->cn_tri, c->corr_v4, phi_c, P.dt, P.nu, chi};
-    if (!cgp::launch_correct_rhs_lattice(c->latd, c->node_of, phi_f, ut, A, c->mrhs, s))
+    if (!cgp::launch_correct_rhs_lattice(c->latd, c->node_of, phi_f, ut, A, c->mrhs,
+                                         mixed ? c->my[3] : nullptr, s))
       return fail(CGP_ERR_INVALID, "correction right-hand side: misaligned buffer or unsupported lattice size");
   } else {
     cgp::launch_correct_rhs(c->F, c->dir_index, c->Mval, P.dt, P.nu, chi, mode, phi_f, ut, p_in,
                             c->mrhs, u_out, p_out, c->latd.lat_of, s);
   }
   if (st) {
-    // a-priori bound of the Chebyshev iteration on [1/2, 2]; lumped: exact
-    const double bound = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
+    // a-priori bound of the Chebyshev iteration on [1/2, 2]; lumped: exact.
+    // Mixed: two refinement steps, each reducing the error by the inner
+    // bound plus an allowance of 8 float ulps for the float storage
+    const double inner = 4.0 * std::pow(1.0 / 3.0, c->cheb_iters);
+    const double bound = mixed ? std::pow(inner + 8.0 * 0x1p-24, 2) : inner;
+    const int steps = mixed ? 2 * c->cheb_iters : c->cheb_iters;
     for (int d = 0; d < 3; ++d) {
       const bool solved = d < 2 ? cheb_u : cheb_p;
-      st[d] = cgp_solve_stats{solved ? c->cheb_iters : 0, 0, 1, 0, solved ? bound : 0.0};
+      st[d] = cgp_solve_stats{solved ? steps : 0, mixed && solved ? 2 : 0, 1, 0,
+                              solved ? bound : 0.0};
     }
   }
   if (nr == 0) return CGP_OK;  // the kernel wrote U and P
+  if (mixed) {
+    const float* d1 = nullptr;
+    const float* d2 = nullptr;
+    if (!cgp::launch_cheb_mixed(c->latd, c->nf, c->mrhs, nr, c->my, c->cheb_iters, s,
+                                (c->timed_id == CGP_K_MASS_SPMV || c->timed_id == CGP_K_MASS_PAIR)
+                                    ? cheb_timer
+                                    : nullptr,
+                                c, &d1, &d2))
+      return fail(CGP_ERR_INVALID, "mass solve: misaligned vectors or unsupported lattice size");
+    cgp::launch_final_update2(c->nf, ut, d1, d2, p_in, phi_f, nr, true, u_out, p_out,
+                              c->latd.lat_of, s);
+    return CGP_OK;
+  }
   const double* du = cgp::launch_cheb(c->latd, c->nf, c->mrhs, nr, c->mx, c->cheb_iters, s,
                                       (c->timed_id == CGP_K_MASS_SPMV || c->timed_id == CGP_K_MASS_PAIR) ? cheb_timer : nullptr, c);
   if (!du) return fail(CGP_ERR_INVALID, "mass solve: misaligned vectors or unsupported lattice size");
@@ -849,7 +875,7 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
       !(prob->mass_tol > 0) || !(prob->inner_tol > 0) || prob->max_iter < 1 ||
       prob->mom_max_iter < 1 || prob->mass_max_iter < 1 || prob->max_outer < 1)
     return fail(CGP_ERR_INVALID, "dt, nu, tolerances and iteration caps must be positive");
-  if (prob->mass_mode < CGP_MASS_CONSISTENT || prob->mass_mode > CGP_MASS_LUMPED)
+  if (prob->mass_mode < CGP_MASS_CONSISTENT || prob->mass_mode > CGP_MASS_CONSISTENT_MIXED)
     return fail(CGP_ERR_INVALID, "unknown mass_mode");
   if (prob->coarse_precond != CGP_PRECOND_JACOBI && prob->coarse_precond != CGP_PRECOND_NDCHOL &&
       prob->coarse_precond != CGP_PRECOND_JACOBI_S4)
@@ -930,7 +956,11 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
       }
     c->hbar = cnt ? sum / cnt : 1.0;
   }
-  c->cheb_iters = cgp::cheb_iterations(prob->mass_tol);
+  // mixed: each of the two float solves reduces the error to the square
+  // root of mass_tol, with one step more for the float storage
+  c->cheb_iters = prob->mass_mode == CGP_MASS_CONSISTENT_MIXED
+                      ? cgp::cheb_iterations(std::sqrt(prob->mass_tol)) + 1
+                      : cgp::cheb_iterations(prob->mass_tol);
   if (c->cheb_iters > prob->mass_max_iter) {
     delete c;
     return fail(CGP_ERR_INVALID, "mass_max_iter is below the Chebyshev count for mass_tol");
@@ -1231,10 +1261,11 @@ bool host_vertex_rows(const cgp::Lattice& L, int32_t n, const int32_t* rowptr, c
 }
 
 // One Chebyshev step over the lattice nodes [l0, l1) as the single-step
-// kernel computes it: out = x + ca (x - xm) + cb D^-1 (b - M x).
-template <int NR>
-bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, const double* b,
-                      const double* xm, const double* x, double ca, double cb, double* out) {
+// kernel computes it: out = x + ca (x - xm) + cb D^-1 (b - M x), values
+// stored as T and combined in FP64.
+template <typename T, int NR>
+bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, const T* b,
+                      const T* xm, const T* x, double ca, double cb, T* out) {
   bool ok = true;
   for (int32_t l = l0; l < l1; ++l) {
     double y[NR], dg;
@@ -1244,7 +1275,7 @@ bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, c
                                        ok = false;
                                        return 0.0;
                                      }
-                                     return x[(int64_t)k * NR + d];
+                                     return (double)x[(int64_t)k * NR + d];
                                    },
                                    y, dg);
     const bool masked = v.ldir[l] != 0;
@@ -1252,28 +1283,31 @@ bool cheb_single_host(const cgp::LatDev& v, int32_t n, int32_t l0, int32_t l1, c
     for (int d = 0; d < NR; ++d) {
       const double xl = x[(int64_t)l * NR + d];
       out[(int64_t)l * NR + d] =
-          (d < 2 && masked) ? 0.0 : xl + ca * (xl - xm[(int64_t)l * NR + d]) + cb * di * (b[(int64_t)l * NR + d] - y[d]);
+          (T)((d < 2 && masked) ? 0.0
+                                : xl + ca * (xl - (double)xm[(int64_t)l * NR + d]) +
+                                      cb * di * ((double)b[(int64_t)l * NR + d] - y[d]));
     }
   }
   return ok;
 }
 
 // A whole mass solve of `iters` Chebyshev steps on the host, launch by
-// launch as launch_cheb runs it: a first step on every node (x_0 = 0), then
-// with pairs (lattice size 8) the step pairs -- a single step over
-// [EB & ~1, n), the interior kernel block by block (each phase for every
+// launch as the device solve runs it: a first step on every node (x_0 = 0),
+// then with pairs (lattice size 8) the step pairs -- a single step over
+// [EB & ~3, n), the interior kernel block by block (each phase for every
 // thread before the next), a single step again -- and single steps on every
 // node for the rest; without pairs single steps throughout.  Lattice-ordered
-// vectors; the three iterate buffers start as NaN, so a value read before
-// any launch wrote it shows up in the result.
-template <int NR>
-bool cheb_solve_host(const cgp::LatDev& v, int32_t n, const double* b, int iters, bool pairs,
-                     double* out) {
+// vectors stored as T; the three iterate buffers start as NaN, so a value
+// read before any launch wrote it shows up in the result.
+template <typename T, int NR>
+bool cheb_solve_host(const cgp::LatDev& v, int32_t n, const T* b, int iters, bool pairs,
+                     T* out) {
   using namespace cgp;
+  constexpr int kPer = 16 / (int)sizeof(T);
   const size_t len = (size_t)n * NR;
-  std::vector<double> xs[3];
-  for (auto& x : xs) x.assign(len, std::nan(""));
-  double* x[3] = {xs[0].data(), xs[1].data(), xs[2].data()};
+  std::vector<T> xs[3];
+  for (auto& x : xs) x.assign(len, (T)std::nan(""));
+  T* x[3] = {xs[0].data(), xs[1].data(), xs[2].data()};
   // (ca_k, cb_k) of the three-term recurrence on [1/2, 2]
   std::vector<double> ca(iters), cb(iters);
   {
@@ -1294,45 +1328,74 @@ bool cheb_solve_host(const cgp::LatDev& v, int32_t n, const double* b, int iters
     const double di = 1.0 / lat_diag(v, l);
     const bool masked = v.ldir[l] != 0;
     for (int d = 0; d < NR; ++d) {
-      x[1][(int64_t)l * NR + d] = (d < 2 && masked) ? 0.0 : cb[0] * di * b[(int64_t)l * NR + d];
-      x[0][(int64_t)l * NR + d] = 0.0;
+      x[1][(int64_t)l * NR + d] = (T)((d < 2 && masked) ? 0.0 : cb[0] * di * (double)b[(int64_t)l * NR + d]);
+      x[0][(int64_t)l * NR + d] = (T)0;
     }
   }
   bool ok = true;
   ch2_fault = false;
-  auto cp2 = [](const double* src, double* dst) {
-    dst[0] = src[0];
-    dst[1] = src[1];
+  auto cp16 = [](const T* src, T* dst) {
+    for (int j = 0; j < kPer; ++j) dst[j] = src[j];
   };
   static constexpr Ch2NbTable nbt = ch2_make_nb_table();
-  auto S = std::make_unique<Cheb2Shared<NR>>();
-  const int32_t lb = v.EB & ~1;
+  auto S = std::make_unique<Cheb2Shared<T, NR>>();
+  const int32_t lb = v.EB & ~3;
   const int nblk = (v.nT + kCh2Tris - 1) / kCh2Tris;
   for (int k = 1; k < iters;) {
     if (!pairs || k + 1 >= iters) {
-      ok = ok && cheb_single_host<NR>(v, n, 0, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
-                                      x[(k + 1) % 3]);
+      ok = ok && cheb_single_host<T, NR>(v, n, 0, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
+                                         x[(k + 1) % 3]);
       k += 1;
       continue;
     }
-    ok = ok && cheb_single_host<NR>(v, n, lb, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
-                                    x[(k + 1) % 3]);
-    const Cheb2Args A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
-                      ca[k], cb[k], ca[k + 1], cb[k + 1]};
+    ok = ok && cheb_single_host<T, NR>(v, n, lb, n, b, x[(k + 2) % 3], x[k % 3], ca[k], cb[k],
+                                       x[(k + 1) % 3]);
+    const Cheb2Args<T> A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
+                         ca[k], cb[k], ca[k + 1], cb[k + 1]};
     for (int blk = 0; blk < nblk; ++blk) {
-      std::fill_n(reinterpret_cast<double*>(S.get()), sizeof(Cheb2Shared<NR>) / sizeof(double),
-                  std::nan(""));
-      for (int t = 0; t < kCh2Threads; ++t) ch2_stage<NR>(v, A, blk, t, *S, cp2, cp2);
-      for (int t = 0; t < kCh2Threads; ++t) ch2_step1<NR>(v, A, blk, t, nbt.w, *S);
-      for (int t = 0; t < kCh2Threads; ++t) ch2_step2<NR>(v, A, blk, t, nbt.w, *S);
-      for (int t = 0; t < kCh2Threads; ++t) ch2_write<NR>(v, A, blk, t, *S, cp2);
+      std::fill_n(reinterpret_cast<T*>(S.get()), sizeof(Cheb2Shared<T, NR>) / sizeof(T),
+                  (T)std::nan(""));
+      for (int t = 0; t < kCh2Threads; ++t) ch2_stage<T, NR>(v, A, blk, t, *S, cp16, cp16);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_step1<T, NR>(v, A, blk, t, nbt.w, *S);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_step2<T, NR>(v, A, blk, t, nbt.w, *S);
+      for (int t = 0; t < kCh2Threads; ++t) ch2_write<T, NR>(v, A, blk, t, *S, cp16);
     }
-    ok = ok && cheb_single_host<NR>(v, n, lb, n, b, x[k % 3], x[(k + 1) % 3], ca[k + 1],
-                                    cb[k + 1], x[(k + 2) % 3]);
+    ok = ok && cheb_single_host<T, NR>(v, n, lb, n, b, x[k % 3], x[(k + 1) % 3], ca[k + 1],
+                                       cb[k + 1], x[(k + 2) % 3]);
     k += 2;
   }
   ok = ok && !ch2_fault;
   std::copy(x[iters % 3], x[iters % 3] + len, out);
+  return ok;
+}
+
+// The mixed-precision solve as the device runs it: float solve of b's float
+// copy (d1), FP64 residual r = b - M d1 stored as float, float solve of r
+// (d2); x = d1 + d2 in FP64.
+template <int NR>
+bool cheb_mixed_host(const cgp::LatDev& v, int32_t n, const double* b, int iters, bool pairs,
+                     double* out) {
+  const size_t len = (size_t)n * NR;
+  std::vector<float> b32(len), d1(len), r32(len), d2(len);
+  for (size_t i = 0; i < len; ++i) b32[i] = (float)b[i];
+  bool ok = cheb_solve_host<float, NR>(v, n, b32.data(), iters, pairs, d1.data());
+  for (int32_t l = 0; l < n; ++l) {
+    double y[NR], dg;
+    cgp::lat_apply<NR, cgp::kCh2M>(v, l,
+                                   [&](int32_t k, int d) {
+                                     if (k < 0 || k >= n) {
+                                       ok = false;
+                                       return 0.0;
+                                     }
+                                     return (double)d1[(size_t)k * NR + d];
+                                   },
+                                   y, dg);
+    const bool masked = v.ldir[l] != 0;
+    for (int d = 0; d < NR; ++d)
+      r32[(size_t)l * NR + d] = (d < 2 && masked) ? 0.0f : (float)(b[(size_t)l * NR + d] - y[d]);
+  }
+  ok = ok && cheb_solve_host<float, NR>(v, n, r32.data(), iters, pairs, d2.data());
+  for (size_t i = 0; i < len; ++i) out[i] = (double)d1[i] + (double)d2[i];
   return ok;
 }
 
@@ -1383,7 +1446,7 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* c, const int32_t* rowptr, const i
 
 int cgp_lattice_cheb_solve_host(const cgp_ctx* c, const int32_t* rowptr, const int32_t* col,
                                 const double* mval, int32_t nr, const double* b, int32_t iters,
-                                int32_t pairs, double* x) {
+                                int32_t pairs, int32_t mixed, double* x) {
   if (!c || !rowptr || !col || !mval || !b || !x) return fail(CGP_ERR_INVALID, "null argument");
   if (nr != 2 && nr != 3) return fail(CGP_ERR_INVALID, "nr must be 2 or 3");
   if (iters < 1 || iters > 1000) return fail(CGP_ERR_INVALID, "iters must be 1..1000");
@@ -1400,8 +1463,13 @@ int cgp_lattice_cheb_solve_host(const cgp_ctx* c, const int32_t* rowptr, const i
   std::vector<double> bl(len), xl(len);
   for (int32_t i = 0; i < n; ++i)
     for (int d = 0; d < nr; ++d) bl[(size_t)L.lat_of[i] * nr + d] = b[(size_t)i * nr + d];
-  const bool ok = nr == 3 ? cheb_solve_host<3>(v, n, bl.data(), iters, pairs != 0, xl.data())
-                          : cheb_solve_host<2>(v, n, bl.data(), iters, pairs != 0, xl.data());
+  bool ok;
+  if (mixed)
+    ok = nr == 3 ? cheb_mixed_host<3>(v, n, bl.data(), iters, pairs != 0, xl.data())
+                 : cheb_mixed_host<2>(v, n, bl.data(), iters, pairs != 0, xl.data());
+  else
+    ok = nr == 3 ? cheb_solve_host<double, 3>(v, n, bl.data(), iters, pairs != 0, xl.data())
+                 : cheb_solve_host<double, 2>(v, n, bl.data(), iters, pairs != 0, xl.data());
   if (!ok) return fail(CGP_ERR_INVALID, "mass solve: index out of range");
   for (int32_t i = 0; i < n; ++i)
     for (int d = 0; d < nr; ++d) x[(size_t)i * nr + d] = xl[(size_t)L.lat_of[i] * nr + d];

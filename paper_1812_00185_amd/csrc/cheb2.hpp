@@ -44,23 +44,27 @@ inline bool ch2_fault = false;
 #define CH2_CHECK(c) (void)(ch2_fault = ch2_fault || !(c))
 #endif
 
+// Values are stored as T (double, or float for the inner solves of the
+// mixed-precision form) and combined in FP64.
+//
 // Block workspace (LDS on the device).  Sizes are multiples of 16 bytes, so
 // every array starts 16-byte aligned when the structure does.
-template <int NR>
+template <typename T, int NR>
 struct Cheb2Shared {
-  double xk[kCh2All * NR];  // x_k: interior nodes, then edge-node slots
-  double x1[kCh2All * NR];  // x_{k+1}: interior nodes, then edge-node slots
-  double xm[kCh2Own * NR];  // x_{k-1}; x_{k+2} once step 2 has run
-  double b[kCh2Own * NR];   // right-hand sides
+  T xk[kCh2All * NR];  // x_k: interior nodes, then edge-node slots
+  T x1[kCh2All * NR];  // x_{k+1}: interior nodes, then edge-node slots
+  T xm[kCh2Own * NR];  // x_{k-1}; x_{k+2} once step 2 has run
+  T b[kCh2Own * NR];   // right-hand sides
 };
 
+template <typename T>
 struct Cheb2Args {
-  int32_t n;         // lattice nodes
-  const double* b;   // [n][NR]
-  const double* xm;  // x_{k-1}
-  const double* xk;  // x_k
-  double* x1;        // x_{k+1}: read on the edge nodes, written on the interior
-  double* x2;        // x_{k+2}, written on the interior (may be the buffer of xm)
+  int32_t n;    // lattice nodes
+  const T* b;   // [n][NR]
+  const T* xm;  // x_{k-1}
+  const T* xk;  // x_k
+  T* x1;        // x_{k+1}: read on the edge nodes, written on the interior
+  T* x2;        // x_{k+2}, written on the interior (may be the buffer of xm)
   double ca1, cb1, ca2, cb2;
 };
 
@@ -127,31 +131,38 @@ CGP_HD inline void ch2_halo_point(int h, int& g, int& a, int& b) {
 }
 
 // Phase 1: the block's interior ranges of x_k, x_{k-1} and b as 16-byte
-// pieces (ld2 / ldnt2 copy two doubles from a 16-byte aligned address;
-// ldnt2 for the streams read once), and x_k, x_{k+1} at the edge nodes.
-template <int NR, class Ld2, class LdNt2>
-CGP_HD inline void ch2_stage(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             Cheb2Shared<NR>& S, Ld2 ld2, LdNt2 ldnt2) {
+// pieces (ld16 / ldnt16 copy 16 bytes between 16-byte aligned addresses;
+// ldnt16 for the streams read once), and x_k, x_{k+1} at the edge nodes.
+template <typename T, int NR, class Ld16, class LdNt16>
+CGP_HD inline void ch2_stage(const LatDev& L, const Cheb2Args<T>& A, int blk, int tid,
+                             Cheb2Shared<T, NR>& S, Ld16 ld16, LdNt16 ldnt16) {
+  constexpr int kPer = 16 / (int)sizeof(T);
   const int ntri = ch2_ntri(L, blk);
-  const int64_t v0 = (int64_t)blk * kCh2Own * NR;  // even: 16-byte aligned
+  // kCh2Own NR values per block: a multiple of 16 bytes, so aligned
+  const int64_t v0 = (int64_t)blk * kCh2Own * NR;
   const int nv = ntri * kCh2NI * NR;
   CH2_CHECK(ntri > 0 && v0 + nv <= (int64_t)L.EB * NR && L.EB <= A.n);
-  for (int q = tid; 2 * q < nv; q += kCh2Threads) {
-    if (2 * q + 1 < nv) {
-      ld2(A.xk + v0 + 2 * q, S.xk + 2 * q);
-      ldnt2(A.xm + v0 + 2 * q, S.xm + 2 * q);
-      ldnt2(A.b + v0 + 2 * q, S.b + 2 * q);
+  for (int q = tid; q * kPer < nv; q += kCh2Threads) {
+    const int v = q * kPer;
+    if (v + kPer <= nv) {
+      ld16(A.xk + v0 + v, S.xk + v);
+      ldnt16(A.xm + v0 + v, S.xm + v);
+      ldnt16(A.b + v0 + v, S.b + v);
     } else {
-      S.xk[2 * q] = A.xk[v0 + 2 * q];
-      S.xm[2 * q] = A.xm[v0 + 2 * q];
-      S.b[2 * q] = A.b[v0 + 2 * q];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (v + j < nv) {
+          S.xk[v + j] = A.xk[v0 + v + j];
+          S.xm[v + j] = A.xm[v0 + v + j];
+          S.b[v + j] = A.b[v0 + v + j];
+        }
     }
   }
   for (int h = tid; h < ntri * 3 * (kCh2M - 1); h += kCh2Threads) {
     int g, a, b;
     ch2_halo_point(h, g, a, b);
-    const int32_t T = blk * kCh2Tris + g;
-    const int32_t i = Ch2Lat::index(L, T, Ch2Lat::tri(L, T), a, b);
+    const int32_t tri = blk * kCh2Tris + g;
+    const int32_t i = Ch2Lat::index(L, tri, Ch2Lat::tri(L, tri), a, b);
     CH2_CHECK(i >= L.EB && i < L.VB && ch2_slot(g, a, b) == kCh2Own + h);
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
@@ -165,16 +176,14 @@ CGP_HD inline void ch2_stage(const LatDev& L, const Cheb2Args& A, int blk, int t
 // iterate, every slot), xm (previous, interior) and bb; writes out
 // (interior).  out may be xm: a thread reads its node's xm before writing
 // it, and no other thread reads that value.  nbt: the neighbour table.
-template <int NR>
+template <typename T, int NR>
 CGP_HD inline void ch2_step(const LatDev& L, int blk, int tid, const uint64_t* nbt,
-                            const double* x, const double* xm, const double* bb, double ca,
-                            double cb, double* out) {
+                            const T* x, const T* xm, const T* bb, double ca, double cb, T* out) {
   const int ntri = ch2_ntri(L, blk);
   for (int t = tid; t < ntri * kCh2NI; t += kCh2Threads) {
     const int g = t / kCh2NI;
     const int r = t - g * kCh2NI;
-    const int32_t T = blk * kCh2Tris + g;
-    const double At = L.af[T];
+    const double At = L.af[blk * kCh2Tris + g];
     const uint64_t w = nbt[r];
     int nb[6];
 #pragma unroll
@@ -196,42 +205,50 @@ CGP_HD inline void ch2_step(const LatDev& L, int blk, int tid, const uint64_t* n
     const double di = 1.0 / At;
 #pragma unroll
     for (int d = 0; d < NR; ++d) {
-      const double s = ((x[nb[0] * NR + d] + x[nb[1] * NR + d]) + (x[nb[2] * NR + d] + x[nb[3] * NR + d])) +
-                       (x[nb[4] * NR + d] + x[nb[5] * NR + d]);
+      auto xq = [&](int q) { return (double)x[nb[q] * NR + d]; };
+      const double s = ((xq(0) + xq(1)) + (xq(2) + xq(3))) + (xq(4) + xq(5));
       const double xv = x[t * NR + d];
       const double y = At * xv + (At / 6.0) * s;
-      out[t * NR + d] = (d < 2 && masked) ? 0.0 : xv + ca * (xv - xm[t * NR + d]) + cb * di * (bb[t * NR + d] - y);
+      out[t * NR + d] = (T)((d < 2 && masked)
+                                ? 0.0
+                                : xv + ca * (xv - (double)xm[t * NR + d]) + cb * di * ((double)bb[t * NR + d] - y));
     }
   }
 }
 
 // Phases 2 and 3: x_{k+1} into S.x1, then x_{k+2} over S.xm.
-template <int NR>
-CGP_HD inline void ch2_step1(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             const uint64_t* nbt, Cheb2Shared<NR>& S) {
-  ch2_step<NR>(L, blk, tid, nbt, S.xk, S.xm, S.b, A.ca1, A.cb1, S.x1);
+template <typename T, int NR>
+CGP_HD inline void ch2_step1(const LatDev& L, const Cheb2Args<T>& A, int blk, int tid,
+                             const uint64_t* nbt, Cheb2Shared<T, NR>& S) {
+  ch2_step<T, NR>(L, blk, tid, nbt, S.xk, S.xm, S.b, A.ca1, A.cb1, S.x1);
 }
-template <int NR>
-CGP_HD inline void ch2_step2(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             const uint64_t* nbt, Cheb2Shared<NR>& S) {
-  ch2_step<NR>(L, blk, tid, nbt, S.x1, S.xk, S.b, A.ca2, A.cb2, S.xm);
+template <typename T, int NR>
+CGP_HD inline void ch2_step2(const LatDev& L, const Cheb2Args<T>& A, int blk, int tid,
+                             const uint64_t* nbt, Cheb2Shared<T, NR>& S) {
+  ch2_step<T, NR>(L, blk, tid, nbt, S.x1, S.xk, S.b, A.ca2, A.cb2, S.xm);
 }
 
 // Phase 4: the interior ranges of x_{k+1} and x_{k+2} out as 16-byte pieces
-// (st2 copies two doubles to a 16-byte aligned address).
-template <int NR, class St2>
-CGP_HD inline void ch2_write(const LatDev& L, const Cheb2Args& A, int blk, int tid,
-                             const Cheb2Shared<NR>& S, St2 st2) {
+// (st16 copies 16 bytes between 16-byte aligned addresses).
+template <typename T, int NR, class St16>
+CGP_HD inline void ch2_write(const LatDev& L, const Cheb2Args<T>& A, int blk, int tid,
+                             const Cheb2Shared<T, NR>& S, St16 st16) {
+  constexpr int kPer = 16 / (int)sizeof(T);
   const int ntri = ch2_ntri(L, blk);
   const int64_t v0 = (int64_t)blk * kCh2Own * NR;
   const int nv = ntri * kCh2NI * NR;
-  for (int q = tid; 2 * q < nv; q += kCh2Threads) {
-    if (2 * q + 1 < nv) {
-      st2(S.x1 + 2 * q, A.x1 + v0 + 2 * q);
-      st2(S.xm + 2 * q, A.x2 + v0 + 2 * q);
+  for (int q = tid; q * kPer < nv; q += kCh2Threads) {
+    const int v = q * kPer;
+    if (v + kPer <= nv) {
+      st16(S.x1 + v, A.x1 + v0 + v);
+      st16(S.xm + v, A.x2 + v0 + v);
     } else {
-      A.x1[v0 + 2 * q] = S.x1[2 * q];
-      A.x2[v0 + 2 * q] = S.xm[2 * q];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (v + j < nv) {
+          A.x1[v0 + v + j] = S.x1[v + j];
+          A.x2[v0 + v + j] = S.xm[v + j];
+        }
     }
   }
 }

@@ -133,6 +133,15 @@ constexpr int kChebTimedPair = 1;
 double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
                     double* const x[3], int iters, hipStream_t s,
                     hipEvent_t* (*timer)(void*, int), void* tctx);
+// Mixed precision: FP64 iterative refinement around two float Chebyshev solves
+// of `iters` steps each (iterates stored as float, combined in FP64): d1 from
+// M d1 = b (b's float copy in y[3]), then the residual r = b - M d1 (FP64,
+// over y[3]), then d2 from M d2 = r; the solution is d1 + d2.  y: five float
+// buffers [n][nr], 16-byte aligned.  Returns false (nothing launched) for an
+// unsupported lattice size or misaligned buffers.
+bool launch_cheb_mixed(const LatDev& L, int32_t n, const double* b, int nr, float* const y[5],
+                       int iters, hipStream_t s, hipEvent_t* (*timer)(void*, int), void* tctx,
+                       const float** d1, const float** d2);
 
 // ---------------------------------------------------------------- restriction / prolongation
 void launch_restrict_galerkin(const int32_t* tri_f, int32_t n_fine_tris, const double2* xy_f,
@@ -166,12 +175,17 @@ void launch_correct_rhs(const DLevel& L, const int32_t* dir_index, const double*
 // (nothing launched) for a misaligned buffer or an unsupported lattice size
 bool launch_correct_rhs_lattice(const LatDev& L, const int32_t* node_of, const double* phi,
                                 const double* ut, const struct CorrLatArgs& A, double* rhs,
-                                hipStream_t s);
+                                float* rhs32, hipStream_t s);
 // U = U~ + dU from the solved increments du [n][nr]; P = P + phi (+ du[2]
 // when nr = 3) unless write_p is false
 void launch_final_update(int32_t n, const double* ut, const double* du, const double* p_in,
                          const double* phi_f, int nr, bool write_p, double* u_out,
                          double* p_out, const int32_t* lat_of, hipStream_t s);
+// the same with dU (and dp) = d1 + d2 from the two float solves of
+// launch_cheb_mixed, added in FP64
+void launch_final_update2(int32_t n, const double* ut, const float* d1, const float* d2,
+                          const double* p_in, const double* phi_f, int nr, bool write_p,
+                          double* u_out, double* p_out, const int32_t* lat_of, hipStream_t s);
 
 // ---------------------------------------------------------------- small vector ops
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);

@@ -1216,6 +1216,24 @@ k_final_update(int32_t n32, const double* __restrict__ ut, const double* __restr
   }
 }
 
+// The same with dU (and dp) as the sum of the two float solves of the
+// mixed-precision mass solves, added in FP64.
+__global__ void __launch_bounds__(kBlock)
+k_final_update2(int32_t n32, const double* __restrict__ ut, const float* __restrict__ d1,
+                const float* __restrict__ d2, const double* p_in, const double* __restrict__ phi,
+                int nr, int write_p, double* __restrict__ u_out, double* p_out,
+                const int32_t* __restrict__ lat_of) {
+  const int64_t n = n32;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int64_t k = (int64_t)lat_of[i] * nr;
+    u_out[i] = ut[i] + ((double)d1[k] + (double)d2[k]);
+    u_out[n + i] = ut[n + i] + ((double)d1[k + 1] + (double)d2[k + 1]);
+    if (write_p) {
+      const double pv = (p_in ? p_in[i] : 0.0) + phi[i];  // p_in == nullptr: P = phi
+      p_out[i] = nr == 3 ? pv + ((double)d1[k + 2] + (double)d2[k + 2]) : pv;
+    }
+  }
+}
 
 // ------------------------------------------------------------------ guess guard
 // Partial sums of ||b - K x||^2 for two candidate initial guesses (FP64).
@@ -1596,6 +1614,13 @@ void launch_final_update(int32_t n, const double* ut, const double* du, const do
                          double* p_out, const int32_t* lat_of, hipStream_t s) {
   k_final_update<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, du, p_in, phi_f, nr,
                                                         write_p ? 1 : 0, u_out, p_out, lat_of);
+}
+
+void launch_final_update2(int32_t n, const double* ut, const float* d1, const float* d2,
+                          const double* p_in, const double* phi_f, int nr, bool write_p,
+                          double* u_out, double* p_out, const int32_t* lat_of, hipStream_t s) {
+  k_final_update2<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, ut, d1, d2, p_in, phi_f, nr,
+                                                         write_p ? 1 : 0, u_out, p_out, lat_of);
 }
 
 void launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {

@@ -38,52 +38,68 @@ namespace {
 // 169 us per launch against 127 us staged, 2049^2 k = 3, NR = 3); neighbours
 // inside the block's range are read from LDS, the others gathered from x_k.
 // b and the iterates must be 16-byte aligned (the workspace pieces are
-// 256-byte aligned).  The launch covers the nodes [lbase, n), lbase even (so
-// that every block range starts 16-byte aligned), with (n - lbase) / kBlock
-// blocks rounded up.
-typedef double nt_d2 __attribute__((ext_vector_type(2)));
+// 256-byte aligned).  The launch covers the nodes [lbase, n), lbase a multiple
+// of 4 (so that every block range starts 16-byte aligned), with
+// (n - lbase) / kBlock blocks rounded up.  Values are stored as T (double, or
+// float for the inner solves of the mixed-precision form) and combined in
+// FP64.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NR, int M>
+template <typename T>
+__device__ inline void ld16(const T* src, T* dst) {
+  *reinterpret_cast<u32x4*>(dst) = *reinterpret_cast<const u32x4*>(src);
+}
+template <typename T>
+__device__ inline void ldnt16(const T* src, T* dst) {
+  *reinterpret_cast<u32x4*>(dst) = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
+}
+template <typename T>
+__device__ inline void stnt16(const T* src, T* dst) {
+  __builtin_nontemporal_store(*reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst));
+}
+
+template <typename T, int NR, int M>
 __global__ void __launch_bounds__(kBlock)
-k_cheb_lattice(LatDev L, int32_t n, int32_t lbase, const double* __restrict__ b,
-               double* __restrict__ xk, const double* __restrict__ xkm, double* __restrict__ xnew,
-               double ca, double cb, int first) {
-  constexpr int kVals = kBlock * NR;  // doubles per block
-  constexpr int kPieces = kVals / 2;  // 16-byte pieces per block
-  __shared__ double2 sb[kPieces], sm[kPieces], sx[kPieces];
+k_cheb_lattice(LatDev L, int32_t n, int32_t lbase, const T* __restrict__ b, T* __restrict__ xk,
+               const T* __restrict__ xkm, T* __restrict__ xnew, double ca, double cb, int first) {
+  constexpr int kPer = 16 / (int)sizeof(T);  // values per 16-byte piece
+  constexpr int kVals = kBlock * NR;         // values per block
+  constexpr int kPieces = kVals / kPer;
+  static_assert(kVals % kPer == 0, "block range in whole pieces");
+  __shared__ u32x4 sb[kPieces], sm[kPieces], sx[kPieces];
+  T* sbd = reinterpret_cast<T*>(sb);
+  T* smd = reinterpret_cast<T*>(sm);
+  T* sxd = reinterpret_cast<T*>(sx);
   // blocks in reverse order: the coarse-vertex rows (at the end of the
   // layout; short rows of dependent gathers) start first instead of trailing
   const int32_t l0 = lbase + (int32_t)(gridDim.x - 1 - blockIdx.x) * kBlock;
   const int32_t l = l0 + threadIdx.x;
-  const int64_t v0 = (int64_t)l0 * NR;  // first double of the block
-  const int64_t vend = (int64_t)n * NR;  // doubles in the vector
-  const double2* b2 = reinterpret_cast<const double2*>(b + v0);
-  const double2* m2 = reinterpret_cast<const double2*>(xkm + v0);
-  const double2* x2 = reinterpret_cast<const double2*>(xk + v0);
+  const int64_t v0 = (int64_t)l0 * NR;   // first value of the block
+  const int64_t vend = (int64_t)n * NR;  // values in the vector
 #pragma unroll
   for (int q = threadIdx.x; q < kPieces; q += kBlock) {
-    if (v0 + 2 * q + 1 < vend) {
+    const int64_t v = v0 + (int64_t)q * kPer;
+    if (v + kPer <= vend) {
       // b and x_{k-1} are read once per launch: non-temporal, so that the L2
       // keeps x_k, which neighbouring blocks gather
-      const nt_d2 bv = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(b2) + q);
-      sb[q] = make_double2(bv.x, bv.y);
+      ldnt16(b + v, sbd + q * kPer);
       if (!first) {
-        const nt_d2 mv = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(m2) + q);
-        sm[q] = make_double2(mv.x, mv.y);
-        sx[q] = x2[q];
+        ldnt16(xkm + v, smd + q * kPer);
+        ld16(xk + v, sxd + q * kPer);
       }
-    } else if (v0 + 2 * q < vend) {
-      sb[q] = make_double2(b[v0 + 2 * q], 0.0);
-      if (!first) {
-        sm[q] = make_double2(xkm[v0 + 2 * q], 0.0);
-        sx[q] = make_double2(xk[v0 + 2 * q], 0.0);
-      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (v + j < vend) {
+          sbd[q * kPer + j] = b[v + j];
+          if (!first) {
+            smd[q * kPer + j] = xkm[v + j];
+            sxd[q * kPer + j] = xk[v + j];
+          }
+        }
     }
   }
   __syncthreads();
-  const double* sbd = reinterpret_cast<const double*>(sb);
-  const double* smd = reinterpret_cast<const double*>(sm);
-  const double* sxd = reinterpret_cast<const double*>(sx);
   double out[NR];
   if (l < n) {
     const bool masked = L.ldir[l] != 0;
@@ -91,46 +107,64 @@ k_cheb_lattice(LatDev L, int32_t n, int32_t lbase, const double* __restrict__ b,
     if (first) {
       const double di = 1.0 / lat_diag(L, l);
 #pragma unroll
-      for (int d = 0; d < NR; ++d) out[d] = (d < 2 && masked) ? 0.0 : cb * di * sbd[t + d];
+      for (int d = 0; d < NR; ++d) out[d] = (d < 2 && masked) ? 0.0 : cb * di * (double)sbd[t + d];
     } else {
       double y[NR], diag;
       // neighbours inside the block's range come from LDS
       auto xv = [&](int32_t i, int d) {
         const uint32_t r = (uint32_t)(i - l0);
-        return r < (uint32_t)kBlock ? sxd[r * NR + d] : xk[(int64_t)i * NR + d];
+        return r < (uint32_t)kBlock ? (double)sxd[r * NR + d] : (double)xk[(int64_t)i * NR + d];
       };
       lat_apply<NR, M>(L, l, xv, y, diag);
       const double di = 1.0 / diag;
 #pragma unroll
       for (int d = 0; d < NR; ++d) {
         const double xv = sxd[t + d];
-        out[d] = (d < 2 && masked) ? 0.0 : xv + ca * (xv - smd[t + d]) + cb * di * (sbd[t + d] - y[d]);
+        out[d] = (d < 2 && masked) ? 0.0 : xv + ca * (xv - (double)smd[t + d]) + cb * di * ((double)sbd[t + d] - y[d]);
       }
     }
   }
   __syncthreads();  // every read of sm is done: it now stages x_new
-  double* smw = reinterpret_cast<double*>(sm);
   if (l < n) {
 #pragma unroll
-    for (int d = 0; d < NR; ++d) smw[threadIdx.x * NR + d] = out[d];
+    for (int d = 0; d < NR; ++d) smd[threadIdx.x * NR + d] = (T)out[d];
   }
   __syncthreads();
-  double2* o2 = reinterpret_cast<double2*>(xnew + v0);
-  double2* k2 = reinterpret_cast<double2*>(xk + v0);
 #pragma unroll
   for (int q = threadIdx.x; q < kPieces; q += kBlock) {
-    if (v0 + 2 * q + 1 < vend) {
-      const double2 ov = sm[q];
-      nt_d2 o;
-      o.x = ov.x;
-      o.y = ov.y;
-      __builtin_nontemporal_store(o, reinterpret_cast<nt_d2*>(o2) + q);
-      if (first) k2[q] = make_double2(0.0, 0.0);
-    } else if (v0 + 2 * q < vend) {
-      xnew[v0 + 2 * q] = smw[2 * q];
-      if (first) xk[v0 + 2 * q] = 0.0;
+    const int64_t v = v0 + (int64_t)q * kPer;
+    if (v + kPer <= vend) {
+      stnt16(smd + q * kPer, xnew + v);
+      if (first) *reinterpret_cast<u32x4*>(xk + v) = u32x4{0u, 0u, 0u, 0u};
+    } else {
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (v + j < vend) {
+          xnew[v + j] = smd[q * kPer + j];
+          if (first) xk[v + j] = (T)0;
+        }
     }
   }
+}
+
+// r = b - M x over every lattice node, b in FP64 and x stored as float, r
+// (FP64 arithmetic) stored as float; velocity components 0 at Dirichlet
+// nodes (the refinement residual of the mixed-precision mass solves).  One
+// thread per node, plain loads: staging x's block range through LDS (with
+// non-temporal loads of b) measured slower, 72 -> 83 us at 2049^2.
+template <int NR, int M>
+__global__ void __launch_bounds__(kBlock)
+k_mass_resid(LatDev L, int32_t n, const double* __restrict__ b, const float* __restrict__ x,
+             float* __restrict__ r) {
+  const int32_t l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= n) return;
+  double y[NR], diag;
+  lat_apply<NR, M>(L, l, [&](int32_t i, int d) { return (double)x[(int64_t)i * NR + d]; }, y,
+                   diag);
+  const bool masked = L.ldir[l] != 0;
+#pragma unroll
+  for (int d = 0; d < NR; ++d)
+    r[(int64_t)l * NR + d] = (d < 2 && masked) ? 0.0f : (float)(b[(int64_t)l * NR + d] - y[d]);
 }
 
 // neighbour table of the interior stencil (cheb2.hpp), in constant memory
@@ -138,40 +172,32 @@ __constant__ Ch2NbTable kCh2NbDev = ch2_make_nb_table();
 
 // Two Chebyshev steps on the interior nodes of kCh2Tris coarse triangles per
 // block (lattice size 8; the phases and their data flow are in cheb2.hpp).
-// 36 KB of LDS per block for NR = 3.
-template <int NR>
-__global__ void __launch_bounds__(kCh2Threads) k_cheb_pair(LatDev L, Cheb2Args A) {
-  __shared__ __align__(16) Cheb2Shared<NR> S;
+// 36 KB of LDS per block for T = double, NR = 3.
+template <typename T, int NR>
+__global__ void __launch_bounds__(kCh2Threads) k_cheb_pair(LatDev L, Cheb2Args<T> A) {
+  __shared__ __align__(16) Cheb2Shared<T, NR> S;
   const int blk = blockIdx.x, tid = threadIdx.x;
-  auto ld2 = [](const double* src, double* dst) {
-    *reinterpret_cast<double2*>(dst) = *reinterpret_cast<const double2*>(src);
-  };
-  auto ldnt2 = [](const double* src, double* dst) {
-    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(src));
-    *reinterpret_cast<double2*>(dst) = make_double2(v.x, v.y);
-  };
-  auto stnt2 = [](const double* src, double* dst) {
-    const double2 v = *reinterpret_cast<const double2*>(src);
-    nt_d2 o;
-    o.x = v.x;
-    o.y = v.y;
-    __builtin_nontemporal_store(o, reinterpret_cast<nt_d2*>(dst));
-  };
-  ch2_stage<NR>(L, A, blk, tid, S, ld2, ldnt2);
+  auto ld = [](const T* src, T* dst) { ld16(src, dst); };
+  auto ldnt = [](const T* src, T* dst) { ldnt16(src, dst); };
+  auto stnt = [](const T* src, T* dst) { stnt16(src, dst); };
+  ch2_stage<T, NR>(L, A, blk, tid, S, ld, ldnt);
   __syncthreads();
-  ch2_step1<NR>(L, A, blk, tid, kCh2NbDev.w, S);
+  ch2_step1<T, NR>(L, A, blk, tid, kCh2NbDev.w, S);
   __syncthreads();
-  ch2_step2<NR>(L, A, blk, tid, kCh2NbDev.w, S);
+  ch2_step2<T, NR>(L, A, blk, tid, kCh2NbDev.w, S);
   __syncthreads();
-  ch2_write<NR>(L, A, blk, tid, S, stnt2);
+  ch2_write<T, NR>(L, A, blk, tid, S, stnt);
 }
 
 // Right-hand sides of the consistent-mass solves on the lattice layout (one
 // thread per lattice node; the stencils are in corrlat.hpp): rhs [n][NR],
 // NR = 2 + chi, written through LDS as 16-byte pieces of the block's range.
+// With rhs32 (not null) also a float copy, the right-hand side of the first
+// inner solve of the mixed-precision form.
 template <int NR, int M, bool kPc>
 __global__ void __launch_bounds__(kBlock) k_correct_rhs_lat(LatDev L, CorrLatArgs A,
-                                                            double* __restrict__ rhs) {
+                                                            double* __restrict__ rhs,
+                                                            float* __restrict__ rhs32) {
   constexpr int kPieces = kBlock * NR / 2;
   __shared__ double2 so[kPieces];
   double* sod = reinterpret_cast<double*>(so);
@@ -193,6 +219,15 @@ __global__ void __launch_bounds__(kBlock) k_correct_rhs_lat(LatDev L, CorrLatArg
     else if (v0 + 2 * q < vend)
       rhs[v0 + 2 * q] = sod[2 * q];
   }
+  if (rhs32) {
+    float2* f2 = reinterpret_cast<float2*>(rhs32 + v0);
+    for (int q = threadIdx.x; q < kPieces; q += kBlock) {
+      if (v0 + 2 * q + 1 < vend)
+        f2[q] = make_float2((float)sod[2 * q], (float)sod[2 * q + 1]);
+      else if (v0 + 2 * q < vend)
+        rhs32[v0 + 2 * q] = (float)sod[2 * q];
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -206,8 +241,9 @@ k_corr_gather(int32_t n, const int32_t* __restrict__ node_of, const double* __re
 
 bool launch_correct_rhs_lattice(const LatDev& L, const int32_t* node_of, const double* phi,
                                 const double* ut, const CorrLatArgs& A, double* rhs,
-                                hipStream_t s) {
-  if (((uintptr_t)rhs & 15) != 0 || ((uintptr_t)A.v4 & 15) != 0) return false;
+                                float* rhs32, hipStream_t s) {
+  if (((uintptr_t)rhs & 15) != 0 || ((uintptr_t)A.v4 & 15) != 0 || ((uintptr_t)rhs32 & 7) != 0)
+    return false;
   const int g = (A.n + kBlock - 1) / kBlock;
   if (!lat_dispatch(L.m, [](auto) {})) return false;
   // with phi_c the copy holds U~ only
@@ -217,13 +253,13 @@ bool launch_correct_rhs_lattice(const LatDev& L, const int32_t* node_of, const d
     constexpr int M = decltype(lat)::kM;
     if (A.phi_c) {
       if (A.chi)
-        k_correct_rhs_lat<3, M, true><<<g, kBlock, 0, s>>>(L, A, rhs);
+        k_correct_rhs_lat<3, M, true><<<g, kBlock, 0, s>>>(L, A, rhs, rhs32);
       else
-        k_correct_rhs_lat<2, M, true><<<g, kBlock, 0, s>>>(L, A, rhs);
+        k_correct_rhs_lat<2, M, true><<<g, kBlock, 0, s>>>(L, A, rhs, rhs32);
     } else if (A.chi) {
-      k_correct_rhs_lat<3, M, false><<<g, kBlock, 0, s>>>(L, A, rhs);
+      k_correct_rhs_lat<3, M, false><<<g, kBlock, 0, s>>>(L, A, rhs, rhs32);
     } else {
-      k_correct_rhs_lat<2, M, false><<<g, kBlock, 0, s>>>(L, A, rhs);
+      k_correct_rhs_lat<2, M, false><<<g, kBlock, 0, s>>>(L, A, rhs, rhs32);
     }
   });
 }
@@ -236,10 +272,13 @@ int cheb_iterations(double tol) {
   return m < 1 ? 1 : m;
 }
 
-double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
-                    double* const x[3], int iters, hipStream_t s,
-                    hipEvent_t* (*timer)(void*, int), void* tctx) {
-  // the kernel moves its block ranges as 16-byte pieces
+namespace {
+
+// The solve of launch_cheb for iterates stored as T.
+template <typename T>
+T* cheb_solve(const LatDev& L, int32_t n, const T* b, int nr, T* const x[3], int iters,
+              hipStream_t s, hipEvent_t* (*timer)(void*, int), void* tctx) {
+  // the kernels move their block ranges as 16-byte pieces
   const uintptr_t align = (uintptr_t)b | (uintptr_t)x[0] | (uintptr_t)x[1] | (uintptr_t)x[2];
   if ((align & 15) != 0 || !lat_dispatch(L.m, [](auto) {})) return nullptr;
   const double lo = 0.5, hi = 2.0;
@@ -261,25 +300,26 @@ double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
   auto single = [&](int k, int32_t lbase, double ca, double cb) {
     const int g = (n - lbase + kBlock - 1) / kBlock;
     if (g <= 0) return;
-    double* xk = x[k % 3];
-    const double* xkm = x[(k + 2) % 3];
-    double* xn = x[(k + 1) % 3];
+    T* xk = x[k % 3];
+    const T* xkm = x[(k + 2) % 3];
+    T* xn = x[(k + 1) % 3];
     hipEvent_t* ev = (timer && k > 0) ? timer(tctx, kChebTimedSingle) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
     lat_dispatch(L.m, [&](auto lat) {
       constexpr int M = decltype(lat)::kM;
       if (nr == 3)
-        k_cheb_lattice<3, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
+        k_cheb_lattice<T, 3, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
       else
-        k_cheb_lattice<2, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
+        k_cheb_lattice<T, 2, M><<<g, kBlock, 0, s>>>(L, n, lbase, b, xk, xkm, xn, ca, cb, k == 0);
     });
     if (ev) (void)hipEventRecord(ev[1], s);
   };
-  // steps in pairs on lattice size 8: edge and vertex nodes (from the even
-  // node at or below EB), the interior two steps at once, edge and vertex
-  // nodes again
+  // steps in pairs on lattice size 8: edge and vertex nodes (from the node
+  // at or below EB with an index divisible by 4, so that block ranges start
+  // 16-byte aligned), the interior two steps at once, edge and vertex nodes
+  // again
   const bool pairs = L.m == kCh2M && L.nT > 0 && L.EB == L.nT * kCh2NI;
-  const int32_t lb = L.EB & ~1;
+  const int32_t lb = L.EB & ~3;
   const int gp = (L.nT + kCh2Tris - 1) / kCh2Tris;
   double ca, cb;
   coef(0, ca, cb);
@@ -294,19 +334,57 @@ double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
     double ca2, cb2;
     coef(k + 1, ca2, cb2);
     single(k, lb, ca, cb);
-    const Cheb2Args A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
-                      ca, cb, ca2, cb2};
+    const Cheb2Args<T> A{n, b, x[(k + 2) % 3], x[k % 3], x[(k + 1) % 3], x[(k + 2) % 3],
+                         ca, cb, ca2, cb2};
     hipEvent_t* ev = timer ? timer(tctx, kChebTimedPair) : nullptr;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (nr == 3)
-      k_cheb_pair<3><<<gp, kCh2Threads, 0, s>>>(L, A);
+      k_cheb_pair<T, 3><<<gp, kCh2Threads, 0, s>>>(L, A);
     else
-      k_cheb_pair<2><<<gp, kCh2Threads, 0, s>>>(L, A);
+      k_cheb_pair<T, 2><<<gp, kCh2Threads, 0, s>>>(L, A);
     if (ev) (void)hipEventRecord(ev[1], s);
     single(k + 1, lb, ca2, cb2);
     k += 2;
   }
   return x[iters % 3];
+}
+
+}  // namespace
+
+double* launch_cheb(const LatDev& L, int32_t n, const double* b, int nr,
+                    double* const x[3], int iters, hipStream_t s,
+                    hipEvent_t* (*timer)(void*, int), void* tctx) {
+  return cheb_solve<double>(L, n, b, nr, x, iters, s, timer, tctx);
+}
+
+bool launch_cheb_mixed(const LatDev& L, int32_t n, const double* b, int nr, float* const y[5],
+                       int iters, hipStream_t s, hipEvent_t* (*timer)(void*, int), void* tctx,
+                       const float** d1, const float** d2) {
+  if (!lat_dispatch(L.m, [](auto) {})) return false;
+  // first inner solve: M d1 = b (float copy in y[3])
+  float* const x1[3] = {y[0], y[1], y[2]};
+  float* r1 = cheb_solve<float>(L, n, y[3], nr, x1, iters, s, timer, tctx);
+  if (!r1) return false;
+  // refinement residual r = b - M d1 over b's float copy
+  const int g = (n + kBlock - 1) / kBlock;
+  lat_dispatch(L.m, [&](auto lat) {
+    constexpr int M = decltype(lat)::kM;
+    if (nr == 3)
+      k_mass_resid<3, M><<<g, kBlock, 0, s>>>(L, n, b, r1, y[3]);
+    else
+      k_mass_resid<2, M><<<g, kBlock, 0, s>>>(L, n, b, r1, y[3]);
+  });
+  // second inner solve M d2 = r, in the buffers d1 does not occupy
+  float* x2[3];
+  int j = 0;
+  for (int k = 0; k < 3; ++k)
+    if (y[k] != r1) x2[j++] = y[k];
+  x2[2] = y[4];
+  float* r2 = cheb_solve<float>(L, n, y[3], nr, x2, iters, s, timer, tctx);
+  if (!r2) return false;
+  *d1 = r1;
+  *d2 = r2;
+  return true;
 }
 
 }  // namespace cgp

@@ -56,7 +56,7 @@ class CGP:
         prec = {"fp64": N.CGP_FP64, "mixed": N.CGP_MIXED}[precision]
         rmode = {"galerkin": N.CGP_RESTRICT_GALERKIN, "inject": N.CGP_RESTRICT_INJECT}[restrict]
         mmode = {"consistent": N.CGP_MASS_CONSISTENT, "lumped_p": N.CGP_MASS_LUMPED_P,
-                 "lumped": N.CGP_MASS_LUMPED}[mass]
+                 "lumped": N.CGP_MASS_LUMPED, "mixed": N.CGP_MASS_CONSISTENT_MIXED}[mass]
         pmode = {"jacobi": N.CGP_PRECOND_JACOBI, "ndchol": N.CGP_PRECOND_NDCHOL,
                  "jacobi_s4": N.CGP_PRECOND_JACOBI_S4}[precond]
         smode = {"incremental": N.CGP_SCHEME_INCREMENTAL,

@@ -34,12 +34,17 @@ def np_(t):
 
 
 def make(w, **kw):
+    """The library's solver for workload w (keyword overrides, e.g. the
+    mixed-precision mass solves, which the oracle -- always FP64 -- does not
+    take) and the oracle of w."""
     print(f"\n[case] {w.name} coarse_n={w.coarse_n} k={w.levels} chi={w.chi} "
           f"prec={w.precision} restrict={w.restrict} {kw}", flush=True)
-    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, chi=w.chi,
-            precision="fp64" if w.precision == 0 else "mixed", restrict=w.restrict,
-            pcg_tol=w.pcg_tol, inner_tol=w.inner_tol, mom_tol=w.mom_tol, mass_tol=w.mass_tol,
-            max_iter=w.max_iter, mass=w.mass, precond=w.precond, scheme=w.scheme, **kw)
+    args = dict(chi=w.chi, precision="fp64" if w.precision == 0 else "mixed",
+                restrict=w.restrict, pcg_tol=w.pcg_tol, inner_tol=w.inner_tol,
+                mom_tol=w.mom_tol, mass_tol=w.mass_tol, max_iter=w.max_iter, mass=w.mass,
+                precond=w.precond, scheme=w.scheme)
+    args.update(kw)
+    g = CGP(w.coarse_mesh(), w.levels, w.dt, w.nu, **args)
     o = build_oracle(w)
     return g, o
 
@@ -141,10 +146,14 @@ def test_pcg_parity(name, wf):
     assert rel(np_(phi_g), phi_o) <= TOL64
 
 
+@pytest.mark.parametrize("mass", ["consistent", "mixed"])
 @pytest.mark.parametrize("name,wf", CASES, ids=[c[0] for c in CASES])
-def test_correct_parity(name, wf):
+def test_correct_parity(name, wf, mass):
+    """Eqs. 25-26 against the oracle's CG solves to 1e-10, with the FP64
+    Chebyshev mass solves and with their mixed-precision form (two
+    float-stored solves of 15 steps around an FP64 residual)."""
     w = wf()
-    g, o = make(w)
+    g, o = make(w, mass=mass)
     rng = np.random.default_rng(5)
     Ut = rng.standard_normal((2, o.nf))
     Ut[:, o.dir] = w.dirichlet_values(o.fine_xy[o.dir], w.dt)
@@ -159,11 +168,13 @@ def test_correct_parity(name, wf):
     # the library solves the mass systems by Chebyshev iteration (fixed count
     # from mass_tol); the oracle by CG -- both to 1e-12
     assert st[0]["iters"] == st[1]["iters"] >= 20 and st[0]["rel_res"] <= 1e-12
+    if mass == "mixed":
+        assert st[0]["iters"] == 30 and st[0]["outer_iters"] == 2
 
 
 # ----------------------------------------------------------------- whole steps
-def run_both(w, steps, seed=None):
-    g, o = make(w)
+def run_both(w, steps, seed=None, **kw):
+    g, o = make(w, **kw)
     Um, U0, P0 = start(w, o, g, seed)
     so = o.initial_state(Um, U0, P0)
     sg = g.new_state(Um, U0, P0)
@@ -210,6 +221,28 @@ def test_step_trajectories(name, wf, steps):
     print(f"[result] {name}: GPU vs oracle {worst:.3e}, oracle self-sensitivity {sens:.3e}, "
           f"bound {bound:.3e}", flush=True)
     assert worst <= bound, (worst, sens)
+
+
+@pytest.mark.parametrize("name,wf,steps", [
+    ("tg33_k1", lambda: get_workload("tg33_k1"), 100),
+    ("cavity_k3_chi0", lambda: cavity(9, 3, chi=0), 10),
+    ("channel_k1_chi1", lambda: channel(1, 0.05, chi=1), 10),
+    ("tg_k3_ragged_chi1", lambda: tg(6, 3, chi=1), 10),
+])
+def test_step_trajectories_mixed_mass(name, wf, steps):
+    """Trajectories with the mixed-precision mass solves against the FP64
+    oracle: within 1e-10, or 10x the oracle's own rounding sensitivity where
+    the trajectory is ill-conditioned."""
+    w = wf()
+    _, _, _, _, worst = run_both(w, steps, mass="mixed")
+    bound = TOL64
+    if worst > bound:
+        sens = oracle_sensitivity(w, steps)
+        bound = sensitivity_bound(sens)
+        print(f"[result] {name}: oracle self-sensitivity {sens:.3e}", flush=True)
+    print(f"[result] {name} (mixed mass): GPU vs oracle {worst:.3e}, bound {bound:.3e}",
+          flush=True)
+    assert worst <= bound, worst
 
 
 def test_step_matches_composed_calls():

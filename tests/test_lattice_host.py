@@ -7,6 +7,7 @@ import os
 
 import numpy as np
 import pytest
+from scipy.sparse.linalg import spsolve
 
 from oracle.fem import Operators
 from oracle.hierarchy import Hierarchy
@@ -125,11 +126,11 @@ def test_cheb_pairs_match_step_by_step(N, name, meshf, nr):
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
 
-        def lib_solve(iters, pairs):
+        def lib_solve(iters, pairs, mixed=0):
             x = np.empty((n, nr))
             rc = g.lib.cgp_lattice_cheb_solve_host(
                 g.ctx, rp.ctypes.data_as(ip), col.ctypes.data_as(ip), val.ctypes.data_as(dp),
-                nr, b.ctypes.data_as(dp), iters, pairs, x.ctypes.data_as(dp))
+                nr, b.ctypes.data_as(dp), iters, pairs, mixed, x.ctypes.data_as(dp))
             assert rc == 0, g.lib.cgp_last_error()
             return x
 
@@ -150,6 +151,23 @@ def test_cheb_pairs_match_step_by_step(N, name, meshf, nr):
             # rounding: the stencil sums in another order than the CSR product
             assert err < 1e-13
             assert np.all(got[mask] == 0.0)
+
+        # the mixed-precision form (two float-stored solves of 15 steps, the
+        # FP64 residual of the first as the second's right-hand side) against
+        # the exact solution; 27 FP64 steps for comparison
+        free = ~mask
+        exact = np.zeros((n, nr))
+        for d in range(nr):
+            f = free[:, d]
+            exact[f, d] = spsolve(M[f][:, f].tocsc(), b[f, d])
+        scale = np.abs(exact).max()
+        mix = lib_solve(15, 1, 1)
+        assert np.array_equal(mix, lib_solve(15, 0, 1)), "mixed: pairs differ from single steps"
+        e_mix = np.abs(mix - exact).max() / scale
+        e64 = np.abs(lib_solve(27, 1) - exact).max() / scale
+        print(f"[cheb mixed] {name}: vs exact {e_mix:.1e} (FP64, 27 steps: {e64:.1e})")
+        assert np.all(mix[mask] == 0.0)
+        assert e_mix < 1e-11 and e64 < 1e-11
     finally:
         g.close()
 
@@ -165,7 +183,7 @@ def test_cheb_solve_host_rejects_other_lattice_sizes(N):
         i = np.zeros(g.nc + 1, np.int32)
         rc = g.lib.cgp_lattice_cheb_solve_host(
             g.ctx, i.ctypes.data_as(ip), i.ctypes.data_as(ip), z.ctypes.data_as(dp), 3,
-            z.ctypes.data_as(dp), 5, 1, z.ctypes.data_as(dp))
+            z.ctypes.data_as(dp), 5, 1, 0, z.ctypes.data_as(dp))
         assert rc != 0 and b"lattice size 8" in g.lib.cgp_last_error()
     finally:
         g.close()

@@ -130,7 +130,7 @@ def test_mesh_errors(lib):
     assert _create(lib, base, 4)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, dt=0.0)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, chi=2)[0] == N.CGP_ERR_INVALID
-    assert _create(lib, base, 1, mass_mode=3)[0] == N.CGP_ERR_INVALID
+    assert _create(lib, base, 1, mass_mode=4)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, scheme=2)[0] == N.CGP_ERR_INVALID
     assert _create(lib, base, 1, scheme=1, chi=1)[0] == N.CGP_ERR_INVALID
     assert b"rotational" in lib.cgp_last_error()
