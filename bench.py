@@ -21,24 +21,29 @@ run over the same trajectory:
                  (no pressure in the momentum equation, P = Phi_f; chi = 0)
   ndchol_mixed   FP64 iterative refinement around FP32 solves with the
                  factor (FP32 storage and accumulation), previous increment
+  ndchol_mass32  ndchol_fp64 with the consistent mass solves as FP64
+                 refinement around two float-stored Chebyshev solves
   learned_mixed_ndchol  the same from the guarded learned guess
 and, for Taylor-Green, each form's error against the exact solution.
 The network is first trained on the GPU, with the library's own kernels, on
 (b, phi) pairs of plain runs of phase-shifted Taylor-Green flows (other
 trajectories than the timed one).  `value` is the throughput in fine
 DOF * steps / s (DOF = 3 N_f: u, v, p) of the step with the FP64 coarse
-solve preconditioned by the nested-dissection factor (ndchol_fp64; the
-problem statement of this workload names no preconditioner; --main-form
-picks another form), which matches the FP64 oracle with an exact coarse
-solve to 1e-10; the other forms (which agree with it to the
+solve preconditioned by the nested-dissection factor and the consistent
+mass solves as FP64 refinement around float-stored Chebyshev solves
+(ndchol_mass32; every operation in FP64, the mass iterates stored as float;
+the problem statement of this workload names no preconditioner;
+--main-form picks another form), which matches the FP64 oracle with an
+exact coarse solve to 1e-10; the other forms (which agree with it to the
 solver tolerance), the coarse-solve time to tolerance of each guess on this
 workload and on the 257 x 257 lid-driven cavity with a 129 x 129 pressure
 mesh (the learned guess's own workload: trained on lid speeds U[0.5, 1.5],
 evaluated on a fresh U = 1 run), the roofline position of the dominant
 kernel (HIP events over the timed region), the CPU oracle timed on a bounded
 sample (the first --parity-steps steps, configured like the main form), the
-parity of the main form (and of the mixed form with the factor) against that
-oracle prefix at every step and of every form's first step,
+parity of the main form (and of the FP64, s-step and mixed forms of the
+same oracle configuration) against that oracle prefix at every step and of
+every form's first step,
 and the other configurations (33 x 33 Taylor-Green, the 257 x 257 cavity at
 k = 0..3 in both schemes, plain FP64 and mixed, the channel with the
 cylinder, mixed and FP64), each timed and checked against the oracle, are
@@ -68,19 +73,23 @@ HBM_PEAK_GBS = 8000.0
 # nnz z, right-hand sides nr, coarse triangles t, edges e, vertices v, levels k.
 #  mass_spmv:   one Chebyshev step of the fused mass solves after the first.
 #               Lattice size 8 (k = 3): over the coarse-edge and vertex nodes
-#               (from the even node at or below 21 t): per node and rhs b,
-#               x_{k-1}, x_k and the new iterate (32 B), a Dirichlet flag byte;
-#               the values one step inside every coarse triangle along its
-#               edges (the 15 ring nodes, 8 B per rhs); per coarse edge its
-#               ends and triangles (16 B); per coarse triangle its area,
-#               vertices and edges (32 B); the coarse-vertex rows (2E + V
-#               entries of 12 B: value, lattice column).  Other sizes: over all
-#               nodes, with the gathered iterate counted once
+#               (from the node at or below 21 t with an index divisible by 4):
+#               per node and rhs b, x_{k-1}, x_k and the new iterate (4
+#               values), a Dirichlet flag byte; the values one step inside
+#               every coarse triangle along its edges (the 15 ring nodes, one
+#               value per rhs); per coarse edge its ends and triangles (16 B);
+#               per coarse triangle its area, vertices and edges (32 B); the
+#               coarse-vertex rows (2E + V entries of 12 B: FP64 value, lattice
+#               column).  Other sizes: over all nodes, with the gathered
+#               iterate counted once
 #  mass_pair:   lattice size 8: two Chebyshev steps on the interior nodes
 #               (21 per coarse triangle): per node and rhs b, x_{k-1}, x_k read
-#               and x_{k+1}, x_{k+2} written (40 B), a flag byte; x_k and
-#               x_{k+1} at the 7 inner nodes of every coarse edge (16 B per
+#               and x_{k+1}, x_{k+2} written (5 values), a flag byte; x_k and
+#               x_{k+1} at the 7 inner nodes of every coarse edge (2 values per
 #               rhs); per coarse triangle its area, vertices and edges (32 B)
+#  mass_spmv32, mass_pair32: the same kernels with the iterates and right-
+#               hand sides stored as float (the mixed-precision mass solves):
+#               4-byte values instead of 8
 #  mom_spmv:    BiCGSTAB v = A p^ (2 rhs): p^ read, r^ read, v written (the
 #               average includes the launches queued past convergence, which
 #               return at once: a bound, not a bandwidth figure)
@@ -88,17 +97,22 @@ HBM_PEAK_GBS = 8000.0
 #               x, p, r, w, s written
 
 
-def _mass_spmv_bytes(n, z, nr, t, e, v, k):
+def _mass_spmv_bytes(n, z, nr, t, e, v, k, vb=8):
     if k != 3:
-        return 32 * nr * n + n + 32 * t + 16 * e + 16 * (2 * e + v) + 4 * v
-    rng = n - ((21 * t) & ~1)
-    return 32 * nr * rng + rng + 8 * nr * 15 * t + 16 * e + 32 * t + 12 * (2 * e + v)
+        return 4 * vb * nr * n + n + 32 * t + 16 * e + 16 * (2 * e + v) + 4 * v
+    rng = n - ((21 * t) & ~3)
+    return 4 * vb * nr * rng + rng + vb * nr * 15 * t + 16 * e + 32 * t + 12 * (2 * e + v)
+
+
+def _mass_pair_bytes(n, z, nr, t, e, v, k, vb=8):
+    return 21 * t * (5 * vb * nr + 1) + 7 * e * 2 * vb * nr + 32 * t
 
 
 KERNELS = {
     "mass_spmv": (1, _mass_spmv_bytes),
-    "mass_pair": (5, lambda n, z, nr, t, e, v, k: 21 * t * (40 * nr + 1) + 7 * e * 16 * nr
-                  + 32 * t),
+    "mass_pair": (5, _mass_pair_bytes),
+    "mass_spmv32": (1, lambda *a: _mass_spmv_bytes(*a, vb=4)),
+    "mass_pair32": (5, lambda *a: _mass_pair_bytes(*a, vb=4)),
     "mom_spmv": (2, lambda n, z, nr, t, e, v, k: 12 * z + 4 * (n + 1) + 3 * 2 * 8 * n),
     "coarse_spmv": (3, lambda n, z, nr, t, e, v, k: 12 * z + 4 * (n + 1) + 11 * 8 * n),
 }
@@ -115,6 +129,10 @@ TRAFFIC_RECORDS = {
                                       ("mass.hip", "lattice.hpp", "cheb2.hpp")),
     ("tg2049_k3_fp64", "mass_pair"): ("k_cheb_pair3_tg2049_k3_fp64_traffic.md",
                                       ("mass.hip", "lattice.hpp", "cheb2.hpp")),
+    ("tg2049_k3_fp64", "mass_spmv32"): ("k_cheb_lattice3_f32_tg2049_k3_fp64_traffic.md",
+                                        ("mass.hip", "lattice.hpp", "cheb2.hpp")),
+    ("tg2049_k3_fp64", "mass_pair32"): ("k_cheb_pair3_f32_tg2049_k3_fp64_traffic.md",
+                                        ("mass.hip", "lattice.hpp", "cheb2.hpp")),
     ("sq2049_k0_pcg", "coarse_spmv"): ("k_pcg_iter_sq2049_k0_fp64_traffic.md",
                                        ("kernels.hip",)),
 }
@@ -153,6 +171,7 @@ def rel(a, b):
 
 # oracle configuration (mass mode, coarse solver, scheme) matching each form
 FORM_MODES = {"ndchol_mixed": ("consistent", "exact", "incremental"),
+              "ndchol_mass32": ("consistent", "exact", "incremental"),
               "learned_mixed_ndchol": ("consistent", "exact", "incremental"),
               "lumped_p_fp64": ("lumped_p", "pcg", "incremental"),
               "lumped_fp64": ("lumped", "pcg", "incremental"),
@@ -397,6 +416,18 @@ def config_legs(torch, which, steps, warmup, with_oracle):
     return legs
 
 
+# forms whose consistent mass solves store their iterates as float
+MASS32_FORMS = ("ndchol_mass32",)
+
+
+def main_form_of(args, forms):
+    """The form whose throughput is `value`: --main-form if it runs, else
+    plain_fp64 if it runs, else the first."""
+    if args.main_form in forms:
+        return args.main_form
+    return "plain_fp64" if "plain_fp64" in forms else forms[0]
+
+
 def run_form(torch, g, uD, fields, warmup, steps, theta=None, kid=0):
     """W untimed steps, then K timed steps (synchronised on both sides, the
     selected kernel bracketed by HIP events), then one untimed step with
@@ -450,8 +481,8 @@ def main():
     ap.add_argument("--forms",
                     default="plain_fp64,learned_mixed,learned_fp64,lumped_p_fp64,lumped_fp64,"
                             "ndchol_fp64,ndchol_lumped_fp64,ncgp_fp64,s4_fp64,ndchol_mixed,"
-                            "learned_mixed_ndchol")
-    ap.add_argument("--main-form", default="ndchol_fp64",
+                            "learned_mixed_ndchol,ndchol_mass32")
+    ap.add_argument("--main-form", default="ndchol_mass32",
                     help="the form whose throughput is `value` (if it runs; else plain_fp64)")
     ap.add_argument("--no-learned", action="store_true",
                     help="the plain FP64 forms only (Jacobi-PCG, standard and s-step): no training, no learned forms or legs")
@@ -514,6 +545,7 @@ def main():
     for form, mass, pre in (("lumped_p_fp64", "lumped_p", "jacobi"),
                             ("lumped_fp64", "lumped", "jacobi"),
                             ("ndchol_fp64", "consistent", "ndchol"),
+                            ("ndchol_mass32", "mixed", "ndchol"),
                             ("ndchol_lumped_fp64", "lumped", "ndchol"),
                             ("s4_fp64", "consistent", "jacobi_s4")):
         if form in forms:
@@ -545,7 +577,7 @@ def main():
     thetas = {"plain_fp64": None, "learned_mixed": theta, "learned_fp64": theta,
               "lumped_p_fp64": None, "lumped_fp64": None, "ndchol_fp64": None,
               "ndchol_lumped_fp64": None, "ncgp_fp64": None, "s4_fp64": None,
-              "ndchol_mixed": None, "learned_mixed_ndchol": theta}
+              "ndchol_mixed": None, "learned_mixed_ndchol": theta, "ndchol_mass32": None}
 
     Um, U0, P0 = w.initial_fields(g.fine_xy)
     xyd = g.fine_xy[g.dirichlet_nodes]
@@ -561,16 +593,21 @@ def main():
         first[form] = (s1.U.cpu().numpy(), s1.P.cpu().numpy())
         del s1
 
-    kid = KERNELS[args.timed_kernel][0]
-    main_form = args.main_form if args.main_form in forms else (
-        "plain_fp64" if "plain_fp64" in forms else forms[0])
+    # the mass kernels of a form with float-stored mass iterates
+    timed = args.timed_kernel
+    mass32 = main_form_of(args, forms) in MASS32_FORMS
+    if mass32 and timed in ("mass_spmv", "mass_pair"):
+        timed += "32"
+    kid = KERNELS[timed][0]
+    main_form = main_form_of(args, forms)
     # the main form and the plain step over a prefix of the trajectory, every
     # step kept, for the parity against the oracle over the same prefix
     nprefix = max(1, min(args.parity_steps, nsteps))
     prefixes = {}
     if not args.no_cpu_baseline:
         for form in forms:
-            if form != main_form and (form not in ("ndchol_mixed", "s4_fp64") or
+            if form != main_form and (form not in ("ndchol_mixed", "s4_fp64", "ndchol_mass32",
+                                                   "ndchol_fp64") or
                                       FORM_MODES.get(form) != FORM_MODES.get(main_form)):
                 continue
             sp = solvers[form].new_state(Um, U0, P0)
@@ -582,9 +619,10 @@ def main():
             del sp
     results, finals = {}, {}
     for form in forms:
+        # the throughput runs carry no per-launch events: those cost host time
+        # at every timed launch (the kernel timing runs separately below)
         el, kms, nl, st, state = run_form(torch, solvers[form], uD, (Um, U0, P0),
-                                          args.warmup, args.steps, thetas[form],
-                                          kid if form == main_form else 0)
+                                          args.warmup, args.steps, thetas[form], 0)
         results[form] = {"value": 3 * g.nf * args.steps / el,
                          "ms_per_step": 1e3 * el / args.steps, "last_step": st}
         finals[form] = (state.U.cpu().numpy(), state.P.cpu().numpy())
@@ -595,8 +633,6 @@ def main():
             results[form]["err_vs_exact"] = {
                 "u": rel(finals[form][0], Ue),
                 "p": rel(Pf - Pf.mean(), Pe - Pe.mean())}
-        if form == main_form:
-            kernel = (kms, nl)
         log(f"[bench] {form}: {args.steps} steps in {el:.3f} s; last step {st}")
         del state
     ref = finals.get("plain_fp64")
@@ -628,15 +664,21 @@ def main():
                 "ms_per_step": kms / args.steps,
                 "measured_gbs": (traffic / avg_s / 1e9) if (traffic and nlaunch) else None}
 
-    roofs = [kernel_roofline(args.timed_kernel, *kernel)]
-    if args.timed_kernel == "mass_spmv" and w.levels == 3:
+    # the timed kernel: HIP events around each of its launches, in a run of
+    # its own over the same steps
+    _, kms1, nl1, _, st1 = run_form(torch, solvers[main_form], uD, (Um, U0, P0), args.warmup,
+                                    args.steps, thetas[main_form], kid)
+    del st1
+    roofs = [kernel_roofline(timed, kms1, nl1)]
+    pair = "mass_pair32" if mass32 else "mass_pair"
+    if timed in ("mass_spmv", "mass_spmv32") and w.levels == 3:
         # the interior two-step kernel of the same solves, timed in a run of
         # its own over the same steps
         el2, kms2, nl2, _, st2 = run_form(torch, solvers[main_form], uD, (Um, U0, P0),
                                           args.warmup, args.steps, thetas[main_form],
-                                          KERNELS["mass_pair"][0])
+                                          KERNELS[pair][0])
         del st2
-        roofs.append(kernel_roofline("mass_pair", kms2, nl2))
+        roofs.append(kernel_roofline(pair, kms2, nl2))
     # the contract's object is the kernel with the most time per step
     roofs.sort(key=lambda r: -r["ms_per_step"])
     roofline = dict(roofs[0], others=roofs[1:])
@@ -726,7 +768,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "form": main_form, **sizes,
                    "levels": w.levels, "dt": w.dt, "nu": w.nu, "chi": w.chi,
-                   "restrict": w.restrict, "pcg_tol": w.pcg_tol, "mom_tol": w.mom_tol},
+                   "restrict": w.restrict, "pcg_tol": w.pcg_tol, "mom_tol": w.mom_tol,
+                   "mass_solves": ("FP64 refinement around two float-stored Chebyshev solves "
+                                   "(FP64 arithmetic)" if main_form in MASS32_FORMS
+                                   else "FP64 Chebyshev")},
         "forms": results, "roofline": roofline, "cpu_baseline": cpu,
         "parity_rel_l2": parity, "time_to_tol": ttt, "calibration": calib,
         "configs": legs,
