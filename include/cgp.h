@@ -448,7 +448,9 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const
  * no pressure term), u_dir [2][n_dirichlet], f [2][N_f] and t_nat [2][N_f]
  * (may be NULL), fills the rows of the fine nodes other than the coarse
  * vertices: aval [nnz_fine] of A = 3/2 M + dt nu K + dt N(2 U^n - U^{n-1})
- * (identity on Dirichlet rows), rhs [2][N_f] and x0 [2][N_f], every other
+ * (identity on Dirichlet rows), rhs [2][N_f], x0 [2][N_f] (the initial guess:
+ * W, the boundary values on Dirichlet rows) and r0 [2][N_f] (the initial
+ * residual rhs - A x0 that the assembly forms for BiCGSTAB), every other
  * entry NaN; rowptr [N_f + 1] and col [nnz_fine] receive the library's fine
  * CSR structure (diagonal first in each row, then the columns in increasing
  * order).  Errors: CGP_ERR_INVALID (arguments, or a context whose fine rows
@@ -456,7 +458,7 @@ int cgp_lattice_mass_apply_host(const cgp_ctx* ctx, const int32_t* rowptr, const
 int cgp_lattice_momentum_host(const cgp_ctx* ctx, const double* u_prev, const double* u,
                               const double* p, const double* u_dir, const double* f,
                               const double* t_nat, int32_t* rowptr, int32_t* col, double* aval,
-                              double* rhs, double* x0);
+                              double* rhs, double* x0, double* r0);
 
 /* Host-only check of the right-hand sides of the consistent-mass solves as
  * the library forms them on the lattice layout (fine geometry from the coarse

@@ -134,7 +134,7 @@ SIGNATURES = [
     ("cgp_lattice_mass_apply_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, _dp, _dp, _dp]),
     ("cgp_lattice_correct_rhs_host", C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp]),
     ("cgp_lattice_momentum_host", C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ip,
-                                            _dp, _dp, _dp]),
+                                            _dp, _dp, _dp, _dp]),
     ("cgp_lattice_cheb_solve_host", C.c_int, [C.c_void_p, _ip, _ip, _dp, C.c_int32, _dp,
                                               C.c_int32, C.c_int32, C.c_int32, _dp]),
     ("cgp_ndchol_solve_host", C.c_int, [C.c_int32, _ip, _ip, _dp, _dp,

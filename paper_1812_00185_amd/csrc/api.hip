@@ -479,12 +479,14 @@ int run_momentum(cgp_ctx* c, const double* u_prev, const double* u, const double
                  const double* u_dir, const double* f, const double* t_nat, double* ut,
                  cgp_solve_stats* st, hipStream_t s) {
   const cgp_problem& P = c->prob;
+  // the assembly also forms the initial residual r = b - A x0 (x0 = W, the
+  // boundary values on Dirichlet rows), so the solve starts without a product
   cgp::launch_momentum_assemble(c->F, c->dir_index, P.dt, P.nu, u_prev, u, p, u_dir, c->ndir,
-                                f, t_nat, c->Aval, c->invdA, c->rhs, ut,
+                                f, t_nat, c->Aval, c->invdA, c->rhs, ut, c->r,
                                 c->phat, c->shat, s, timer(c, CGP_K_MOM_ASSEMBLE),
                                 c->lat.mom_ok ? &c->mlat : nullptr);
   cgp::BicgVecs V{ut, c->r, c->rhat, c->p, c->v, c->phat, c->shat, c->t, c->rhs, c->invdA};
-  cgp::launch_bicg_init(c->F, c->Aval, V, c->scal, c->part, c->nb_f, s);
+  cgp::launch_bicg_start(c->nf, V, c->scal, c->part, c->nb_f, s);
   Scal out[2];
   const int last = P.mom_max_iter + 1;
   // the first chunk covers the previous solve's iterations plus the launch
@@ -1508,8 +1510,8 @@ int cgp_lattice_correct_rhs_host(const cgp_ctx* c, const double* phi_f, const do
 int cgp_lattice_momentum_host(const cgp_ctx* c, const double* u_prev, const double* u,
                               const double* p, const double* u_dir, const double* f,
                               const double* t_nat, int32_t* rowptr, int32_t* col, double* aval,
-                              double* rhs, double* x0) {
-  if (!c || !u_prev || !u || !u_dir || !rowptr || !col || !aval || !rhs || !x0)
+                              double* rhs, double* x0, double* r0) {
+  if (!c || !u_prev || !u || !u_dir || !rowptr || !col || !aval || !rhs || !x0 || !r0)
     return fail(CGP_ERR_INVALID, "null argument");
   const cgp::Lattice& L = c->lat;
   if (!L.mom_ok) return fail(CGP_ERR_INVALID, "no lattice form of the momentum rows on this context");
@@ -1522,6 +1524,7 @@ int cgp_lattice_momentum_host(const cgp_ctx* c, const double* u_prev, const doub
   std::fill_n(aval, nnz, nan);
   std::fill_n(rhs, 2 * (size_t)n, nan);
   std::fill_n(x0, 2 * (size_t)n, nan);
+  std::fill_n(r0, 2 * (size_t)n, nan);
   std::vector<double> invd(n, nan);
   // the fields of the assembly pre-pass
   const double dt = c->prob.dt;
@@ -1538,7 +1541,7 @@ int cgp_lattice_momentum_host(const cgp_ctx* c, const double* u_prev, const doub
   }
   const cgp::MomLatArgs A{n, L.nV, g.rowptr.data(), L.mslot.data(), c->mrow_h.data(),
                           c->mtri_h.data(), c->h.dir_index.data(), W.data(), R.data(), p, u_dir,
-                          c->ndir, t_nat, dt, dt * c->prob.nu, aval, invd.data(), rhs, x0};
+                          c->ndir, t_nat, dt, dt * c->prob.nu, aval, invd.data(), rhs, x0, r0};
   auto put = [&](int32_t s, double val) { aval[s] = val; };
   for (int32_t i = L.nV; i < n; ++i) {
     if (t_nat)

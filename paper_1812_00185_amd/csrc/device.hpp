@@ -71,8 +71,9 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
                               const double* t_nat, double* Aval, double* invdA, double* rhs,
-                              double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
-                              hipEvent_t* ev = nullptr, const MomLattice* ml = nullptr);
+                              double* x0, double* r0, double* scratch_w, double* scratch_r,
+                              hipStream_t s, hipEvent_t* ev = nullptr,
+                              const MomLattice* ml = nullptr);
 
 // ---------------------------------------------------------------- BiCGSTAB (2 rhs)
 struct BicgVecs {
@@ -80,8 +81,11 @@ struct BicgVecs {
   const double* b;
   const double* invd;
 };
-void launch_bicg_init(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
-                      double* part, int nb, hipStream_t s);
+// the start of the momentum BiCGSTAB: the assembly wrote r = b - A x0
+// (launch_momentum_assemble's r0); r^ = r and the partial sums of (r, r),
+// (b, b)
+void launch_bicg_start(int32_t n, const BicgVecs& V, Scal* sc, double* part, int nb,
+                       hipStream_t s);
 // `ev`, when not null, is a pair of events recorded around the SpMV kernel
 // v = A p^ (measurement hook).
 void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,

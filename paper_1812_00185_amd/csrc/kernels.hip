@@ -322,7 +322,8 @@ __device__ __forceinline__ void mom_side_rows(
     double dtnu, const double2* __restrict__ W, const double2* __restrict__ R,
     const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
     const double* __restrict__ tn, double* __restrict__ A, double* __restrict__ invdA,
-    double* __restrict__ rhs, double* __restrict__ x0, int blk, int nblk) {
+    double* __restrict__ rhs, double* __restrict__ x0, double* __restrict__ r0, int blk,
+    int nblk) {
   const int64_t n = L.n;
   const int lane = threadIdx.x % kRowLanes, rpb = kBlock / kRowLanes;
   for (int base = blk * rpb; base < row_end; base += nblk * rpb) {
@@ -341,6 +342,8 @@ __device__ __forceinline__ void mom_side_rows(
         // rows keep a zero residual and BiCGSTAB works on the free rows only
         x0[i] = gx;
         x0[n + i] = gy;
+        r0[i] = 0.0;
+        r0[n + i] = 0.0;
       }
       continue;
     }
@@ -349,8 +352,9 @@ __device__ __forceinline__ void mom_side_rows(
     const double Pi = p ? p[i] : 0.0;
     const double2 wi = W[i];
     const double wix = wi.x, wiy = wi.y;
-    // dm, dk, dn, rx, ry, gx, gy (, tx, ty: traction)
-    constexpr int NA = kTrac ? 9 : 7;
+    // dm, dk, dn, rx, ry, gx, gy (, tx, ty: traction), then (A x0)_i without
+    // the diagonal term
+    constexpr int NA = (kTrac ? 9 : 7) + 2, AX = NA - 2;
     double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
@@ -361,7 +365,7 @@ __device__ __forceinline__ void mom_side_rows(
     struct Slot {
       int j;
       int2 sd;
-      double2 pj, wj, rj, pk[2], wk[2];
+      double2 pj, wj, rj, pk[2], wk[2], xj;
       double Pj, tj[2];
     };
     const int2* side2 = reinterpret_cast<const int2*>(L.side);
@@ -373,6 +377,9 @@ __device__ __forceinline__ void mom_side_rows(
       d.pj = L.xy[j];
       d.wj = W[j];
       d.rj = R[j];
+      // the initial guess at j: W, or the boundary value on a Dirichlet row
+      const int dj = dir_index[j];
+      d.xj = dj >= 0 ? make_double2(udir[dj], udir[ndir + dj]) : d.wj;
       d.Pj = p ? p[j] : 0.0;
       d.pk[0] = L.xy[k0];
       d.wk[0] = W[k0];
@@ -406,7 +413,10 @@ __device__ __forceinline__ void mom_side_rows(
         acc[5] += g.bi * (Pj + 0.5 * Pi);
         acc[6] += g.ci * (Pj + 0.5 * Pi);
       }
-      A[s] = 1.5 * m + dtnu * kk + dt * nn;
+      const double av = 1.5 * m + dtnu * kk + dt * nn;
+      A[s] = av;
+      acc[AX] += av * d.xj.x;
+      acc[AX + 1] += av * d.xj.y;
       acc[0] += m;
       acc[1] += kk;
       acc[2] += nn;
@@ -435,6 +445,8 @@ __device__ __forceinline__ void mom_side_rows(
       rhs[n + i] = ry;
       x0[i] = wix;
       x0[n + i] = wiy;
+      r0[i] = rx - (aii * wix + acc[AX]);
+      r0[n + i] = ry - (aii * wiy + acc[AX + 1]);
     }
   }
 }
@@ -446,9 +458,9 @@ k_momentum_assemble(DLevel L, const int32_t* __restrict__ dir_index, double dt, 
                     const double* __restrict__ p, const double* __restrict__ udir, int32_t ndir,
                     const double* __restrict__ tn, double* __restrict__ A,
                     double* __restrict__ invdA, double* __restrict__ rhs,
-                    double* __restrict__ x0) {
+                    double* __restrict__ x0, double* __restrict__ r0) {
   mom_side_rows<kTrac>(L, L.n, dir_index, dt, dtnu, W, R, p, udir, ndir, tn, A, invdA, rhs, x0,
-                       blockIdx.x, gridDim.x);
+                       r0, blockIdx.x, gridDim.x);
 }
 
 // The rows of the lattice's interior and coarse-edge nodes, [A.row0, A.n),
@@ -463,7 +475,7 @@ template <bool kTrac>
 __global__ void __launch_bounds__(kBlock) k_momentum_lat(DLevel L, MomLatArgs A, int nbv) {
   if ((int)blockIdx.x < nbv) {
     mom_side_rows<kTrac>(L, A.row0, A.dir_index, A.dt, A.dtnu, A.W, A.R, A.p, A.udir, A.ndir,
-                         A.tn, A.A, A.invdA, A.rhs, A.x0, blockIdx.x, nbv);
+                         A.tn, A.A, A.invdA, A.rhs, A.x0, A.r0, blockIdx.x, nbv);
     return;
   }
   constexpr int kMaxVals = kBlock * 7;
@@ -487,27 +499,21 @@ __global__ void __launch_bounds__(kBlock) k_momentum_lat(DLevel L, MomLatArgs A,
 //   B4  half-step test (x += alpha p^ and stop) or t = A s^, partials (t, s), (t, t)
 //   B5  omega, x += alpha p^ + omega s^, r = s - omega t, partials (r, r), (r^, r)
 
+// The start: the assembly has written r = b - A x0 (x0 = W, the boundary
+// values on Dirichlet rows); r^ = r, partial sums of (r, r) and (b, b).
 __global__ void __launch_bounds__(kBlock)
-k_bicg_init(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* part) {
-  __shared__ TileStage<double> st;
-  const int64_t n = L.n;
+k_bicg_start(int32_t n32, BicgVecs V, Scal* sc, double* part) {
+  const int64_t n = n32;
   double rr[2] = {0, 0}, bb[2] = {0, 0};
-  for (int t = blockIdx.x; t < L.ntiles; t += gridDim.x) {
-    const int r0 = L.tile[t], r1 = L.tile[t + 1];
-    const int s0 = stage_tile<double, true>(st, L, A, r0, r1);
-    const int row = r0 + threadIdx.x;
-    if (row < r1) {
-      double ax[2];
-      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.x[d * n + c]; }, ax);
+  for (int64_t row = blockIdx.x * (int64_t)kBlock + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * kBlock) {
 #pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const double b = V.b[d * n + row];
-        const double r = b - ax[d];
-        V.r[d * n + row] = r;
-        V.rhat[d * n + row] = r;
-        rr[d] += r * r;
-        bb[d] += b * b;
-      }
+    for (int d = 0; d < 2; ++d) {
+      const double b = V.b[d * n + row];
+      const double r = V.r[d * n + row];
+      V.rhat[d * n + row] = r;
+      rr[d] += r * r;
+      bb[d] += b * b;
     }
   }
   const double vals[6] = {rr[0], rr[1], rr[0], rr[1], bb[0], bb[1]};
@@ -1487,8 +1493,8 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const double* u_prev, const double* u, const double* p,
                               const double* u_dir, int32_t n_dir, const double* f,
                               const double* t_nat, double* Aval, double* invdA, double* rhs,
-                              double* x0, double* scratch_w, double* scratch_r, hipStream_t s,
-                              hipEvent_t* ev, const MomLattice* ml) {
+                              double* x0, double* r0, double* scratch_w, double* scratch_r,
+                              hipStream_t s, hipEvent_t* ev, const MomLattice* ml) {
   double2* W = reinterpret_cast<double2*>(scratch_w);
   double2* R = reinterpret_cast<double2*>(scratch_r);
   if (ev) (void)hipEventRecord(ev[0], s);
@@ -1496,17 +1502,17 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
   if (!ml || ml->row0 >= L.n) {  // every row side-based
     if (t_nat)
       k_momentum_assemble<true><<<row_group_grid(L.n), kBlock, 0, s>>>(
-          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0);
+          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, t_nat, Aval, invdA, rhs, x0, r0);
     else
       k_momentum_assemble<false><<<row_group_grid(L.n), kBlock, 0, s>>>(
-          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs, x0);
+          L, dir_index, dt, dt * nu, W, R, p, u_dir, n_dir, nullptr, Aval, invdA, rhs, x0, r0);
   } else {
     // the coarse-vertex rows [0, row0) side-based, the rest on the lattice,
     // in one launch
     const int32_t row0 = ml->row0;
     const MomLatArgs A{L.n, row0, L.rowptr, ml->slot, ml->rows, ml->tris, dir_index, W, R,
                        p,   u_dir, n_dir,   t_nat,    dt,       dt * nu,  Aval,      invdA,
-                       rhs, x0};
+                       rhs, x0,    r0};
     const int nbv = (row0 + kBlock / kRowLanes - 1) / (kBlock / kRowLanes);
     const int g = nbv + (int)((L.n - row0 + kBlock - 1) / kBlock);
     if (t_nat)
@@ -1517,9 +1523,9 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 
-void launch_bicg_init(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,
-                      double* part, int nb, hipStream_t s) {
-  k_bicg_init<<<nb, kBlock, 0, s>>>(L, Aval, V, sc, part);
+void launch_bicg_start(int32_t n, const BicgVecs& V, Scal* sc, double* part, int nb,
+                       hipStream_t s) {
+  k_bicg_start<<<nb, kBlock, 0, s>>>(n, V, sc, part);
 }
 
 void launch_bicg_iter(const DLevel& L, const double* Aval, const BicgVecs& V, Scal* sc,

@@ -11,7 +11,9 @@
 //   M_ij += A_t / 12,  K_ij += (b_i b_j + c_i c_j) / (4 A_t),
 //   N_ij += (b_j, c_j) . (2 w_i + w_j + w_k) / 24,
 // the diagonal from the row sums (M_ii = sum_j M_ij, K_ii = -sum_j K_ij,
-// N_ii = -sum_j N_ij), and the right-hand side
+// N_ii = -sum_j N_ij), the initial residual rhs - A x0 of the BiCGSTAB solve
+// (x0 = W, the boundary values on Dirichlet rows) from the row's values
+// while they are in registers, and the right-hand side
 //   sum_j M_ij R_j + M_ii R_i + (dt / 6) sum_t (b_i, c_i) (P_i + P_j + P_k)
 // (R = 2 U^n - 1/2 U^{n-1} + dt F; the last term is -dt (G P)_i with
 // G = -D^T).  An interior node of T has six neighbours, each in two of the
@@ -183,6 +185,7 @@ struct MomLatArgs {
   double* invdA;
   double* rhs;                  // [2][n]
   double* x0;                   // [2][n]
+  double* r0;                   // [2][n] the initial residual rhs - A x0
 };
 
 // Accumulators of one row: per direction M, K, N; the pressure gradient sums.
@@ -296,6 +299,8 @@ CGP_HDI void mom_row(const MomLatArgs& A, int32_t i, Put put) {
     A.rhs[n + i] = gy;
     A.x0[i] = gx;
     A.x0[n + i] = gy;
+    A.r0[i] = 0.0;  // x0 holds the boundary value: no residual on this row
+    A.r0[n + i] = 0.0;
     return;
   }
   const MomRow rr = A.rows[i];
@@ -342,17 +347,23 @@ CGP_HDI void mom_row(const MomLatArgs& A, int32_t i, Put put) {
     mom_edge_side<1, kTrac>(A, rr, i, s, wi, pi, wd, pd, tx, ty);
   }
   const uint8_t* sl = A.slot + 8 * (int64_t)i;
-  double sm = 0.0, sk = 0.0, sn = 0.0, rx = 0.0, ry = 0.0;
+  double sm = 0.0, sk = 0.0, sn = 0.0, rx = 0.0, ry = 0.0, ax = 0.0, ay = 0.0;
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     if (sl[d] == kNoSlot) continue;
-    put(beg + sl[d], 1.5 * s.m[d] + A.dtnu * s.k[d] + A.dt * s.nx[d]);
+    const double av = 1.5 * s.m[d] + A.dtnu * s.k[d] + A.dt * s.nx[d];
+    put(beg + sl[d], av);
     sm += s.m[d];
     sk += s.k[d];
     sn += s.nx[d];
-    const double2 rj = A.R[rr.nb[d]];  // R only here: fewer live registers
+    const int32_t j = rr.nb[d];
+    const double2 rj = A.R[j];  // R only here: fewer live registers
     rx += s.m[d] * rj.x;
     ry += s.m[d] * rj.y;
+    // (A x0) at this row: x0 = W, the boundary value on Dirichlet rows
+    const int dj = A.dir_index[j];
+    ax += av * (dj >= 0 ? A.udir[dj] : wd[d].x);
+    ay += av * (dj >= 0 ? A.udir[A.ndir + dj] : wd[d].y);
   }
   const double2 ri = A.R[i];
   const double aii = 1.5 * sm - A.dtnu * sk - A.dt * sn;
@@ -368,6 +379,8 @@ CGP_HDI void mom_row(const MomLatArgs& A, int32_t i, Put put) {
   A.rhs[n + i] = ry;
   A.x0[i] = wi.x;
   A.x0[n + i] = wi.y;
+  A.r0[i] = rx - (aii * wi.x + ax);
+  A.r0[n + i] = ry - (aii * wi.y + ay);
 }
 
 }  // namespace cgp

@@ -261,7 +261,7 @@ def test_lattice_momentum_rows_match_assembled(N, name, meshf, k, trac):
     """The momentum rows of Eq. 21 as the library assembles them on the
     lattice layout (fine-triangle coefficients from the coarse triangles, no
     coordinate, side or column index read) against the oracle's assembled
-    matrix, right-hand side and initial guess, on every row of a fine node
+    matrix, right-hand side, initial guess and initial residual, on every row of a fine node
     other than the coarse vertices (those keep the side-based assembly):
     random fields, pressure, forcing, Dirichlet values and, on natural
     boundaries, traction."""
@@ -290,13 +290,14 @@ def test_lattice_momentum_rows_match_assembled(N, name, meshf, k, trac):
         aval = np.empty(nnz)
         rhs = np.empty((2, n))
         x0 = np.empty((2, n))
+        r0 = np.empty((2, n))
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         arr = lambda a: None if a is None else np.ascontiguousarray(a).ctypes.data_as(dp)
         rc = g.lib.cgp_lattice_momentum_host(
             g.ctx, arr(Up), arr(U), arr(P), arr(uD), arr(F), arr(T), rowptr.ctypes.data_as(ip),
             col.ctypes.data_as(ip), aval.ctypes.data_as(dp), rhs.ctypes.data_as(dp),
-            x0.ctypes.data_as(dp))
+            x0.ctypes.data_as(dp), r0.ctypes.data_as(dp))
         assert rc == 0, g.lib.cgp_last_error()
         rows = np.arange(g.nc, n)
         assert rows.size > 0
@@ -314,8 +315,14 @@ def test_lattice_momentum_rows_match_assembled(N, name, meshf, k, trac):
         assert np.array_equal(rhs[:, rows[dirrow[rows]]], rhs_o[:, rows[dirrow[rows]]])
         ea = np.abs(aval[lo:hi][fr] - ref[fr]).max() / np.abs(ref[fr]).max()
         er = np.abs(rhs[:, rf] - rhs_o[:, rf]).max() / np.abs(rhs_o[:, rf]).max()
-        print(f"[mom rows] {name}: N_f={n}, free rows {rf.size}: A {ea:.1e} rhs {er:.1e}")
-        assert ea < 1e-13 and er < 1e-13
+        # the initial residual the assembly forms for BiCGSTAB: rhs - A x0 with
+        # the oracle's matrix and guess (zero on Dirichlet rows)
+        res_o = np.stack([rhs_o[d] - A @ x0_o[d] for d in range(2)])
+        assert np.all(r0[:, rows[dirrow[rows]]] == 0.0)
+        e0 = np.abs(r0[:, rf] - res_o[:, rf]).max() / np.abs(rhs_o[:, rf]).max()
+        print(f"[mom rows] {name}: N_f={n}, free rows {rf.size}: A {ea:.1e} rhs {er:.1e} "
+              f"r0 {e0:.1e}")
+        assert ea < 1e-13 and er < 1e-13 and e0 < 1e-13
         # the coarse-vertex rows are left to the side-based kernel
         assert np.all(np.isnan(aval[:lo])) and np.all(np.isnan(rhs[:, :g.nc]))
     finally:
