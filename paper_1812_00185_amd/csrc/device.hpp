@@ -76,6 +76,9 @@ void launch_momentum_assemble(const DLevel& L, const int32_t* dir_index, double 
                               const MomLattice* ml = nullptr);
 
 // ---------------------------------------------------------------- BiCGSTAB (2 rhs)
+// x, r, rhat, p, v, t, b: [2][n] (one right-hand side after the other);
+// phat = D^-1 p and shat = D^-1 s: [n][2] (the two right-hand sides
+// interleaved), so that the products gather both with one 16-byte load
 struct BicgVecs {
   double *x, *r, *rhat, *p, *v, *phat, *shat, *t;
   const double* b;

@@ -188,6 +188,32 @@ __device__ __forceinline__ void tile_row(const TileStage<T>& st, const DLevel& L
   tile_row_range<T, NR>(st, L.rowptr[row] - s0, L.rowptr[row + 1] - s0, g, acc);
 }
 
+// tile_row for two right-hand sides stored interleaved ([n][2]): one
+// 16-byte gather per nonzero
+__device__ __forceinline__ void tile_row2(const TileStage<double>& st, const DLevel& L, int s0,
+                                          int row, const double2* __restrict__ x2,
+                                          double (&acc)[2]) {
+  const int a = L.rowptr[row] - s0, b = L.rowptr[row + 1] - s0;
+  acc[0] = acc[1] = 0.0;
+  for (int s = a; s < b; s += kRowBatch) {
+    double v[kRowBatch];
+    double2 x[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      if (s + u < b) {
+        v[u] = st.val[s + u];
+        x[u] = x2[st.col[s + u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+      if (s + u < b) {
+        acc[0] += v[u] * x[u].x;
+        acc[1] += v[u] * x[u].y;
+      }
+  }
+}
+
 struct SideGeo {
   double area, bi, ci, bj, cj;
 };
@@ -498,6 +524,8 @@ __global__ void __launch_bounds__(kBlock) k_momentum_lat(DLevel L, MomLatArgs A,
 //   B3  alpha, s = r - alpha v (in r),    s^ = D^-1 s, partial (s, s)
 //   B4  half-step test (x += alpha p^ and stop) or t = A s^, partials (t, s), (t, t)
 //   B5  omega, x += alpha p^ + omega s^, r = s - omega t, partials (r, r), (r^, r)
+// p^ and s^, the vectors the products gather, hold the two right-hand sides
+// interleaved ([n][2]); the others hold them one after the other ([2][n]).
 
 // The start: the assembly has written r = b - A x0 (x0 = W, the boundary
 // values on Dirichlet rows); r^ = r, partial sums of (r, r) and (b, b).
@@ -570,7 +598,7 @@ k_bicg_b1(int32_t n32, BicgVecs V, Scal* sc, const double* part, int nb, int it,
       const double pv = it == 1 ? V.r[d * n + i]
                                 : V.r[d * n + i] + beta[d] * (V.p[d * n + i] - omega[d] * V.v[d * n + i]);
       V.p[d * n + i] = pv;
-      V.phat[d * n + i] = dinv * pv;
+      V.phat[2 * i + d] = dinv * pv;
     }
   }
 }
@@ -588,7 +616,7 @@ k_bicg_b2(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
     const int row = r0 + threadIdx.x;
     if (row < r1) {
       double av[2];
-      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.phat[d * n + c]; }, av);
+      tile_row2(st, L, s0, row, reinterpret_cast<const double2*>(V.phat), av);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         V.v[d * n + row] = av[d];
@@ -621,7 +649,7 @@ k_bicg_b3(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp)
       if (!act[d]) continue;
       const double s = V.r[d * n + i] - alpha[d] * V.v[d * n + i];
       V.r[d * n + i] = s;
-      V.shat[d * n + i] = dinv * s;
+      V.shat[2 * i + d] = dinv * s;
       ss[d] += s * s;
     }
   }
@@ -662,7 +690,7 @@ k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
 #pragma unroll
       for (int d = 0; d < 2; ++d)
-        if (half[d]) V.x[d * n + i] += alpha[d] * V.phat[d * n + i];
+        if (half[d]) V.x[d * n + i] += alpha[d] * V.phat[2 * i + d];
     }
   }
   if (!need_t) return;
@@ -673,7 +701,7 @@ k_bicg_b4(DLevel L, const double* __restrict__ A, BicgVecs V, Scal* sc, double* 
     const int row = r0 + threadIdx.x;
     if (row < r1) {
       double at[2];
-      tile_row<double, 2>(st, L, s0, row, [&](int d, int c) { return V.shat[d * n + c]; }, at);
+      tile_row2(st, L, s0, row, reinterpret_cast<const double2*>(V.shat), at);
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         V.t[d * n + row] = at[d];
@@ -707,7 +735,7 @@ k_bicg_b5(int32_t n32, BicgVecs V, Scal* sc, double* part, int nb, int my_stamp)
     for (int d = 0; d < 2; ++d) {
       if (!act[d]) continue;
       const int64_t k = d * n + i;
-      V.x[k] += alpha[d] * V.phat[k] + omega[d] * V.shat[k];
+      V.x[k] += alpha[d] * V.phat[2 * i + d] + omega[d] * V.shat[2 * i + d];
       const double r = V.r[k] - omega[d] * V.t[k];
       V.r[k] = r;
       rr[d] += r * r;
