@@ -29,7 +29,7 @@ using cgp::DLevel;
 using cgp::Scal;
 
 // The no-alloc scratch (see cgp_pcg_solve_noalloc): 7.5 MB per GPU.
-constexpr size_t kScratchDoubles = 128 + 8 * 2 * 1024 + 7 * 131072;
+constexpr size_t kScratchDoubles = 128 + 8 * 2 * 1280 + 7 * 131072;
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
@@ -943,7 +943,7 @@ int cgp_create(const cgp_problem* prob, cgp_ctx** out) {
   c->nb_f = std::min(cgp::kNbMax, std::max(1, (c->nf + cgp::kBlock - 1) / cgp::kBlock));
   // the coarse PCG product kernel requires every block to own a tile
   // one row per thread in the PCG iteration kernel; the tiled kernels loop
-  c->nb_c = std::min(cgp::kNbMax, std::max({1, c->h.gc.ntiles(),
+  c->nb_c = std::min(cgp::kNbCoarse, std::max({1, c->h.gc.ntiles(),
                                             (c->nc + cgp::kBlock - 1) / cgp::kBlock}));
   {  // mean coarse edge length (scale of the learned guess's edge features)
     const cgp::Graph& g = c->h.gc;

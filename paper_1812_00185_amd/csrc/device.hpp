@@ -11,7 +11,10 @@
 namespace cgp {
 
 constexpr int kBlock = 256;    // threads per block (4 wave64)
-constexpr int kNbMax = 1024;   // blocks per solver launch (partial-sum slots)
+constexpr int kNbMax = 1280;   // blocks per solver launch (partial-sum slots)
+// the fine BiCGSTAB launches up to kNbMax blocks: five per CU, as many as the
+// products' 30 KB LDS tiles allow; the coarse solvers up to kNbCoarse
+constexpr int kNbCoarse = 1024;
 constexpr int kEllPad = 8;     // ELL widths are multiples of this
 constexpr int kSlots = 8;      // reduction slots per right-hand side
 
