@@ -3,9 +3,10 @@
 // (forward) or a column range of G^T (backward), with the front vector of the
 // supernode in LDS.  G is column-major, so for a fixed column the 64 lanes of
 // a wave read 64 consecutive rows; the W waves of the group split the
-// reduction range.  A level's launch takes W from its longest reduction, so
-// that no wave walks more than about 16 terms (8 loads in flight each) and
-// the wide separators near the root are not a long chain of dependent loads.
+// reduction range.  A level's launch takes W (4, 8 or 16) from its longest
+// reduction, so that a wave walks at most 16 terms (8 loads in flight each)
+// for reductions of up to 256 terms and len / 16 beyond, and the wide
+// separators near the root are not a long chain of dependent loads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
