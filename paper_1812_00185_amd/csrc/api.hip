@@ -238,6 +238,7 @@ size_t carve(cgp_ctx* c, void* base) {
     d.vw = L.vw;
     d.vcol = w.take<int32_t>(L.vcol.size());
     d.vval = w.take<double>(L.vcol.size());
+    d.erec = L.erec.empty() ? nullptr : w.take<cgp::LatEdgeRec>(L.erec.size());
     c->vpos = w.take<int32_t>(L.vpos.size());
     c->node_of = w.take<int32_t>(L.node_of.size());
     c->corr_v4 = w.take<double>(4 * L.node_of.size());
@@ -1069,6 +1070,8 @@ int cgp_assemble(cgp_ctx* c, void* ws, size_t bytes, void* host, size_t host_byt
     HIPCHK(up((void*)d.ldir, L.ldir.data(), L.ldir.size()));
     HIPCHK(up((void*)d.lat_of, L.lat_of.data(), 4 * L.lat_of.size()));
     HIPCHK(up((void*)d.vcol, L.vcol.data(), 4 * L.vcol.size()));
+    if (d.erec)
+      HIPCHK(up((void*)d.erec, L.erec.data(), sizeof(cgp::LatEdgeRec) * L.erec.size()));
     HIPCHK(up((void*)c->vpos, L.vpos.data(), 4 * L.vpos.size()));
     HIPCHK(up((void*)c->node_of, L.node_of.data(), 4 * L.node_of.size()));
     HIPCHK(up((void*)c->mslot, L.mslot.data(), L.mslot.size()));

@@ -27,6 +27,7 @@ LatDev Lattice::host_view() const {
   d.lat_of = lat_of.data();
   d.vw = vw;
   d.vcol = vcol.data();
+  d.erec = erec.empty() ? nullptr : erec.data();
   return d;
 }
 
@@ -123,6 +124,15 @@ std::string build_lattice(const Hierarchy& h, Lattice& L) {
     }
     if (!diag) return "lattice: vertex row without its diagonal";
   }
+  // the coarse edges' records (from the tables above)
+  std::vector<LatEdgeRec> erec(L.nE);
+  const LatDev tv = L.host_view();
+  if (!lat_dispatch(m, [&](auto lat) {
+        constexpr int M = decltype(lat)::kM;
+        for (int32_t E = 0; E < L.nE; ++E) erec[E] = Lat<M>::edge_record(tv, E);
+      }))
+    return "lattice: unsupported lattice size";
+  L.erec = std::move(erec);
   return "";
 }
 

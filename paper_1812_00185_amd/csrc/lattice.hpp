@@ -34,6 +34,8 @@
 
 namespace cgp {
 
+struct LatEdgeRec;
+
 struct LatDev {
   int32_t m;      // 2^levels
   int32_t nI;     // interior nodes per coarse triangle, (m-1)(m-2)/2
@@ -52,7 +54,26 @@ struct LatDev {
   int32_t vw;
   const int32_t* vcol;    // lattice column indices
   const double* vval;     // values
+  const LatEdgeRec* erec; // [nE] per coarse edge (Lat<M>::edge_record), or nullptr
 };
+
+// Per coarse edge, what the rows of its inner nodes read besides their own
+// values, so that a row costs one record load instead of the edge's triangle
+// and table lookups: for each adjacent triangle q, the lattice indices of the
+// row of points one step inside it, parallel to the edge (pts[q][y], y = 0 ..
+// m - 1: point (y, 1), (m - 1 - y, y) or (1, y) of the triangle for the
+// edge as its local edge 0, 1 or 2; the node at t steps from the edge's lower
+// end neighbours points p and p - 1 of that row, p = t, or m - t when the
+// row runs the other way) and the triangle's fine area; the edge's two
+// vertices.
+constexpr int kLatMaxM = 8;
+struct LatEdgeRec {
+  int32_t pts[2][kLatMaxM];
+  double A[2];
+  int32_t v[2];     // lower, higher vertex (coarse numbering)
+  int32_t meta[2];  // bit 0: triangle q present; bit 1: p = m - t
+};
+static_assert(sizeof(LatEdgeRec) == 96, "edge record");
 
 // first lattice index of interior row a (1 <= a <= m-2) within a triangle
 CGP_HD constexpr int32_t lat_rowoff(int32_t m, int32_t a) {
@@ -216,6 +237,32 @@ struct Lat {
     a = j == 0 ? p : (j == 1 ? M - p : 0);
     b = j == 0 ? 0 : (j == 1 ? p : M - p);
   }
+
+  // the record of coarse edge E (set-up; see LatEdgeRec).  The point at
+  // steps s from v_j is (s, 0), (m - s, s) or (0, m - s) on local edge 0, 1
+  // or 2, and its two inner neighbours are points s and s - 1 (edges 0, 1) or
+  // m - s and m - s - 1 (edge 2) of the inner row.
+  static LatEdgeRec edge_record(const LatDev& L, int32_t E) {
+    static_assert(M <= kLatMaxM, "edge record size");
+    LatEdgeRec r{};
+    r.v[0] = L.edge_v[2 * E];
+    r.v[1] = L.edge_v[2 * E + 1];
+    for (int q = 0; q < 2; ++q) {
+      const int32_t tj = L.edge_t[2 * E + q];
+      if (tj < 0) continue;
+      const int32_t T = tj >> 2, j = tj & 3;
+      const LatTri tr = tri(L, T);
+      const bool rev = ((tr.te[j] & 1) != 0) != (j == 2);
+      r.meta[q] = 1 | (rev ? 2 : 0);
+      for (int32_t y = 0; y < M; ++y) {
+        const int32_t a = j == 0 ? y : (j == 1 ? M - 1 - y : 1);
+        const int32_t b = j == 0 ? 1 : y;
+        r.pts[q][y] = index(L, T, tr, a, b);
+      }
+      r.A[q] = L.af[T];
+    }
+    return r;
+  }
 };
 
 // (M x)_l for NR interleaved components (x(idx, d) reads component d of
@@ -243,12 +290,32 @@ CGP_HD inline void lat_apply(const LatDev& L, int32_t l, X x, double (&y)[NR], d
   if (l < L.VB) {
     int32_t E, t;
     G::edge(L, l, E, t);
-    const int32_t prev = t == 1 ? L.VB + L.edge_v[2 * E] : l - 1;
-    const int32_t next = t == M - 1 ? L.VB + L.edge_v[2 * E + 1] : l + 1;
     double acc[NR];
     double asum = 0.0;
 #pragma unroll
     for (int d = 0; d < NR; ++d) acc[d] = 0.0;
+    if (L.erec) {  // the same reads and operations, from the edge's record
+      const LatEdgeRec& R = L.erec[E];
+      const int32_t prev = t == 1 ? L.VB + R.v[0] : l - 1;
+      const int32_t next = t == M - 1 ? L.VB + R.v[1] : l + 1;
+      for (int q = 0; q < 2; ++q) {
+        const int32_t meta = R.meta[q];
+        if (!(meta & 1)) continue;
+        const int32_t p = (meta & 2) ? M - t : t;
+        const int32_t i1 = R.pts[q][p], i2 = R.pts[q][p - 1];
+        const double A = R.A[q];
+        asum += A;
+#pragma unroll
+        for (int d = 0; d < NR; ++d) acc[d] += (A / 6.0) * (x(i1, d) + x(i2, d));
+      }
+      diag = 0.5 * asum;
+#pragma unroll
+      for (int d = 0; d < NR; ++d)
+        y[d] = diag * x(l, d) + (asum / 12.0) * (x(prev, d) + x(next, d)) + acc[d];
+      return;
+    }
+    const int32_t prev = t == 1 ? L.VB + L.edge_v[2 * E] : l - 1;
+    const int32_t next = t == M - 1 ? L.VB + L.edge_v[2 * E + 1] : l + 1;
     for (int q = 0; q < 2; ++q) {
       const int32_t tj = L.edge_t[2 * E + q];
       if (tj < 0) continue;
@@ -354,6 +421,8 @@ struct Lattice {
   // node matched its CSR row exactly
   std::vector<uint8_t> mslot;
   bool mom_ok = false;
+  // per coarse edge, the record of its inner nodes' rows (LatEdgeRec)
+  std::vector<LatEdgeRec> erec;
   // view with host pointers (vval left empty)
   LatDev host_view() const;
 };
